@@ -1,0 +1,177 @@
+"""Benchmark of the PA Lagrange-phase hot path on one MI355X.
+
+One step = the whole hot path over the 48^3 Q2-Q1 Taylor-Green workload with
+inputs resident in HBM: one quadrature-data update, 50 x (F.1 + F^T.v), and
+one mass CG solve to a 1e-12 relative residual (v.n = 0 on the boundary).
+
+value = kinematic DOFs processed by force actions per second of the whole
+step, 3N x 100 / t_step / 1e9 (GDOF/s; the CG and qdata time count against
+it). The roofline object rates the dominant kernel (the force action with the
+larger total time) by algorithmic bytes per launch over its mean duration,
+measured with HIP events recorded by the library on its own stream.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2|c3|c4]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+CONFIGS = {
+    # name: (n, p, Q, label)
+    "c2": (48, 2, 4, "48^3 hex, H1 Q2 / L2 Q1, 4^3 Gauss points, Taylor-Green, seed 0"),
+    "c3": (24, 4, 6, "24^3 hex, H1 Q4 / L2 Q3, 6^3 Gauss points, Taylor-Green, seed 0"),
+    "c4": (64, 3, 5, "64^3 hex, H1 Q3 / L2 Q2, 5^3 Gauss points, Taylor-Green, seed 0, FP64 path"),
+}
+N_PAIRS = 50
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(E, N, p, Q):
+    """Bytes the PA action must move (stored S, unique-DOF vectors, map)."""
+    Q3, D3, Dl3 = Q ** 3, (p + 1) ** 3, p ** 3
+    S = 9 * Q3 * E * 8
+    return {
+        "force_1": S + 3 * N * 8 + D3 * E * 4,
+        "force_e": S + Dl3 * E * 8 + 3 * N * 8 + D3 * E * 4,
+        "force_T": S + 3 * N * 8 + Dl3 * E * 8 + D3 * E * 4,
+        "mass": Q3 * E * 8 + 2 * 3 * N * 8 + D3 * E * 4,
+        "qdata": 2 * 3 * N * 8 + Dl3 * E * 8 + Q3 * E * 8 + D3 * E * 4 + S,
+    }
+
+
+def cpu_baseline(mesh, v, e, p, Q, budget_s=12.0):
+    """The plain oracle (single thread) on a bounded element sample: qdata, F.1 and
+    F^T.v over the first k elements, scaled to GDOF/s of the full mesh."""
+    import oracle as O
+    E, N = mesh.n_elem, mesh.n_nodes
+    k = 256
+    while True:
+        el = np.arange(k, dtype=np.int32)
+        t0 = time.perf_counter()
+        S = O.qdata(mesh.elem_nodes, p, Q, N, mesh.x0, mesh.x0, v, e, elems=el, want=("S",))["S"]
+        t1 = time.perf_counter()
+        O.force_mult(mesh.elem_nodes, p, Q, N, S, None, elems=el)
+        O.force_mult_T(mesh.elem_nodes, p, Q, N, S, v, elems=el)
+        t2 = time.perf_counter()
+        if (t2 - t0) > budget_s / 4 or k * 2 > E:
+            break
+        k *= 2
+    frac = k / E
+    pair_s = (t2 - t1) / frac                 # one F.1 + F^T.v over the whole mesh
+    gdofs = 3 * N * 2 / pair_s / 1e9
+    return {"value": gdofs, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+            "sample": f"F.1 + F^T.v on the first {k} of {E} elements "
+                      f"({t2 - t1:.2f} s; qdata on them {t1 - t0:.2f} s, excluded), scaled by E/{k}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the PA path here runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not part of this build).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2112_07075_amd as fe
+    from paper_2112_07075_amd import workload as W
+
+    n, p, Q, label = CONFIGS[args.config]
+    mesh = W.cube_mesh(n, p, W.default_amp(p), seed=0)
+    v_np, e_np = W.taylor_green_fields(mesh)
+    E, N = mesh.n_elem, mesh.n_nodes
+    dev = torch.device("cuda:0")
+    x0 = torch.from_numpy(mesh.x0).to(dev)
+    v = torch.from_numpy(v_np).to(dev)
+    e = torch.from_numpy(e_np).to(dev)
+    ess = torch.from_numpy(W.boundary_normal_dofs(mesh)).to(dev)
+    ctx = fe.fe_pa_setup(fe.MeshDesc(mesh.elem_nodes, x0, p, Q), fe.Opts(flags=fe.FE_OPT_TIMERS))
+    y = torch.empty((3, N), dtype=torch.float64, device=dev)
+    z = torch.empty((E, p ** 3), dtype=torch.float64, device=dev)
+    a = torch.zeros((3, N), dtype=torch.float64, device=dev)
+    cg_info = {}
+
+    def step():
+        fe.fe_qdata_update(ctx, x0, v, e)
+        for _ in range(N_PAIRS):
+            fe.fe_force_mult(ctx, None, y)
+            fe.fe_force_mult_T(ctx, v, z)
+        # momentum equation M_v a = -F.1, a = 0 on v.n = 0 DOFs
+        torch.neg(y, out=y)
+        a.zero_()
+        rc, it, rr = fe.fe_mass_cg(ctx, y, a, ess, rel_tol=1e-12, max_iter=5000)
+        cg_info.update(iters=it, rel_res=rr)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    fe.fe_timer_reset(ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    step_s = (t1 - t0) / args.steps
+
+    timers = {}
+    for name, which in (("qdata", fe.FE_TIMER_QDATA), ("force_1", fe.FE_TIMER_FORCE),
+                        ("force_T", fe.FE_TIMER_FORCE_T), ("mass", fe.FE_TIMER_MASS)):
+        ms, cnt = fe.fe_timer_read(ctx, which)
+        timers[name] = (ms, cnt)
+    ab = algorithmic_bytes(E, N, p, Q)
+    per = {k: (ms / cnt if cnt else float("nan")) for k, (ms, cnt) in timers.items()}
+    dom = max(("force_1", "force_T"), key=lambda k: timers[k][0])
+    achieved = ab[dom] / (per[dom] * 1e-3) / 1e9
+    diag = fe.fe_get_diag(ctx)
+
+    out = {
+        "metric": "F.1 + F^T.v action GDOF/s (FP64) and % HBM roofline",
+        "value": 3 * N * 2 * N_PAIRS / step_s / 1e9,
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded perturbed unit cube, Taylor-Green fields)",
+        "config": {
+            "workload": f"{args.config.upper()}: {label}; step = qdata + {N_PAIRS} x (F.1 + F^T.v)"
+                        f" + mass CG to 1e-12",
+            "elements": E, "h1_dofs": 3 * N, "l2_dofs": E * p ** 3, "order": p, "q1d": Q,
+            "parallelism": "single GPU",
+        },
+        "kernels_us": {k: round(vv * 1e3, 2) for k, vv in per.items()},
+        "kernels_gbs": {k: round(ab[k] / (per[k] * 1e-3) / 1e9, 1) for k in per},
+        "force_pair_gdof_s": 3 * N * 2 / ((per["force_1"] + per["force_T"]) * 1e-3) / 1e9,
+        "cg": {"iters": cg_info.get("iters"), "true_rel_res": cg_info.get("rel_res"),
+               "mass_us": round(per["mass"] * 1e3, 2)},
+        "min_detj": diag["min_detj"],
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(mesh, v_np, e_np, p, Q)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

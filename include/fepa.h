@@ -1,0 +1,232 @@
+/*
+ * fepa.h -- C ABI of the MI355X partial-assembly (PA) operator library for
+ * high-order Lagrangian hydrodynamics on curved hexahedral meshes.
+ *
+ * The operators are those of the semi-discrete Lagrange system of the paper
+ * (Sec. 3.3, equations semiDiscreteLagStart..semiDiscreteLagEnd):
+ *
+ *     M_v dv/dt = -F 1,      M_E de/dt = F^T v,      dx/dt = v,
+ *     rho |J| = rho0 |J0|    (pointwise mass conservation),
+ *
+ * evaluated by partial assembly, A = P^T G^T B^T D B G P (Sec. 3.1), with the
+ * basis operator B applied by sum factorisation (Sec. 3.2, eq. local_action).
+ * Here G/G^T is the element restriction (gather through the element-to-node
+ * map) and its scatter-add; P is the identity on one GPU; D is the stored
+ * quadrature data (S for the force operator, m_q for the mass operator).
+ *
+ * Discretisation (the paper names the spaces, Sec. 2.1; the concrete choices
+ * below are this library's):
+ *   - reference element [0,1]^3;
+ *   - kinematic H1 space Q_p, p = 1..4: nodal Lagrange at the p+1 Gauss-Lobatto
+ *     points per axis (D = p+1);
+ *   - thermodynamic L2 space Q_{p-1}: nodal Lagrange at the p Gauss-Legendre
+ *     points per axis (Dl = p);
+ *   - quadrature: tensor Gauss-Legendre with Q = q1d points per axis,
+ *     p+1 <= Q <= p+3.
+ *   - force matrix F[(i,c), j] = int sigma : grad(w_i e_c) phi_j dx, with
+ *     sigma = -p I + mu eps(v) (ideal gas p = (gamma-1) rho e; scalar artificial
+ *     viscosity mu = rho l (q1 c_s + q2 l max(0, -tr eps)), l = detJ^(1/3)/p,
+ *     c_s = sqrt(gamma (gamma-1) max(e,0))), so the stored quadrature data is
+ *     S_q = w_q detJ_q sigma_q J_q^{-T} (3x3 per point).
+ *   - mass matrix M_v = block-diag over the 3 components of the scalar
+ *     (M)_{ij} = sum_q m_q w_i(q) w_j(q), m_q = rho0 detJ0_q w_q (Sec. 3.2).
+ *
+ * Layouts (all device arrays contiguous, FP64 unless stated):
+ *   - H1 vectors (x, v, forces): SoA by component, [3][N_tot]; entry (c, g)
+ *     at c*N_tot + g, where g = node_offset[m] + local node id of mesh m.
+ *   - L2 vectors (e, F^T v): [E_tot][Dl^3] with the mesh blocks concatenated
+ *     (element offset elem_offset[m]); local j = jx + Dl*(jy + Dl*jz).
+ *   - element-to-node map (host, given at setup): int32 [E][D^3], local
+ *     i = ix + D*(iy + D*iz) (x fastest), values in [0, N) of that mesh.
+ *   - exported quadrature data: S [E_tot][3][3][Q^3] (row c, column d,
+ *     q = qx + Q*(qy + Q*qz)), m_q [E_tot][Q^3].
+ *
+ * Conventions:
+ *   - Ownership: the caller owns every vector argument; the context owns maps,
+ *     basis tables, S, m_q and all solver workspace, allocated once in
+ *     fe_pa_setup. No other call allocates device memory.
+ *   - Streams: all device work of a context is enqueued on the HIP stream given
+ *     at setup. Calls are asynchronous except fe_pa_setup, fe_mass_cg,
+ *     fe_get_diag, fe_export_qdata and fe_timer_read, which synchronise that
+ *     stream.
+ *   - Aliasing: inputs and outputs must not overlap (FE_EINVAL when an exact
+ *     alias is seen).
+ *   - Errors: functions return FE_OK (0) or a negative FE_E* code and never
+ *     throw; fe_status_str() names a code and fe_last_error() gives the
+ *     context's last detailed message. A context is not thread safe; distinct
+ *     contexts are independent.
+ */
+#ifndef FEPA_H
+#define FEPA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define FE_OK            0
+#define FE_EINVAL       -1  /* bad argument: NULL pointer, size, alias, range  */
+#define FE_ENOMEM       -2  /* device or host allocation failed during setup   */
+#define FE_EDEVICE      -3  /* a HIP runtime call failed                        */
+#define FE_EUNSUPPORTED -4  /* (p, Q) or precision not provided by this build   */
+#define FE_EBADMESH     -5  /* non-positive Jacobian determinant at setup       */
+#define FE_ENOTCONV     -6  /* CG reached max_iter before the tolerance         */
+
+/* ------------------------------------------------------------ precisions */
+#define FE_PREC_FP64 0  /* every contraction and stored value in FP64          */
+#define FE_PREC_FP32 1  /* S, m_q stored FP32; contractions FP32 (precision form) */
+#define FE_PREC_BF16 2  /* contractions BF16 x BF16 -> FP32 on MFMA (precision form) */
+
+/* ------------------------------------------------------------ option flags */
+#define FE_OPT_TIMERS   0x1  /* record HIP events around the main kernels     */
+#define FE_OPT_BATCHED  0x2  /* multi-mesh: one persistent launch per action  */
+#define FE_OPT_GRAPH    0x4  /* CG iterations replayed from a captured graph  */
+
+/* kernels timed under FE_OPT_TIMERS */
+#define FE_TIMER_QDATA   0
+#define FE_TIMER_FORCE   1
+#define FE_TIMER_FORCE_T 2
+#define FE_TIMER_MASS    3
+#define FE_TIMER_COUNT   4
+
+typedef struct fe_ctx fe_ctx_t;
+
+/* One mesh. elem_nodes is HOST memory, read during fe_pa_setup only.
+ * x0 is DEVICE memory [3][n_nodes]: initial node positions, read during
+ * fe_pa_setup only (to form m_q = rho0 detJ0 w). */
+typedef struct fe_mesh_desc {
+    int32_t n_elem;            /* E >= 1                                    */
+    int32_t order;             /* p, 1..4                                   */
+    int32_t q1d;               /* Q, order+1 .. order+3                     */
+    int32_t n_nodes;           /* N >= 1 scalar H1 nodes                    */
+    const int32_t *elem_nodes; /* host [E][(p+1)^3], entries in [0, N)      */
+    const double *x0;          /* device [3][N]                             */
+    double rho0;               /* initial density (> 0), uniform            */
+} fe_mesh_desc_t;
+
+typedef struct fe_opts {
+    int32_t precision;         /* FE_PREC_*                                 */
+    int32_t flags;             /* FE_OPT_* bit set                          */
+    double gamma;              /* ideal-gas ratio of specific heats (> 1)   */
+    double q1, q2;             /* linear / quadratic viscosity coefficients */
+} fe_opts_t;
+
+typedef struct fe_info {
+    int32_t n_mesh;
+    int64_t n_elem_total;      /* E_tot                                     */
+    int64_t n_nodes_total;     /* N_tot (scalar); H1 vectors hold 3*N_tot    */
+    int64_t l2_size_total;     /* sum over meshes of E*p^3                  */
+    int64_t qdata_bytes;       /* device bytes of S and m_q                 */
+    int64_t workspace_bytes;   /* all other context-owned device bytes      */
+    int32_t precision;
+    int32_t flags;
+} fe_info_t;
+
+typedef struct fe_diag {
+    double min_detj;           /* min detJ seen by the last fe_qdata_update */
+    int32_t nonfinite;         /* 1 if the last qdata produced a NaN/Inf    */
+    int32_t cg_iters;          /* iterations of the last fe_mass_cg         */
+    double cg_rel_res;         /* its final true relative residual          */
+} fe_diag_t;
+
+/*
+ * Build a context: validate the meshes, build the 1-D basis tables, upload the
+ * maps, allocate S, m_q and the solver workspace, and compute m_q from x0
+ * (Sec. 3.3's rho |J| = rho0 |J0|). n_mesh > 1 selects a multi-mesh context
+ * whose vectors concatenate the meshes in order (offsets via fe_mesh_offsets).
+ * hip_stream: a hipStream_t (NULL = the null stream).
+ * Returns FE_EINVAL (bad sizes, NULL pointers, map out of range),
+ * FE_EUNSUPPORTED ((p, Q) or precision not built), FE_EBADMESH (detJ0 <= 0
+ * somewhere; the context is not created), FE_ENOMEM, FE_EDEVICE.
+ * On success *out owns all resources until fe_destroy.
+ */
+int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *opts,
+                void *hip_stream, fe_ctx_t **out);
+
+/* Release a context and all device memory it owns (synchronises its stream). NULL is ignored. */
+void fe_destroy(fe_ctx_t *ctx);
+
+/* Sizes and byte counts of a context (host only, no device work). */
+int fe_query(const fe_ctx_t *ctx, fe_info_t *info);
+
+/* Per-mesh offsets: node_offset[m], elem_offset[m], l2_offset[m] (host arrays of n_mesh int64; any may be NULL). */
+int fe_mesh_offsets(const fe_ctx_t *ctx, int64_t *node_offset, int64_t *elem_offset,
+                    int64_t *l2_offset);
+
+/*
+ * Quadrature-data update (the qdata step of the Lagrange phase): from the
+ * current positions x, velocities v ([3][N_tot], device) and specific internal
+ * energy e ([E_tot][Dl^3], device), compute J, detJ, J^{-1}, rho = m_q/(w detJ),
+ * e_q, the ideal-gas pressure, the viscosity and S_q = w detJ sigma J^{-T}
+ * into the context. Also records min detJ and a non-finite flag (fe_get_diag).
+ * Asynchronous. FE_EINVAL on NULL pointers.
+ */
+int fe_qdata_update(fe_ctx_t *ctx, const double *x, const double *v, const double *e);
+
+/*
+ * Force action y = F e ([3][N_tot], device, overwritten). e is [E_tot][Dl^3]
+ * on the device, or NULL for e = 1 (the right side -F 1 of the momentum
+ * equation, Sec. 3.3). Uses the S of the last fe_qdata_update. Asynchronous.
+ */
+int fe_force_mult(fe_ctx_t *ctx, const double *e, double *y);
+
+/*
+ * Transpose force action z = F^T v ([E_tot][Dl^3], device, overwritten) from
+ * v ([3][N_tot], device): the right side of the energy equation (Sec. 3.3).
+ * Element-local output, no scatter. Asynchronous.
+ */
+int fe_force_mult_T(fe_ctx_t *ctx, const double *v, double *z);
+
+/* Mass action y = M_v x ([3][N_tot] device in and out; y overwritten). Asynchronous. */
+int fe_mass_mult(fe_ctx_t *ctx, const double *x, double *y);
+
+/*
+ * Solve M_v x = b by unpreconditioned conjugate gradients on the free DOFs,
+ * with x = 0 on the essential DOFs ess_dofs (device int32 indices into
+ * [3][N_tot], sorted or not, no duplicates; NULL/n_ess = 0 for none).
+ * x (device [3][N_tot]) holds the initial guess on entry and the solution on
+ * exit; b (device) is not modified. Stops when ||r|| <= rel_tol ||b_free||
+ * (recursive residual), then reports the true relative residual
+ * ||b_free - (M x)_free|| / ||b_free|| in *rel_res and the iteration count in
+ * *iters (either pointer may be NULL). Under FE_PREC_FP32/BF16 the solve is
+ * iterative refinement: FP64 outer residuals with an inner low-precision CG.
+ * Synchronises the stream. Returns FE_ENOTCONV when max_iter iterations did
+ * not reach rel_tol (x then holds the last iterate).
+ */
+int fe_mass_cg(fe_ctx_t *ctx, const double *b, double *x, const int32_t *ess_dofs,
+               int32_t n_ess, double rel_tol, int32_t max_iter, int32_t *iters,
+               double *rel_res);
+
+/* Diagnostics of the last qdata update and CG solve. Synchronises the stream. */
+int fe_get_diag(fe_ctx_t *ctx, fe_diag_t *diag);
+
+/*
+ * Copy the stored quadrature data to caller device buffers S_out
+ * ([E_tot][3][3][Q^3], FP64) and mq_out ([E_tot][Q^3], FP64); either may be
+ * NULL. Only for single-(p,Q) contexts (all meshes share Q); FE_EINVAL
+ * otherwise. FP32-stored data is widened. Synchronises the stream.
+ */
+int fe_export_qdata(fe_ctx_t *ctx, double *S_out, double *mq_out);
+
+/*
+ * Per-kernel timers (FE_OPT_TIMERS): total milliseconds and launch count of
+ * kernel class `which` (FE_TIMER_*) since setup or the last reset, measured
+ * with HIP events recorded on the context stream around each launch.
+ * Synchronises the stream. FE_EINVAL when timers are off.
+ */
+int fe_timer_read(fe_ctx_t *ctx, int32_t which, double *total_ms, int64_t *count);
+int fe_timer_reset(fe_ctx_t *ctx);
+
+/* Static name of a status code. */
+const char *fe_status_str(int status);
+
+/* Last detailed error message of a context ("" if none); NULL ctx gives the message of the last failed setup. */
+const char *fe_last_error(const fe_ctx_t *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEPA_H */

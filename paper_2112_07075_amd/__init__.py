@@ -1,0 +1,248 @@
+"""Python binding of libfepa (MI355X partial-assembly Lagrange-phase operators).
+
+Argument marshalling only: every function forwards torch device pointers and
+the current HIP stream to the C ABI of the same name (include/fepa.h). All
+arithmetic runs in the library's HIP kernels; there is no fallback path. If
+libfepa.so has not been built, every call raises FepaError.
+
+Tensors: H1 vectors are float64 [3][N_tot] (or flat 3*N_tot), L2 vectors are
+float64 [E_tot][p^3], all contiguous on the GPU. Meshes are described by
+MeshDesc (host int32 element-to-node map, device float64 x0 [3][N]).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfepa.so")
+
+FE_OK, FE_EINVAL, FE_ENOMEM, FE_EDEVICE, FE_EUNSUPPORTED, FE_EBADMESH, FE_ENOTCONV = \
+    0, -1, -2, -3, -4, -5, -6
+FE_PREC_FP64, FE_PREC_FP32, FE_PREC_BF16 = 0, 1, 2
+FE_OPT_TIMERS, FE_OPT_BATCHED, FE_OPT_GRAPH = 0x1, 0x2, 0x4
+FE_TIMER_QDATA, FE_TIMER_FORCE, FE_TIMER_FORCE_T, FE_TIMER_MASS = 0, 1, 2, 3
+
+ABI_FUNCTIONS = ("fe_pa_setup", "fe_destroy", "fe_query", "fe_mesh_offsets", "fe_qdata_update",
+                 "fe_force_mult", "fe_force_mult_T", "fe_mass_mult", "fe_mass_cg",
+                 "fe_get_diag", "fe_export_qdata", "fe_timer_read", "fe_timer_reset",
+                 "fe_status_str", "fe_last_error")
+
+
+class FepaError(RuntimeError):
+    def __init__(self, status: int, msg: str = ""):
+        super().__init__(f"{status}: {msg}")
+        self.status = status
+
+
+class _MeshDesc(C.Structure):
+    _fields_ = [("n_elem", C.c_int32), ("order", C.c_int32), ("q1d", C.c_int32),
+                ("n_nodes", C.c_int32), ("elem_nodes", C.c_void_p), ("x0", C.c_void_p),
+                ("rho0", C.c_double)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("flags", C.c_int32), ("gamma", C.c_double),
+                ("q1", C.c_double), ("q2", C.c_double)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("n_mesh", C.c_int32), ("n_elem_total", C.c_int64), ("n_nodes_total", C.c_int64),
+                ("l2_size_total", C.c_int64), ("qdata_bytes", C.c_int64),
+                ("workspace_bytes", C.c_int64), ("precision", C.c_int32), ("flags", C.c_int32)]
+
+
+class _Diag(C.Structure):
+    _fields_ = [("min_detj", C.c_double), ("nonfinite", C.c_int32), ("cg_iters", C.c_int32),
+                ("cg_rel_res", C.c_double)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libfepa.so (raises FepaError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FepaError(FE_EDEVICE, f"{LIB_PATH} is missing: build it with "
+                                    "`python -m paper_2112_07075_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.fe_pa_setup.argtypes = [C.POINTER(_MeshDesc), i32, C.POINTER(_Opts), vp, C.POINTER(vp)]
+    L.fe_destroy.argtypes = [vp]
+    L.fe_destroy.restype = None
+    L.fe_query.argtypes = [vp, C.POINTER(_Info)]
+    L.fe_mesh_offsets.argtypes = [vp, vp, vp, vp]
+    L.fe_qdata_update.argtypes = [vp, vp, vp, vp]
+    L.fe_force_mult.argtypes = [vp, vp, vp]
+    L.fe_force_mult_T.argtypes = [vp, vp, vp]
+    L.fe_mass_mult.argtypes = [vp, vp, vp]
+    L.fe_mass_cg.argtypes = [vp, vp, vp, vp, i32, dbl, i32, C.POINTER(i32), C.POINTER(dbl)]
+    L.fe_get_diag.argtypes = [vp, C.POINTER(_Diag)]
+    L.fe_export_qdata.argtypes = [vp, vp, vp]
+    L.fe_timer_read.argtypes = [vp, i32, C.POINTER(dbl), C.POINTER(i64)]
+    L.fe_timer_reset.argtypes = [vp]
+    L.fe_status_str.argtypes = [C.c_int]
+    L.fe_status_str.restype = C.c_char_p
+    L.fe_last_error.argtypes = [vp]
+    L.fe_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc: int, ctx=None) -> int:
+    if rc != FE_OK:
+        L = lib()
+        detail = L.fe_last_error(ctx).decode()
+        raise FepaError(rc, f"{L.fe_status_str(rc).decode()}: {detail}")
+    return rc
+
+
+def _ptr(t):
+    """Device pointer of a contiguous CUDA/HIP tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise FepaError(FE_EINVAL, "tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise FepaError(FE_EINVAL, "tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class MeshDesc:
+    """One mesh: host int32 map [E][(p+1)^3] (numpy), device float64 x0 [3][N] (torch)."""
+    elem_nodes: object
+    x0: object
+    order: int
+    q1d: int
+    rho0: float = 1.0
+
+
+@dataclass
+class Opts:
+    precision: int = FE_PREC_FP64
+    flags: int = 0
+    gamma: float = 5.0 / 3.0
+    q1: float = 0.5
+    q2: float = 2.0
+
+
+class Ctx:
+    """Owns an fe_ctx_t handle (destroyed with the object)."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.fe_destroy(self.handle)
+            self.handle = None
+
+    @property
+    def _as_parameter_(self):
+        return self.handle
+
+
+# ------------------------------------------------------------------ the ABI
+def fe_pa_setup(meshes, opts: Opts | None = None, stream=None) -> Ctx:
+    import numpy as np
+    L = lib()
+    if isinstance(meshes, MeshDesc):
+        meshes = [meshes]
+    descs = (_MeshDesc * len(meshes))()
+    keep = []
+    for k, m in enumerate(meshes):
+        en = np.ascontiguousarray(m.elem_nodes, dtype=np.int32)
+        keep.append(en)
+        E = en.shape[0]
+        descs[k] = _MeshDesc(E, m.order, m.q1d, m.x0.shape[-1], en.ctypes.data,
+                             _ptr(m.x0).value, float(m.rho0))
+    o = opts or Opts()
+    co = _Opts(o.precision, o.flags, o.gamma, o.q1, o.q2)
+    h = C.c_void_p()
+    _check(L.fe_pa_setup(descs, len(meshes), C.byref(co), _stream(stream), C.byref(h)))
+    return Ctx(h, keep)
+
+
+def fe_destroy(ctx: Ctx) -> None:
+    if ctx.handle:
+        lib().fe_destroy(ctx.handle)
+        ctx.handle = None
+
+
+def fe_query(ctx: Ctx) -> dict:
+    info = _Info()
+    _check(lib().fe_query(ctx.handle, C.byref(info)), ctx.handle)
+    return {f: getattr(info, f) for f, _ in _Info._fields_}
+
+
+def fe_mesh_offsets(ctx: Ctx):
+    import numpy as np
+    n = fe_query(ctx)["n_mesh"]
+    a, b, c = (np.zeros(n, dtype=np.int64) for _ in range(3))
+    _check(lib().fe_mesh_offsets(ctx.handle, a.ctypes.data, b.ctypes.data, c.ctypes.data),
+           ctx.handle)
+    return a, b, c
+
+
+def fe_qdata_update(ctx: Ctx, x, v, e) -> None:
+    _check(lib().fe_qdata_update(ctx.handle, _ptr(x), _ptr(v), _ptr(e)), ctx.handle)
+
+
+def fe_force_mult(ctx: Ctx, e, y) -> None:
+    _check(lib().fe_force_mult(ctx.handle, _ptr(e), _ptr(y)), ctx.handle)
+
+
+def fe_force_mult_T(ctx: Ctx, v, z) -> None:
+    _check(lib().fe_force_mult_T(ctx.handle, _ptr(v), _ptr(z)), ctx.handle)
+
+
+def fe_mass_mult(ctx: Ctx, x, y) -> None:
+    _check(lib().fe_mass_mult(ctx.handle, _ptr(x), _ptr(y)), ctx.handle)
+
+
+def fe_mass_cg(ctx: Ctx, b, x, ess_dofs=None, rel_tol=1e-12, max_iter=1000, check=True):
+    """Returns (status, iterations, true relative residual); raises unless status is OK
+    (or ENOTCONV with check=False)."""
+    it, rr = C.c_int32(0), C.c_double(0.0)
+    n_ess = 0 if ess_dofs is None else int(ess_dofs.numel())
+    rc = lib().fe_mass_cg(ctx.handle, _ptr(b), _ptr(x), _ptr(ess_dofs), n_ess, float(rel_tol),
+                          int(max_iter), C.byref(it), C.byref(rr))
+    if check or rc not in (FE_OK, FE_ENOTCONV):
+        _check(rc, ctx.handle)
+    return rc, it.value, rr.value
+
+
+def fe_get_diag(ctx: Ctx) -> dict:
+    d = _Diag()
+    _check(lib().fe_get_diag(ctx.handle, C.byref(d)), ctx.handle)
+    return {f: getattr(d, f) for f, _ in _Diag._fields_}
+
+
+def fe_export_qdata(ctx: Ctx, S_out=None, mq_out=None) -> None:
+    _check(lib().fe_export_qdata(ctx.handle, _ptr(S_out), _ptr(mq_out)), ctx.handle)
+
+
+def fe_timer_read(ctx: Ctx, which: int):
+    ms, cnt = C.c_double(0.0), C.c_int64(0)
+    _check(lib().fe_timer_read(ctx.handle, which, C.byref(ms), C.byref(cnt)), ctx.handle)
+    return ms.value, cnt.value
+
+
+def fe_timer_reset(ctx: Ctx) -> None:
+    _check(lib().fe_timer_reset(ctx.handle), ctx.handle)
+
+
+def fe_status_str(status: int) -> str:
+    return lib().fe_status_str(status).decode()

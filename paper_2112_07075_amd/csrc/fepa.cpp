@@ -1,0 +1,580 @@
+// Host side of the C ABI declared in include/fepa.h: context set-up and
+// validation, device memory ownership (everything allocated once at set-up),
+// dispatch of the (p, Q) kernel instances per mesh, the CG driver and the
+// per-kernel event timers.
+#include "fepa.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "basis.hpp"
+#include "kern_cg.hpp"
+#include "kern_fp64.hpp"
+
+using namespace fepa;
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+struct MeshRec {
+    int E = 0, p = 0, Q = 0, N = 0;
+    long long node_off = 0, elem_off = 0, l2_off = 0, S_off = 0, mq_off = 0;
+    long long map_off = 0;   // into the concatenated map (int32 entries)
+    long long part_off = 0;  // into the CG partial-sum array
+    int tab_slot = 0;        // into the table buffer (doubles)
+    const KernelSet *ks = nullptr;
+    double rho0 = 1.0;
+};
+
+struct TimerPool {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t used = 0;
+    double folded_ms = 0.0;
+    long long count = 0;
+};
+
+constexpr size_t kTimerPairs = 4096;
+
+}  // namespace
+
+struct fe_ctx {
+    std::vector<MeshRec> mesh;
+    fe_opts_t opts{};
+    hipStream_t st = nullptr;
+    int device = 0;
+    long long E_tot = 0, N_tot = 0, L2_tot = 0, S_len = 0, mq_len = 0;
+    bool uniform_pq = true;
+    // device memory owned by the context
+    double *S = nullptr, *mq = nullptr, *tabs = nullptr;
+    int32_t *maps = nullptr;
+    long long *min_key = nullptr;
+    int *nonfinite = nullptr;
+    double *r = nullptr, *p = nullptr, *Ap = nullptr;
+    double *part = nullptr, *part2 = nullptr, *scal = nullptr;
+    unsigned char *fr = nullptr;
+    CgState *cg = nullptr;
+    int *bad = nullptr;
+    long long n_parts = 0;
+    // pinned host staging
+    CgState *h_cg = nullptr;
+    double *h_scal = nullptr;
+    long long *h_key = nullptr;
+    int *h_flag = nullptr;
+    // bookkeeping
+    long long qdata_bytes = 0, work_bytes = 0;
+    int last_iters = 0;
+    double last_res = 0.0;
+    std::string err;
+    TimerPool timers[FE_TIMER_COUNT];
+};
+
+namespace {
+
+int fail(fe_ctx *c, int code, const char *fmt, const char *detail = nullptr)
+{
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), fmt, detail ? detail : "");
+    if (c)
+        c->err = buf;
+    else
+        g_setup_error = buf;
+    return code;
+}
+
+#define HIP_OK(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess) return fail(ctx, FE_EDEVICE, "%s", hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+int dev_alloc(fe_ctx *ctx, T **ptr, long long count, long long *acc)
+{
+    const size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
+    if (hipMalloc((void **)ptr, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *ptr = nullptr;
+        return fail(ctx, FE_ENOMEM, "device allocation failed%s");
+    }
+    if (acc) *acc += (long long)bytes;
+    return FE_OK;
+}
+
+void free_all(fe_ctx *c)
+{
+    if (!c) return;
+    if (c->st) (void)hipStreamSynchronize(c->st);
+    void *dptrs[] = {c->S, c->mq, c->tabs, c->maps, c->min_key, c->nonfinite, c->r, c->p,
+                     c->Ap, c->part, c->part2, c->scal, c->fr, c->cg, c->bad};
+    for (void *d : dptrs)
+        if (d) (void)hipFree(d);
+    void *hptrs[] = {c->h_cg, c->h_scal, c->h_key, c->h_flag};
+    for (void *h : hptrs)
+        if (h) (void)hipHostFree(h);
+    for (auto &tp : c->timers)
+        for (auto &pr : tp.ev) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+}
+
+double key_to_double(long long k)
+{
+    long long b = k >= 0 ? k : (k ^ 0x7fffffffffffffffLL);
+    double d;
+    std::memcpy(&d, &b, sizeof(d));
+    return d;
+}
+
+// ---- timers
+struct ScopedTimer {
+    fe_ctx *c;
+    TimerPool *tp = nullptr;
+    ScopedTimer(fe_ctx *ctx, int which) : c(ctx)
+    {
+        if (!(c->opts.flags & FE_OPT_TIMERS)) return;
+        tp = &c->timers[which];
+        if (tp->used == tp->ev.size()) {
+            // pool exhausted: fold what was recorded so far
+            (void)hipStreamSynchronize(c->st);
+            for (auto &pr : tp->ev) {
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, pr.first, pr.second);
+                tp->folded_ms += ms;
+            }
+            tp->used = 0;
+        }
+        (void)hipEventRecord(tp->ev[tp->used].first, c->st);
+    }
+    ~ScopedTimer()
+    {
+        if (!tp) return;
+        (void)hipEventRecord(tp->ev[tp->used].second, c->st);
+        tp->used++;
+        tp->count++;
+    }
+};
+
+bool supported_pq(int p, int Q) { return fp64_kernels(p, Q) != nullptr; }
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+const char *fe_status_str(int s)
+{
+    switch (s) {
+    case FE_OK: return "ok";
+    case FE_EINVAL: return "invalid argument";
+    case FE_ENOMEM: return "out of memory";
+    case FE_EDEVICE: return "HIP runtime error";
+    case FE_EUNSUPPORTED: return "unsupported order/quadrature/precision";
+    case FE_EBADMESH: return "non-positive Jacobian determinant";
+    case FE_ENOTCONV: return "CG did not converge";
+    default: return "unknown status";
+    }
+}
+
+const char *fe_last_error(const fe_ctx_t *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_setup_error.c_str();
+}
+
+int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *opts,
+                void *hip_stream, fe_ctx_t **out)
+{
+    fe_ctx *ctx = nullptr;
+    g_setup_error.clear();
+    if (!out) return fail(nullptr, FE_EINVAL, "out is NULL%s");
+    *out = nullptr;
+    if (!meshes || n_mesh < 1) return fail(nullptr, FE_EINVAL, "need at least one mesh%s");
+    fe_opts_t o{};
+    if (opts) {
+        o = *opts;
+    } else {
+        o.precision = FE_PREC_FP64;
+        o.gamma = 5.0 / 3.0;
+        o.q1 = 0.5;
+        o.q2 = 2.0;
+    }
+    if (!(o.gamma > 1.0) || !(o.q1 >= 0.0) || !(o.q2 >= 0.0))
+        return fail(nullptr, FE_EINVAL, "gamma must be > 1 and q1, q2 >= 0%s");
+    if (o.precision != FE_PREC_FP64)
+        return fail(nullptr, FE_EUNSUPPORTED, "precision not provided by this build%s");
+    if (o.flags & ~(FE_OPT_TIMERS | FE_OPT_BATCHED | FE_OPT_GRAPH))
+        return fail(nullptr, FE_EINVAL, "unknown option flags%s");
+    // host-side validation of every mesh before any device work
+    for (int m = 0; m < n_mesh; ++m) {
+        const fe_mesh_desc_t &d = meshes[m];
+        if (d.n_elem < 1 || d.n_nodes < 1 || d.order < 1 || d.order > 4)
+            return fail(nullptr, FE_EINVAL, "mesh sizes or order out of range%s");
+        if (d.q1d < d.order + 1 || d.q1d > d.order + 3)
+            return fail(nullptr, FE_EUNSUPPORTED, "q1d must be in [order+1, order+3]%s");
+        if (!supported_pq(d.order, d.q1d))
+            return fail(nullptr, FE_EUNSUPPORTED, "(order, q1d) not built%s");
+        if (!d.elem_nodes || !d.x0) return fail(nullptr, FE_EINVAL, "NULL mesh array%s");
+        if (!(d.rho0 > 0.0)) return fail(nullptr, FE_EINVAL, "rho0 must be > 0%s");
+        const long long D3 = (long long)(d.order + 1) * (d.order + 1) * (d.order + 1);
+        const long long cnt = D3 * d.n_elem;
+        for (long long k = 0; k < cnt; ++k)
+            if (d.elem_nodes[k] < 0 || d.elem_nodes[k] >= d.n_nodes)
+                return fail(nullptr, FE_EINVAL, "element-to-node map entry out of range%s");
+    }
+
+    ctx = new (std::nothrow) fe_ctx();
+    if (!ctx) return fail(nullptr, FE_ENOMEM, "host allocation failed%s");
+    ctx->opts = o;
+    ctx->st = (hipStream_t)hip_stream;
+    auto bail = [&](int code) {
+        g_setup_error = ctx->err;
+        free_all(ctx);
+        delete ctx;
+        return code;
+    };
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        ctx->err = "no HIP device";
+        return bail(FE_EDEVICE);
+    }
+
+    // layout of the concatenated vectors and context arrays
+    std::map<std::pair<int, int>, int> slot_of;
+    std::vector<double> tab_host;
+    long long map_len = 0;
+    for (int m = 0; m < n_mesh; ++m) {
+        const fe_mesh_desc_t &d = meshes[m];
+        MeshRec r;
+        r.E = d.n_elem;
+        r.p = d.order;
+        r.Q = d.q1d;
+        r.N = d.n_nodes;
+        r.rho0 = d.rho0;
+        r.ks = fp64_kernels(r.p, r.Q);
+        const long long Q3 = (long long)r.Q * r.Q * r.Q;
+        const long long D3 = (long long)(r.p + 1) * (r.p + 1) * (r.p + 1);
+        r.node_off = ctx->N_tot;
+        r.elem_off = ctx->E_tot;
+        r.l2_off = ctx->L2_tot;
+        r.S_off = ctx->S_len;
+        r.mq_off = ctx->mq_len;
+        r.map_off = map_len;
+        r.part_off = ctx->n_parts;
+        auto key = std::make_pair(r.p, r.Q);
+        if (!slot_of.count(key)) {
+            slot_of[key] = (int)tab_host.size();
+            std::vector<double> t = build_table(r.p, r.Q);
+            tab_host.insert(tab_host.end(), t.begin(), t.end());
+            while (tab_host.size() % 32) tab_host.push_back(0.0);  // 256-byte aligned slots
+        }
+        r.tab_slot = slot_of[key];
+        ctx->N_tot += r.N;
+        ctx->E_tot += r.E;
+        ctx->L2_tot += (long long)r.E * r.p * r.p * r.p;
+        ctx->S_len += 9 * Q3 * r.E;
+        ctx->mq_len += Q3 * r.E;
+        map_len += D3 * r.E;
+        ctx->n_parts += r.ks->mass_blocks(r.E);
+        if (m > 0 && (r.p != ctx->mesh[0].p || r.Q != ctx->mesh[0].Q)) ctx->uniform_pq = false;
+        ctx->mesh.push_back(r);
+    }
+    if (ctx->N_tot * 3 > (1LL << 31) - 1) {
+        ctx->err = "too many nodes for int32 DOF indices";
+        return bail(FE_EINVAL);
+    }
+
+    long long qb = 0, wb = 0;
+    int rc = FE_OK;
+    if ((rc = dev_alloc(ctx, &ctx->S, ctx->S_len, &qb)) || (rc = dev_alloc(ctx, &ctx->mq, ctx->mq_len, &qb)) ||
+        (rc = dev_alloc(ctx, &ctx->tabs, (long long)tab_host.size(), &wb)) ||
+        (rc = dev_alloc(ctx, &ctx->maps, map_len, &wb)) ||
+        (rc = dev_alloc(ctx, &ctx->min_key, 1, &wb)) || (rc = dev_alloc(ctx, &ctx->nonfinite, 1, &wb)) ||
+        (rc = dev_alloc(ctx, &ctx->r, 3 * ctx->N_tot, &wb)) || (rc = dev_alloc(ctx, &ctx->p, 3 * ctx->N_tot, &wb)) ||
+        (rc = dev_alloc(ctx, &ctx->Ap, 3 * ctx->N_tot, &wb)) ||
+        (rc = dev_alloc(ctx, &ctx->part, std::max<long long>(ctx->n_parts, kVecBlocks), &wb)) ||
+        (rc = dev_alloc(ctx, &ctx->part2, kVecBlocks, &wb)) || (rc = dev_alloc(ctx, &ctx->scal, 8, &wb)) ||
+        (rc = dev_alloc(ctx, &ctx->fr, 3 * ctx->N_tot, &wb)) || (rc = dev_alloc(ctx, &ctx->cg, 1, &wb)) ||
+        (rc = dev_alloc(ctx, &ctx->bad, 1, &wb)))
+        return bail(rc);
+    ctx->qdata_bytes = qb;
+    ctx->work_bytes = wb;
+    if (hipHostMalloc((void **)&ctx->h_cg, sizeof(CgState)) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->h_scal, 8 * sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->h_key, sizeof(long long)) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->h_flag, sizeof(int)) != hipSuccess) {
+        ctx->err = "pinned host allocation failed";
+        return bail(FE_ENOMEM);
+    }
+    if (o.flags & FE_OPT_TIMERS)
+        for (auto &tp : ctx->timers) {
+            tp.ev.resize(kTimerPairs);
+            for (auto &pr : tp.ev)
+                if (hipEventCreate(&pr.first) != hipSuccess || hipEventCreate(&pr.second) != hipSuccess) {
+                    ctx->err = "event creation failed";
+                    return bail(FE_EDEVICE);
+                }
+        }
+
+    // uploads: tables, maps with global node ids
+    std::vector<int32_t> map_host((size_t)map_len);
+    for (int m = 0; m < n_mesh; ++m) {
+        const MeshRec &r = ctx->mesh[m];
+        const long long D3 = (long long)(r.p + 1) * (r.p + 1) * (r.p + 1);
+        for (long long k = 0; k < D3 * r.E; ++k)
+            map_host[r.map_off + k] = (int32_t)(meshes[m].elem_nodes[k] + r.node_off);
+    }
+    if (hipMemcpyAsync(ctx->tabs, tab_host.data(), tab_host.size() * sizeof(double),
+                       hipMemcpyHostToDevice, ctx->st) != hipSuccess ||
+        hipMemcpyAsync(ctx->maps, map_host.data(), map_host.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice, ctx->st) != hipSuccess) {
+        ctx->err = "upload failed";
+        return bail(FE_EDEVICE);
+    }
+    // m_q = rho0 detJ0 w from x0 (qdata kernels in set-up mode)
+    launch_reset_diag(ctx->min_key, ctx->nonfinite, ctx->st);
+    for (int m = 0; m < n_mesh; ++m) {
+        const MeshRec &r = ctx->mesh[m];
+        QParams prm{r.rho0, o.gamma, o.gamma - 1.0, o.q1, o.q2, 1.0 / r.p};
+        r.ks->qdata(meshes[m].x0, nullptr, nullptr, ctx->maps + r.map_off, r.N, (int)r.node_off,
+                    ctx->mq + r.mq_off, nullptr, r.E, ctx->tabs + r.tab_slot, prm, ctx->min_key,
+                    ctx->nonfinite, true, ctx->st);
+    }
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(ctx->h_key, ctx->min_key, sizeof(long long), hipMemcpyDeviceToHost, ctx->st) != hipSuccess ||
+        hipMemcpyAsync(ctx->h_flag, ctx->nonfinite, sizeof(int), hipMemcpyDeviceToHost, ctx->st) != hipSuccess ||
+        hipStreamSynchronize(ctx->st) != hipSuccess) {
+        ctx->err = "set-up kernels failed";
+        return bail(FE_EDEVICE);
+    }
+    const double min0 = key_to_double(*ctx->h_key);
+    if (!(min0 > 0.0) || *ctx->h_flag) {
+        char buf[128];
+        std::snprintf(buf, sizeof(buf), "initial mesh has min detJ = %.3e", min0);
+        ctx->err = buf;
+        return bail(FE_EBADMESH);
+    }
+    *out = ctx;
+    return FE_OK;
+}
+
+void fe_destroy(fe_ctx_t *ctx)
+{
+    if (!ctx) return;
+    free_all(ctx);
+    delete ctx;
+}
+
+int fe_query(const fe_ctx_t *ctx, fe_info_t *info)
+{
+    if (!ctx || !info) return FE_EINVAL;
+    info->n_mesh = (int32_t)ctx->mesh.size();
+    info->n_elem_total = ctx->E_tot;
+    info->n_nodes_total = ctx->N_tot;
+    info->l2_size_total = ctx->L2_tot;
+    info->qdata_bytes = ctx->qdata_bytes;
+    info->workspace_bytes = ctx->work_bytes;
+    info->precision = ctx->opts.precision;
+    info->flags = ctx->opts.flags;
+    return FE_OK;
+}
+
+int fe_mesh_offsets(const fe_ctx_t *ctx, int64_t *node_offset, int64_t *elem_offset,
+                    int64_t *l2_offset)
+{
+    if (!ctx) return FE_EINVAL;
+    for (size_t m = 0; m < ctx->mesh.size(); ++m) {
+        if (node_offset) node_offset[m] = ctx->mesh[m].node_off;
+        if (elem_offset) elem_offset[m] = ctx->mesh[m].elem_off;
+        if (l2_offset) l2_offset[m] = ctx->mesh[m].l2_off;
+    }
+    return FE_OK;
+}
+
+int fe_qdata_update(fe_ctx_t *ctx, const double *x, const double *v, const double *e)
+{
+    if (!ctx) return FE_EINVAL;
+    if (!x || !v || !e) return fail(ctx, FE_EINVAL, "NULL input%s");
+    launch_reset_diag(ctx->min_key, ctx->nonfinite, ctx->st);
+    {
+        ScopedTimer tm(ctx, FE_TIMER_QDATA);
+        for (const MeshRec &r : ctx->mesh) {
+            QParams prm{r.rho0, ctx->opts.gamma, ctx->opts.gamma - 1.0, ctx->opts.q1, ctx->opts.q2,
+                        1.0 / r.p};
+            r.ks->qdata(x, v, e + r.l2_off, ctx->maps + r.map_off, ctx->N_tot, 0,
+                        ctx->mq + r.mq_off, ctx->S + r.S_off, r.E, ctx->tabs + r.tab_slot, prm,
+                        ctx->min_key, ctx->nonfinite, false, ctx->st);
+        }
+    }
+    HIP_OK(hipGetLastError());
+    return FE_OK;
+}
+
+int fe_force_mult(fe_ctx_t *ctx, const double *e, double *y)
+{
+    if (!ctx) return FE_EINVAL;
+    if (!y) return fail(ctx, FE_EINVAL, "NULL output%s");
+    if ((const void *)e == (const void *)y) return fail(ctx, FE_EINVAL, "input aliases output%s");
+    launch_fill(y, 3 * ctx->N_tot, 0.0, ctx->st);
+    {
+        ScopedTimer tm(ctx, FE_TIMER_FORCE);
+        for (const MeshRec &r : ctx->mesh)
+            r.ks->force(ctx->S + r.S_off, e ? e + r.l2_off : nullptr, ctx->maps + r.map_off, y, r.E,
+                        ctx->N_tot, ctx->tabs + r.tab_slot, ctx->st);
+    }
+    HIP_OK(hipGetLastError());
+    return FE_OK;
+}
+
+int fe_force_mult_T(fe_ctx_t *ctx, const double *v, double *z)
+{
+    if (!ctx) return FE_EINVAL;
+    if (!v || !z) return fail(ctx, FE_EINVAL, "NULL argument%s");
+    if ((const void *)v == (const void *)z) return fail(ctx, FE_EINVAL, "input aliases output%s");
+    {
+        ScopedTimer tm(ctx, FE_TIMER_FORCE_T);
+        for (const MeshRec &r : ctx->mesh)
+            r.ks->force_t(ctx->S + r.S_off, v, ctx->maps + r.map_off, z + r.l2_off, r.E, ctx->N_tot,
+                          ctx->tabs + r.tab_slot, ctx->st);
+    }
+    HIP_OK(hipGetLastError());
+    return FE_OK;
+}
+
+static void mass_launch(fe_ctx *ctx, const double *x, double *y, bool dot, const int *skip)
+{
+    for (const MeshRec &r : ctx->mesh)
+        r.ks->mass(ctx->mq + r.mq_off, x, ctx->maps + r.map_off, y, r.E, ctx->N_tot,
+                   ctx->tabs + r.tab_slot, dot ? ctx->part + r.part_off : nullptr, skip, ctx->st);
+}
+
+int fe_mass_mult(fe_ctx_t *ctx, const double *x, double *y)
+{
+    if (!ctx) return FE_EINVAL;
+    if (!x || !y) return fail(ctx, FE_EINVAL, "NULL argument%s");
+    if ((const void *)x == (const void *)y) return fail(ctx, FE_EINVAL, "input aliases output%s");
+    launch_fill(y, 3 * ctx->N_tot, 0.0, ctx->st);
+    {
+        ScopedTimer tm(ctx, FE_TIMER_MASS);
+        mass_launch(ctx, x, y, false, nullptr);
+    }
+    HIP_OK(hipGetLastError());
+    return FE_OK;
+}
+
+int fe_mass_cg(fe_ctx_t *ctx, const double *b, double *x, const int32_t *ess_dofs, int32_t n_ess,
+               double rel_tol, int32_t max_iter, int32_t *iters, double *rel_res)
+{
+    if (!ctx) return FE_EINVAL;
+    if (!b || !x) return fail(ctx, FE_EINVAL, "NULL argument%s");
+    if ((const void *)b == (const void *)x) return fail(ctx, FE_EINVAL, "b aliases x%s");
+    if (n_ess < 0 || (n_ess > 0 && !ess_dofs)) return fail(ctx, FE_EINVAL, "bad essential DOF list%s");
+    if (!(rel_tol >= 0.0) || max_iter < 0) return fail(ctx, FE_EINVAL, "bad tolerance or max_iter%s");
+    const long long n = 3 * ctx->N_tot;
+    launch_reset_diag(nullptr, ctx->bad, ctx->st);
+    cg_mask(ctx->fr, n, ess_dofs, n_ess, ctx->bad, ctx->st);
+    cg_mask_apply(x, ctx->fr, n, ctx->st);
+    launch_fill(ctx->Ap, n, 0.0, ctx->st);
+    mass_launch(ctx, x, ctx->Ap, false, nullptr);
+    cg_start(b, ctx->Ap, ctx->r, ctx->p, ctx->fr, n, ctx->part, ctx->part2, ctx->cg, rel_tol,
+             max_iter, ctx->st);
+    launch_fill(ctx->Ap, n, 0.0, ctx->st);
+    HIP_OK(hipGetLastError());
+    const int *skip = &ctx->cg->done;
+    int batch = 4;
+    for (;;) {
+        for (int k = 0; k < batch; ++k) {
+            {
+                ScopedTimer tm(ctx, FE_TIMER_MASS);
+                mass_launch(ctx, ctx->p, ctx->Ap, true, skip);
+            }
+            cg_alpha(ctx->part, (int)ctx->n_parts, ctx->cg, ctx->st);
+            cg_update(x, ctx->r, ctx->p, ctx->Ap, ctx->fr, n, ctx->cg, ctx->part2, ctx->st);
+            cg_beta(ctx->part2, ctx->cg, ctx->st);
+            cg_direction(ctx->p, ctx->r, ctx->Ap, n, ctx->cg, ctx->st);
+        }
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpyAsync(ctx->h_cg, ctx->cg, sizeof(CgState), hipMemcpyDeviceToHost, ctx->st));
+        HIP_OK(hipMemcpyAsync(ctx->h_flag, ctx->bad, sizeof(int), hipMemcpyDeviceToHost, ctx->st));
+        HIP_OK(hipStreamSynchronize(ctx->st));
+        if (*ctx->h_flag) return fail(ctx, FE_EINVAL, "essential DOF index out of range%s");
+        if (ctx->h_cg->done) break;
+        if (batch < 32) batch *= 2;
+    }
+    const CgState st = *ctx->h_cg;
+    // true residual of the free system
+    launch_fill(ctx->Ap, n, 0.0, ctx->st);
+    mass_launch(ctx, x, ctx->Ap, false, nullptr);
+    resid_norm2(b, ctx->Ap, ctx->fr, n, ctx->part2, ctx->scal, ctx->st);
+    HIP_OK(hipMemcpyAsync(ctx->h_scal, ctx->scal, sizeof(double), hipMemcpyDeviceToHost, ctx->st));
+    HIP_OK(hipStreamSynchronize(ctx->st));
+    const double res = std::sqrt(*ctx->h_scal / (st.bb > 0.0 ? st.bb : 1.0));
+    ctx->last_iters = st.iter;
+    ctx->last_res = res;
+    if (iters) *iters = st.iter;
+    if (rel_res) *rel_res = res;
+    if (st.done == 2) return fail(ctx, FE_ENOTCONV, "iteration limit reached%s");
+    return FE_OK;
+}
+
+int fe_get_diag(fe_ctx_t *ctx, fe_diag_t *diag)
+{
+    if (!ctx || !diag) return FE_EINVAL;
+    HIP_OK(hipMemcpyAsync(ctx->h_key, ctx->min_key, sizeof(long long), hipMemcpyDeviceToHost, ctx->st));
+    HIP_OK(hipMemcpyAsync(ctx->h_flag, ctx->nonfinite, sizeof(int), hipMemcpyDeviceToHost, ctx->st));
+    HIP_OK(hipStreamSynchronize(ctx->st));
+    diag->min_detj = key_to_double(*ctx->h_key);
+    diag->nonfinite = *ctx->h_flag;
+    diag->cg_iters = ctx->last_iters;
+    diag->cg_rel_res = ctx->last_res;
+    return FE_OK;
+}
+
+int fe_export_qdata(fe_ctx_t *ctx, double *S_out, double *mq_out)
+{
+    if (!ctx) return FE_EINVAL;
+    if (!ctx->uniform_pq) return fail(ctx, FE_EINVAL, "export needs one (order, q1d) for all meshes%s");
+    if (S_out)
+        HIP_OK(hipMemcpyAsync(S_out, ctx->S, sizeof(double) * ctx->S_len, hipMemcpyDeviceToDevice, ctx->st));
+    if (mq_out)
+        HIP_OK(hipMemcpyAsync(mq_out, ctx->mq, sizeof(double) * ctx->mq_len, hipMemcpyDeviceToDevice, ctx->st));
+    HIP_OK(hipStreamSynchronize(ctx->st));
+    return FE_OK;
+}
+
+int fe_timer_read(fe_ctx_t *ctx, int32_t which, double *total_ms, int64_t *count)
+{
+    if (!ctx || which < 0 || which >= FE_TIMER_COUNT) return FE_EINVAL;
+    if (!(ctx->opts.flags & FE_OPT_TIMERS)) return fail(ctx, FE_EINVAL, "timers are off%s");
+    HIP_OK(hipStreamSynchronize(ctx->st));
+    TimerPool &tp = ctx->timers[which];
+    double ms = tp.folded_ms;
+    for (size_t k = 0; k < tp.used; ++k) {
+        float t = 0.f;
+        HIP_OK(hipEventElapsedTime(&t, tp.ev[k].first, tp.ev[k].second));
+        ms += t;
+    }
+    if (total_ms) *total_ms = ms;
+    if (count) *count = tp.count;
+    return FE_OK;
+}
+
+int fe_timer_reset(fe_ctx_t *ctx)
+{
+    if (!ctx) return FE_EINVAL;
+    HIP_OK(hipStreamSynchronize(ctx->st));
+    for (auto &tp : ctx->timers) {
+        tp.used = 0;
+        tp.folded_ms = 0.0;
+        tp.count = 0;
+    }
+    return FE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,249 @@
+// Vector kernels of the mass conjugate-gradient solve (the CG inversion of the
+// kinematic mass matrix, paper Sec. 3.3 and Sec. 6): masked residual set-up,
+// fused axpy + dot, direction update, and deterministic two-level FP64
+// reductions (per-workgroup partials, then one workgroup). The iteration state
+// lives on the device; every kernel leaves at once when the solve is done, so
+// the host can enqueue batches of iterations and poll rarely.
+#include "kern_cg.hpp"
+
+namespace fepa {
+
+__device__ __forceinline__ double block_sum(double v, double *sred)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) sred[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)((blockDim.x + 63) >> 6); ++k) s += sred[k];
+    __syncthreads();
+    return s;  // valid in thread 0
+}
+
+__global__ void k_mask_build(unsigned char *__restrict__ fr, long long n)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        fr[i] = 1;
+}
+
+__global__ void k_mask_ess(unsigned char *__restrict__ fr, long long n,
+                           const int32_t *__restrict__ ess, int n_ess, int *__restrict__ bad)
+{
+    const int stride = gridDim.x * blockDim.x;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n_ess; k += stride) {
+        const long long i = ess[k];
+        if (i >= 0 && i < n)
+            fr[i] = 0;
+        else
+            atomicOr(bad, 1);
+    }
+}
+
+// x_ess = 0
+__global__ void k_mask_apply(double *__restrict__ x, const unsigned char *__restrict__ fr,
+                             long long n)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        if (!fr[i]) x[i] = 0.0;
+}
+
+// r = (b - Ax) on free DOFs (0 elsewhere); p = r; partials of r.r and b_free.b_free
+__global__ void k_cg_start(const double *__restrict__ b, const double *__restrict__ Ax,
+                           double *__restrict__ r, double *__restrict__ p,
+                           const unsigned char *__restrict__ fr, long long n,
+                           double *__restrict__ part_rr, double *__restrict__ part_bb)
+{
+    __shared__ double sred[16];
+    double rr = 0.0, bb = 0.0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double bi = fr[i] ? b[i] : 0.0;
+        const double ri = fr[i] ? bi - Ax[i] : 0.0;
+        r[i] = ri;
+        p[i] = ri;
+        rr += ri * ri;
+        bb += bi * bi;
+    }
+    rr = block_sum(rr, sred);
+    bb = block_sum(bb, sred);
+    if (threadIdx.x == 0) {
+        part_rr[blockIdx.x] = rr;
+        part_bb[blockIdx.x] = bb;
+    }
+}
+
+// one workgroup: finish the start-up sums and decide whether any iteration is needed
+__global__ void k_cg_start_final(const double *__restrict__ part_rr,
+                                 const double *__restrict__ part_bb, int nparts,
+                                 CgState *__restrict__ st, double rel_tol, int max_iter)
+{
+    __shared__ double sred[16];
+    double rr = 0.0, bb = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += blockDim.x) {
+        rr += part_rr[k];
+        bb += part_bb[k];
+    }
+    rr = block_sum(rr, sred);
+    bb = block_sum(bb, sred);
+    if (threadIdx.x == 0) {
+        st->rr = rr;
+        st->bb = bb;
+        st->stop = rel_tol * rel_tol * bb;
+        st->iter = 0;
+        st->max_iter = max_iter;
+        st->done = (rr <= st->stop) ? 1 : (max_iter <= 0 ? 2 : 0);
+        st->alpha = st->beta = st->pAp = 0.0;
+    }
+}
+
+// alpha = rr / (p . M p) from the mass kernel's per-workgroup partials
+__global__ void k_cg_alpha(const double *__restrict__ part, int nparts, CgState *__restrict__ st)
+{
+    __shared__ double sred[16];
+    if (st->done) return;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += blockDim.x) s += part[k];
+    s = block_sum(s, sred);
+    if (threadIdx.x == 0) {
+        st->pAp = s;
+        st->alpha = st->rr / s;
+    }
+}
+
+// x += alpha p; r -= alpha Ap (free DOFs); partials of the new r.r
+__global__ void k_cg_update(double *__restrict__ x, double *__restrict__ r,
+                            const double *__restrict__ p, const double *__restrict__ Ap,
+                            const unsigned char *__restrict__ fr, long long n,
+                            const CgState *__restrict__ st, double *__restrict__ part)
+{
+    __shared__ double sred[16];
+    if (st->done) return;
+    const double alpha = st->alpha;
+    double rr = 0.0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        x[i] += alpha * p[i];
+        const double ri = fr[i] ? r[i] - alpha * Ap[i] : 0.0;
+        r[i] = ri;
+        rr += ri * ri;
+    }
+    rr = block_sum(rr, sred);
+    if (threadIdx.x == 0) part[blockIdx.x] = rr;
+}
+
+// beta = rr_new / rr; convergence and iteration-limit checks
+__global__ void k_cg_beta(const double *__restrict__ part, int nparts, CgState *__restrict__ st)
+{
+    __shared__ double sred[16];
+    if (st->done) return;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += blockDim.x) s += part[k];
+    s = block_sum(s, sred);
+    if (threadIdx.x == 0) {
+        st->iter += 1;
+        st->beta = s / st->rr;
+        st->rr = s;
+        if (s <= st->stop)
+            st->done = 1;
+        else if (st->iter >= st->max_iter)
+            st->done = 2;
+    }
+}
+
+// p = r + beta p; Ap = 0 for the next mass application
+__global__ void k_cg_direction(double *__restrict__ p, const double *__restrict__ r,
+                               double *__restrict__ Ap, long long n,
+                               const CgState *__restrict__ st)
+{
+    if (st->done) return;
+    const double beta = st->beta;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        p[i] = r[i] + beta * p[i];
+        Ap[i] = 0.0;
+    }
+}
+
+// partials of the free-DOF residual norm ||b - Ax||^2
+__global__ void k_resid_norm(const double *__restrict__ b, const double *__restrict__ Ax,
+                             const unsigned char *__restrict__ fr, long long n,
+                             double *__restrict__ part)
+{
+    __shared__ double sred[16];
+    double s = 0.0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        if (fr[i]) {
+            const double d = b[i] - Ax[i];
+            s += d * d;
+        }
+    s = block_sum(s, sred);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void k_sum_final(const double *__restrict__ part, int nparts, double *__restrict__ out)
+{
+    __shared__ double sred[16];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += blockDim.x) s += part[k];
+    s = block_sum(s, sred);
+    if (threadIdx.x == 0) *out = s;
+}
+
+void cg_mask(unsigned char *fr, long long n, const int32_t *ess, int n_ess, int *bad,
+             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mask_build, dim3(kVecBlocks), dim3(256), 0, st, fr, n);
+    if (n_ess > 0 && ess)
+        hipLaunchKernelGGL(k_mask_ess, dim3(256), dim3(256), 0, st, fr, n, ess, n_ess, bad);
+}
+
+void cg_mask_apply(double *x, const unsigned char *fr, long long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mask_apply, dim3(kVecBlocks), dim3(256), 0, st, x, fr, n);
+}
+
+void cg_start(const double *b, const double *Ax, double *r, double *p, const unsigned char *fr,
+              long long n, double *part_a, double *part_b, CgState *state, double rel_tol,
+              int max_iter, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_start, dim3(kVecBlocks), dim3(256), 0, st, b, Ax, r, p, fr, n, part_a,
+                       part_b);
+    hipLaunchKernelGGL(k_cg_start_final, dim3(1), dim3(1024), 0, st, part_a, part_b, kVecBlocks,
+                       state, rel_tol, max_iter);
+}
+
+void cg_alpha(const double *part, int nparts, CgState *state, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, st, part, nparts, state);
+}
+
+void cg_update(double *x, double *r, const double *p, const double *Ap, const unsigned char *fr,
+               long long n, const CgState *state, double *part, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_update, dim3(kVecBlocks), dim3(256), 0, st, x, r, p, Ap, fr, n, state,
+                       part);
+}
+
+void cg_beta(const double *part, CgState *state, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1024), 0, st, part, kVecBlocks, state);
+}
+
+void cg_direction(double *p, const double *r, double *Ap, long long n, const CgState *state,
+                  hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_direction, dim3(kVecBlocks), dim3(256), 0, st, p, r, Ap, n, state);
+}
+
+void resid_norm2(const double *b, const double *Ax, const unsigned char *fr, long long n,
+                 double *part, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_resid_norm, dim3(kVecBlocks), dim3(256), 0, st, b, Ax, fr, n, part);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(1024), 0, st, part, kVecBlocks, out);
+}
+
+}  // namespace fepa

@@ -1,0 +1,648 @@
+// FP64 partial-assembly kernels for gfx950: quadrature data, force actions
+// F e / F 1 and F^T v, and the H1 mass action (paper Sec. 3.1 operator
+// decomposition, Sec. 3.2 sum factorisation, Sec. 3.3 Lagrange operators).
+//
+// Thread layouts
+//   column layout (force, force^T, mass): one thread per quadrature column
+//     (qx, qy) of an element, walking qz in registers; NE = 256/Q^2 elements
+//     per workgroup. The qz contraction runs in registers with coefficients
+//     that are uniform across the wave (scalar loads); the qy and qx
+//     contractions go through LDS.
+//   point layout (qdata): one thread per quadrature point, Q^3 per element,
+//     all three 1-D stages staged through LDS.
+// Element data (S, m_q) is stored element-slowest, quadrature-point-fastest,
+// so every load instruction of a wave reads whole 128-byte lines.
+#include "kern_common.hpp"
+#include "kern_fp64.hpp"
+
+namespace fepa {
+
+// ---------------------------------------------------------------- helpers
+__global__ void k_fill(double *__restrict__ y, long long n, double val)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) y[i] = val;
+}
+
+// ------------------------------------------------------------------ force F e
+// y[c][g] += sum_E sum_q sum_d S[c][d](q) dw_i/dxi_d(q) (B_l e)(q)
+// Three H1 contraction stages per component with the three derivative terms
+// fused: z-stage -> (B, B, G), y-stage -> (B | G + B), x-stage -> (G + B).
+template <int D, int Q, bool ONE>
+__global__ void __launch_bounds__(col_ne(Q) * Q * Q)
+k_force(const double *__restrict__ S, const double *__restrict__ e,
+        const int32_t *__restrict__ map, double *__restrict__ y, int E, long long ncomp,
+        const double *__restrict__ tab)
+{
+    constexpr int NE = col_ne(Q), DL = D - 1, QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D;
+    constexpr int DL3 = DL * DL * DL;
+    using T = Tab<D, Q>;
+    __shared__ double sA[NE][3][D][QQ];
+    __shared__ double sC[NE][2][D][D * Q];
+
+    const int tid = threadIdx.x, le = tid / QQ, t = tid % QQ, qx = t % Q, qy = t / Q;
+    const long long el = (long long)xcd_block(blockIdx.x, gridDim.x) * NE + le;
+    const bool act = el < E;
+    const double *__restrict__ Se = S + (act ? el : 0) * 9 * Q3;
+
+    // per-thread columns of the 1-D tables
+    double cBy[Q], cGy[Q], cBx[Q], cGx[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        cBy[k] = qy < D ? tab[T::B + k * D + qy] : 0.0;
+        cGy[k] = qy < D ? tab[T::G + k * D + qy] : 0.0;
+        cBx[k] = qx < D ? tab[T::B + k * D + qx] : 0.0;
+        cGx[k] = qx < D ? tab[T::G + k * D + qx] : 0.0;
+    }
+    int gnode[D];
+#pragma unroll
+    for (int iz = 0; iz < D; ++iz)
+        gnode[iz] = (act && qx < D && qy < D) ? map[el * D3 + iz * D * D + qy * D + qx] : 0;
+
+    // energy at the points of this column: (B_l x B_l x B_l) e
+    double eq[Q];
+    if (ONE) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) eq[k] = 1.0;
+    } else {
+        double ex[DL3];
+#pragma unroll
+        for (int j = 0; j < DL3; ++j) ex[j] = act ? e[el * DL3 + j] : 0.0;
+        double rx[DL], ry[DL];
+#pragma unroll
+        for (int j = 0; j < DL; ++j) {
+            rx[j] = tab[T::BL + qx * DL + j];
+            ry[j] = tab[T::BL + qy * DL + j];
+        }
+        double tz[DL];
+#pragma unroll
+        for (int jz = 0; jz < DL; ++jz) {
+            double s = 0.0;
+#pragma unroll
+            for (int jy = 0; jy < DL; ++jy) {
+                double u = 0.0;
+#pragma unroll
+                for (int jx = 0; jx < DL; ++jx) u += rx[jx] * ex[(jz * DL + jy) * DL + jx];
+                s += ry[jy] * u;
+            }
+            tz[jz] = s;
+        }
+#pragma unroll
+        for (int qz = 0; qz < Q; ++qz) {
+            double s = 0.0;
+#pragma unroll
+            for (int jz = 0; jz < DL; ++jz) s += tab[T::BL + qz * DL + jz] * tz[jz];
+            eq[qz] = s;
+        }
+    }
+
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) {
+        double a0[D], a1[D], a2[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) a0[i] = a1[i] = a2[i] = 0.0;
+#pragma unroll
+        for (int qz = 0; qz < Q; ++qz) {
+            const double s0 = act ? Se[(c * 3 + 0) * Q3 + qz * QQ + t] * eq[qz] : 0.0;
+            const double s1 = act ? Se[(c * 3 + 1) * Q3 + qz * QQ + t] * eq[qz] : 0.0;
+            const double s2 = act ? Se[(c * 3 + 2) * Q3 + qz * QQ + t] * eq[qz] : 0.0;
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) {
+                const double b = tab[T::B + qz * D + iz], g = tab[T::G + qz * D + iz];
+                a0[iz] += b * s0;
+                a1[iz] += b * s1;
+                a2[iz] += g * s2;
+            }
+        }
+#pragma unroll
+        for (int iz = 0; iz < D; ++iz) {
+            sA[le][0][iz][t] = a0[iz];
+            sA[le][1][iz][t] = a1[iz];
+            sA[le][2][iz][t] = a2[iz];
+        }
+        __syncthreads();
+        if (qy < D) {
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) {
+                double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+                for (int k = 0; k < Q; ++k) {
+                    c0 += cBy[k] * sA[le][0][iz][k * Q + qx];
+                    c1 += cGy[k] * sA[le][1][iz][k * Q + qx] + cBy[k] * sA[le][2][iz][k * Q + qx];
+                }
+                sC[le][0][iz][qy * Q + qx] = c0;
+                sC[le][1][iz][qy * Q + qx] = c1;
+            }
+        }
+        __syncthreads();
+        if (act && qx < D && qy < D) {
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) {
+                double r = 0.0;
+#pragma unroll
+                for (int k = 0; k < Q; ++k)
+                    r += cGx[k] * sC[le][0][iz][qy * Q + k] + cBx[k] * sC[le][1][iz][qy * Q + k];
+                atomicAdd(&y[c * ncomp + gnode[iz]], r);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------- force^T F^T v
+// z[E][j] = sum_q phi_j(q) sum_{c,d} S[c][d](q) (grad_xi v_c)_d(q)
+template <int D, int Q>
+__global__ void __launch_bounds__(col_ne(Q) * Q * Q)
+k_force_t(const double *__restrict__ S, const double *__restrict__ v,
+          const int32_t *__restrict__ map, double *__restrict__ z, int E, long long ncomp,
+          const double *__restrict__ tab)
+{
+    constexpr int NE = col_ne(Q), DL = D - 1, QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D;
+    constexpr int DL3 = DL * DL * DL;
+    using T = Tab<D, Q>;
+    __shared__ double sU[NE][3][D3];
+    __shared__ double sX[NE][2][D][D * Q];
+    __shared__ double sT[NE][DL][QQ];
+    __shared__ double sT2[NE][DL][DL * Q];
+
+    const int tid = threadIdx.x, le = tid / QQ, t = tid % QQ, qx = t % Q, qy = t / Q;
+    const long long el = (long long)xcd_block(blockIdx.x, gridDim.x) * NE + le;
+    const bool act = el < E;
+    const double *__restrict__ Se = S + (act ? el : 0) * 9 * Q3;
+
+    for (int k = t; k < 3 * D3; k += QQ) {
+        const int c = k / D3, i = k % D3;
+        sU[le][c][i] = act ? v[c * ncomp + map[el * D3 + i]] : 0.0;
+    }
+    double rBx[D], rGx[D], rBy[D], rGy[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        rBx[i] = tab[T::B + qx * D + i];
+        rGx[i] = tab[T::G + qx * D + i];
+        rBy[i] = tab[T::B + qy * D + i];
+        rGy[i] = tab[T::G + qy * D + i];
+    }
+    __syncthreads();
+
+    double s[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) s[k] = 0.0;
+
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) {
+        // x-stage: thread (qx, iy = qy)
+        if (qy < D) {
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) {
+                double ub = 0.0, ug = 0.0;
+#pragma unroll
+                for (int ix = 0; ix < D; ++ix) {
+                    const double u = sU[le][c][(iz * D + qy) * D + ix];
+                    ub += rBx[ix] * u;
+                    ug += rGx[ix] * u;
+                }
+                sX[le][0][iz][qy * Q + qx] = ub;
+                sX[le][1][iz][qy * Q + qx] = ug;
+            }
+        }
+        __syncthreads();
+        // y-stage into registers: thread (qx, qy)
+        double vx[D], vy[D], vz[D];
+#pragma unroll
+        for (int iz = 0; iz < D; ++iz) {
+            double a = 0.0, b = 0.0, cc = 0.0;
+#pragma unroll
+            for (int iy = 0; iy < D; ++iy) {
+                const double ub = sX[le][0][iz][iy * Q + qx], ug = sX[le][1][iz][iy * Q + qx];
+                a += rBy[iy] * ug;
+                b += rGy[iy] * ub;
+                cc += rBy[iy] * ub;
+            }
+            vx[iz] = a;
+            vy[iz] = b;
+            vz[iz] = cc;
+        }
+        // z-stage and the pointwise S : grad v
+#pragma unroll
+        for (int qz = 0; qz < Q; ++qz) {
+            double dx = 0.0, dy = 0.0, dz = 0.0;
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) {
+                const double bb = tab[T::B + qz * D + iz], gg = tab[T::G + qz * D + iz];
+                dx += bb * vx[iz];
+                dy += bb * vy[iz];
+                dz += gg * vz[iz];
+            }
+            if (act)
+                s[qz] += Se[(c * 3 + 0) * Q3 + qz * QQ + t] * dx +
+                         Se[(c * 3 + 1) * Q3 + qz * QQ + t] * dy +
+                         Se[(c * 3 + 2) * Q3 + qz * QQ + t] * dz;
+        }
+        __syncthreads();
+    }
+    // L2 test functions: B_l^T in z (registers), y and x (LDS)
+#pragma unroll
+    for (int jz = 0; jz < DL; ++jz) {
+        double a = 0.0;
+#pragma unroll
+        for (int qz = 0; qz < Q; ++qz) a += tab[T::BL + qz * DL + jz] * s[qz];
+        sT[le][jz][t] = a;
+    }
+    __syncthreads();
+    if (qy < DL) {
+#pragma unroll
+        for (int jz = 0; jz < DL; ++jz) {
+            double a = 0.0;
+#pragma unroll
+            for (int k = 0; k < Q; ++k) a += tab[T::BL + k * DL + qy] * sT[le][jz][k * Q + qx];
+            sT2[le][jz][qy * Q + qx] = a;
+        }
+    }
+    __syncthreads();
+    if (act && qx < DL && qy < DL) {
+#pragma unroll
+        for (int jz = 0; jz < DL; ++jz) {
+            double a = 0.0;
+#pragma unroll
+            for (int k = 0; k < Q; ++k) a += tab[T::BL + k * DL + qx] * sT2[le][jz][qy * Q + k];
+            z[el * DL3 + (jz * DL + qy) * DL + qx] = a;
+        }
+    }
+}
+
+// -------------------------------------------------------------- mass M_v x
+// y_c += R^T B^T diag(m_q) B R x_c for c = 0..2 (block diagonal over components).
+// With DOT, also accumulates sum_E x_E^T (M_E x_E) per workgroup into part[].
+template <int D, int Q, bool DOT>
+__global__ void __launch_bounds__(col_ne(Q) * Q * Q)
+k_mass(const double *__restrict__ mq, const double *__restrict__ x,
+       const int32_t *__restrict__ map, double *__restrict__ y, int E, long long ncomp,
+       const double *__restrict__ tab, double *__restrict__ part, const int *__restrict__ skip)
+{
+    constexpr int NE = col_ne(Q), QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D;
+    using T = Tab<D, Q>;
+    if (skip && *skip) return;  // a finished CG solve
+    __shared__ double sU[NE][3][D3];
+    __shared__ double sX[NE][D][D * Q];
+    __shared__ double sZ[NE][D][QQ];
+    __shared__ double sY[NE][D][D * Q];
+
+    const int tid = threadIdx.x, le = tid / QQ, t = tid % QQ, qx = t % Q, qy = t / Q;
+    const long long el = (long long)xcd_block(blockIdx.x, gridDim.x) * NE + le;
+    const bool act = el < E;
+
+    for (int k = t; k < 3 * D3; k += QQ) {
+        const int c = k / D3, i = k % D3;
+        sU[le][c][i] = act ? x[c * ncomp + map[el * D3 + i]] : 0.0;
+    }
+    double rBx[D], rBy[D], cBy[Q], cBx[Q], m[Q];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        rBx[i] = tab[T::B + qx * D + i];
+        rBy[i] = tab[T::B + qy * D + i];
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        cBy[k] = qy < D ? tab[T::B + k * D + qy] : 0.0;
+        cBx[k] = qx < D ? tab[T::B + k * D + qx] : 0.0;
+        m[k] = act ? mq[el * Q3 + k * QQ + t] : 0.0;
+    }
+    int gnode[D];
+#pragma unroll
+    for (int iz = 0; iz < D; ++iz)
+        gnode[iz] = (act && qx < D && qy < D) ? map[el * D3 + iz * D * D + qy * D + qx] : 0;
+    double dot = 0.0;
+    __syncthreads();
+
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) {
+        if (qy < D) {
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) {
+                double a = 0.0;
+#pragma unroll
+                for (int ix = 0; ix < D; ++ix) a += rBx[ix] * sU[le][c][(iz * D + qy) * D + ix];
+                sX[le][iz][qy * Q + qx] = a;
+            }
+        }
+        __syncthreads();
+        double w[D];
+#pragma unroll
+        for (int iz = 0; iz < D; ++iz) {
+            double a = 0.0;
+#pragma unroll
+            for (int iy = 0; iy < D; ++iy) a += rBy[iy] * sX[le][iz][iy * Q + qx];
+            w[iz] = a;
+        }
+        double a[D];
+#pragma unroll
+        for (int iz = 0; iz < D; ++iz) a[iz] = 0.0;
+#pragma unroll
+        for (int qz = 0; qz < Q; ++qz) {
+            double u = 0.0;
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) u += tab[T::B + qz * D + iz] * w[iz];
+            u *= m[qz];
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) a[iz] += tab[T::B + qz * D + iz] * u;
+        }
+#pragma unroll
+        for (int iz = 0; iz < D; ++iz) sZ[le][iz][t] = a[iz];
+        __syncthreads();
+        if (qy < D) {
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) {
+                double b = 0.0;
+#pragma unroll
+                for (int k = 0; k < Q; ++k) b += cBy[k] * sZ[le][iz][k * Q + qx];
+                sY[le][iz][qy * Q + qx] = b;
+            }
+        }
+        __syncthreads();
+        if (act && qx < D && qy < D) {
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) {
+                double r = 0.0;
+#pragma unroll
+                for (int k = 0; k < Q; ++k) r += cBx[k] * sY[le][iz][qy * Q + k];
+                atomicAdd(&y[c * ncomp + gnode[iz]], r);
+                if (DOT) dot += r * sU[le][c][(iz * D + qy) * D + qx];
+            }
+        }
+    }
+    if (DOT) {
+        // workgroup sum: wave reduction by DPP-backed shuffles, then LDS
+        for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off);
+        __shared__ double sred[16];
+        const int lane = tid & 63, wv = tid >> 6;
+        if (lane == 0) sred[wv] = dot;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+            for (int k = 0; k < (int)((blockDim.x + 63) >> 6); ++k) s += sred[k];
+            part[blockIdx.x] = s;
+        }
+    }
+}
+
+// ----------------------------------------------------------------- qdata
+// One thread per quadrature point. Gathers x and v (INIT: x0 only), forms the
+// reference gradients of the 6 (or 3) fields by three staged 1-D
+// contractions, then the pointwise algebra:
+//   J, detJ, J^-1; rho = m_q / (w detJ); e_q = (B_l^3 e)(q); p = (gamma-1) rho e_q;
+//   grad v = (grad_xi v) J^-1; eps = sym grad v; l = detJ^(1/3)/p;
+//   mu = rho l (q1 c_s + q2 l max(0, -tr eps)); sigma = -p I + mu eps;
+//   S = w detJ sigma J^-T.
+// INIT mode writes m_q = rho0 detJ0 w instead of S.
+template <int D, int Q, bool INIT>
+__global__ void __launch_bounds__(pt_ne(Q) * Q * Q * Q)
+k_qdata(const double *__restrict__ x, const double *__restrict__ v,
+        const double *__restrict__ e, const int32_t *__restrict__ map, long long ncomp,
+        int node_off, double *__restrict__ mq, double *__restrict__ S, int E,
+        const double *__restrict__ tab, QParams prm, long long *__restrict__ min_key,
+        int *__restrict__ nonfinite)
+{
+    constexpr int NE = pt_ne(Q), DL = D - 1, QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D;
+    constexpr int DL3 = DL * DL * DL;
+    constexpr int NF = INIT ? 3 : 6;
+    using T = Tab<D, Q>;
+    __shared__ double sTab[T::SIZE];
+    __shared__ double sU[NE][NF][D3];
+    __shared__ double sX[NE][NF][2][D * D * Q];
+    __shared__ double sY[NE][NF][3][D * QQ];
+    __shared__ double sE[NE][DL3 > 0 ? DL3 : 1];
+    __shared__ long long sMin;
+    __shared__ int sBad;
+
+    const int tid = threadIdx.x, le = tid / Q3, q = tid % Q3;
+    const int qx = q % Q, qy = (q / Q) % Q, qz = q / QQ;
+    const long long el = (long long)xcd_block(blockIdx.x, gridDim.x) * NE + le;
+    const bool act = el < E;
+
+    for (int k = tid; k < T::SIZE; k += blockDim.x) sTab[k] = tab[k];
+    if (tid == 0) {
+        sMin = 0x7fffffffffffffffLL;
+        sBad = 0;
+    }
+    for (int k = q; k < NF * D3; k += Q3) {
+        const int f = k / D3, i = k % D3;
+        double val = 0.0;
+        if (act) {
+            const long long g = (long long)map[el * D3 + i] - node_off;
+            val = f < 3 ? x[f * ncomp + g] : v[(f - 3) * ncomp + g];
+        }
+        sU[le][f][i] = val;
+    }
+    if (!INIT)
+        for (int k = q; k < DL3; k += Q3) sE[le][k] = act ? e[el * DL3 + k] : 0.0;
+    __syncthreads();
+
+    // x-stage: items (f, iz, iy, qx')
+    for (int k = q; k < NF * D * D * Q; k += Q3) {
+        const int f = k / (D * D * Q), r = k % (D * D * Q);
+        const int iz = r / (D * Q), iy = (r / Q) % D, kx = r % Q;
+        double ub = 0.0, ug = 0.0;
+#pragma unroll
+        for (int ix = 0; ix < D; ++ix) {
+            const double u = sU[le][f][(iz * D + iy) * D + ix];
+            ub += sTab[T::B + kx * D + ix] * u;
+            ug += sTab[T::G + kx * D + ix] * u;
+        }
+        sX[le][f][0][r] = ub;
+        sX[le][f][1][r] = ug;
+    }
+    __syncthreads();
+    // y-stage: items (f, iz, qy', qx') -> (B_y G_x, G_y B_x, B_y B_x)
+    for (int k = q; k < NF * D * QQ; k += Q3) {
+        const int f = k / (D * QQ), r = k % (D * QQ);
+        const int iz = r / QQ, ky = (r / Q) % Q, kx = r % Q;
+        double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+        for (int iy = 0; iy < D; ++iy) {
+            const double ub = sX[le][f][0][(iz * D + iy) * Q + kx];
+            const double ug = sX[le][f][1][(iz * D + iy) * Q + kx];
+            const double by = sTab[T::B + ky * D + iy], gy = sTab[T::G + ky * D + iy];
+            a += by * ug;
+            b += gy * ub;
+            c += by * ub;
+        }
+        sY[le][f][0][r] = a;
+        sY[le][f][1][r] = b;
+        sY[le][f][2][r] = c;
+    }
+    __syncthreads();
+    // z-stage at this thread's point: grad[f][d] = d(field f)/d(xi_d)
+    double grad[NF][3];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+        for (int iz = 0; iz < D; ++iz) {
+            const double bz = sTab[T::B + qz * D + iz], gz = sTab[T::G + qz * D + iz];
+            a += bz * sY[le][f][0][(iz * Q + qy) * Q + qx];
+            b += bz * sY[le][f][1][(iz * Q + qy) * Q + qx];
+            c += gz * sY[le][f][2][(iz * Q + qy) * Q + qx];
+        }
+        grad[f][0] = a;
+        grad[f][1] = b;
+        grad[f][2] = c;
+    }
+    const double w = sTab[T::W + qx] * sTab[T::W + qy] * sTab[T::W + qz];
+    // J[c][d] = grad[c][d]
+    const double J00 = grad[0][0], J01 = grad[0][1], J02 = grad[0][2];
+    const double J10 = grad[1][0], J11 = grad[1][1], J12 = grad[1][2];
+    const double J20 = grad[2][0], J21 = grad[2][1], J22 = grad[2][2];
+    const double A00 = J11 * J22 - J12 * J21, A01 = J02 * J21 - J01 * J22, A02 = J01 * J12 - J02 * J11;
+    const double A10 = J12 * J20 - J10 * J22, A11 = J00 * J22 - J02 * J20, A12 = J02 * J10 - J00 * J12;
+    const double A20 = J10 * J21 - J11 * J20, A21 = J01 * J20 - J00 * J21, A22 = J00 * J11 - J01 * J10;
+    const double detJ = J00 * A00 + J01 * A10 + J02 * A20;
+    bool nf = !isfinite(detJ);
+
+    if (INIT) {
+        if (act) mq[el * Q3 + q] = prm.rho0 * detJ * w;
+    } else if (act) {
+        const double id = 1.0 / detJ;
+        const double Ji[3][3] = {{A00 * id, A01 * id, A02 * id},
+                                 {A10 * id, A11 * id, A12 * id},
+                                 {A20 * id, A21 * id, A22 * id}};
+        const double m = mq[el * Q3 + q];
+        const double rho = m / (w * detJ);
+        double eqv = 0.0;
+        for (int j = 0; j < DL3; ++j) {
+            const int jx = j % DL, jy = (j / DL) % DL, jz = j / (DL * DL);
+            eqv += sTab[T::BL + qx * DL + jx] * sTab[T::BL + qy * DL + jy] *
+                   sTab[T::BL + qz * DL + jz] * sE[le][j];
+        }
+        const double pres = prm.gm1 * rho * eqv;
+        const double cs = sqrt(prm.gamma * prm.gm1 * fmax(eqv, 0.0));
+        double L[3][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                L[c][k] = grad[3 + c][0] * Ji[0][k] + grad[3 + c][1] * Ji[1][k] +
+                          grad[3 + c][2] * Ji[2][k];
+        double eps[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) eps[a][b] = 0.5 * (L[a][b] + L[b][a]);
+        const double tr = eps[0][0] + eps[1][1] + eps[2][2];
+        const double ell = cbrt(detJ) * prm.inv_order;
+        const double mu = rho * ell * (prm.q1 * cs + prm.q2 * ell * fmax(-tr, 0.0));
+        const double wd = w * detJ;
+        double *__restrict__ Se = S + el * 9 * Q3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                double sv = 0.0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const double sig = mu * eps[c][k] - (c == k ? pres : 0.0);
+                    sv += sig * Ji[d][k];
+                }
+                sv *= wd;
+                if (!isfinite(sv)) nf = true;
+                Se[(c * 3 + d) * Q3 + q] = sv;
+            }
+    }
+    if (act) {
+        atomicMin(&sMin, ordered_key(detJ));
+        if (nf) atomicOr(&sBad, 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        atomicMin(min_key, sMin);
+        if (sBad) atomicOr(nonfinite, 1);
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+template <int D, int Q>
+struct Launch {
+    static constexpr int NEc = col_ne(Q), NEp = pt_ne(Q);
+    static int blocks_col(int E) { return (E + NEc - 1) / NEc; }
+    static int blocks_pt(int E) { return (E + NEp - 1) / NEp; }
+
+    static void force(const double *S, const double *e, const int32_t *map, double *y, int E,
+                      long long ncomp, const double *tab, hipStream_t st)
+    {
+        if (e)
+            hipLaunchKernelGGL((k_force<D, Q, false>), dim3(blocks_col(E)), dim3(NEc * Q * Q), 0,
+                               st, S, e, map, y, E, ncomp, tab);
+        else
+            hipLaunchKernelGGL((k_force<D, Q, true>), dim3(blocks_col(E)), dim3(NEc * Q * Q), 0,
+                               st, S, e, map, y, E, ncomp, tab);
+    }
+    static void force_t(const double *S, const double *v, const int32_t *map, double *z, int E,
+                        long long ncomp, const double *tab, hipStream_t st)
+    {
+        hipLaunchKernelGGL((k_force_t<D, Q>), dim3(blocks_col(E)), dim3(NEc * Q * Q), 0, st, S, v,
+                           map, z, E, ncomp, tab);
+    }
+    static void mass(const double *mq, const double *x, const int32_t *map, double *y, int E,
+                     long long ncomp, const double *tab, double *part, const int *skip,
+                     hipStream_t st)
+    {
+        if (part)
+            hipLaunchKernelGGL((k_mass<D, Q, true>), dim3(blocks_col(E)), dim3(NEc * Q * Q), 0,
+                               st, mq, x, map, y, E, ncomp, tab, part, skip);
+        else
+            hipLaunchKernelGGL((k_mass<D, Q, false>), dim3(blocks_col(E)), dim3(NEc * Q * Q), 0,
+                               st, mq, x, map, y, E, ncomp, tab, part, skip);
+    }
+    static void qdata(const double *x, const double *v, const double *e, const int32_t *map,
+                      long long ncomp, int node_off, double *mq, double *S, int E,
+                      const double *tab, QParams prm, long long *min_key, int *nonfinite,
+                      bool init, hipStream_t st)
+    {
+        if (init)
+            hipLaunchKernelGGL((k_qdata<D, Q, true>), dim3(blocks_pt(E)), dim3(NEp * Q * Q * Q), 0,
+                               st, x, v, e, map, ncomp, node_off, mq, S, E, tab, prm, min_key,
+                               nonfinite);
+        else
+            hipLaunchKernelGGL((k_qdata<D, Q, false>), dim3(blocks_pt(E)), dim3(NEp * Q * Q * Q),
+                               0, st, x, v, e, map, ncomp, node_off, mq, S, E, tab, prm, min_key,
+                               nonfinite);
+    }
+    static int mass_blocks(int E) { return blocks_col(E); }
+};
+
+#define FEPA_PQ_LIST(X) \
+    X(1, 2) X(1, 3) X(1, 4) X(2, 3) X(2, 4) X(2, 5) X(3, 4) X(3, 5) X(3, 6) X(4, 5) X(4, 6) X(4, 7)
+
+const KernelSet *fp64_kernels(int p, int Q)
+{
+#define FEPA_ENTRY(P, QQ)                                                                  \
+    static const KernelSet ks_##P##_##QQ = {Launch<P + 1, QQ>::force, Launch<P + 1, QQ>::force_t, \
+                                            Launch<P + 1, QQ>::mass, Launch<P + 1, QQ>::qdata,  \
+                                            Launch<P + 1, QQ>::mass_blocks};                   \
+    if (p == P && Q == QQ) return &ks_##P##_##QQ;
+    FEPA_PQ_LIST(FEPA_ENTRY)
+#undef FEPA_ENTRY
+    return nullptr;
+}
+
+__global__ void k_reset_diag(long long *__restrict__ key, int *__restrict__ flag)
+{
+    if (threadIdx.x == 0) {
+        if (key) *key = 0x7fffffffffffffffLL;
+        if (flag) *flag = 0;
+    }
+}
+
+void launch_reset_diag(long long *key, int *flag, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reset_diag, dim3(1), dim3(64), 0, st, key, flag);
+}
+
+void launch_fill(double *y, long long n, double val, hipStream_t st)
+{
+    if (n <= 0) return;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, y, n, val);
+}
+
+}  // namespace fepa

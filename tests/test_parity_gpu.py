@@ -1,0 +1,305 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, element by
+element, plus the invariants of the discrete operators on the GPU outputs.
+
+FP64 bar: every output within 1e-12 of the oracle, measured as
+max|gpu - oracle| / max(sum of term magnitudes) (force and mass actions) or
+per-element relative error (quadrature data)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2112_07075_amd as fe
+from paper_2112_07075_amd import workload as W
+
+from helpers import elems_touching, make_case, oracle_qdata, rel_cw, rel_elem
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+class GpuRun:
+    """Set up a context for a case and run every action once."""
+
+    def __init__(self, torch, case, flags=0):
+        self.t = torch
+        self.c = case
+        self.x0 = dev(torch, case.mesh.x0)
+        self.ctx = fe.fe_pa_setup(fe.MeshDesc(case.mesh.elem_nodes, self.x0, case.p, case.Q),
+                                  fe.Opts(q1=case.q1, q2=case.q2, flags=flags))
+        self.x, self.v, self.e = (dev(torch, a) for a in (case.x, case.v, case.e))
+        fe.fe_qdata_update(self.ctx, self.x, self.v, self.e)
+
+    def empty_h1(self):
+        return self.t.empty((3, self.c.N), dtype=self.t.float64, device="cuda")
+
+    def qdata(self):
+        Q3 = self.c.Q ** 3
+        S = self.t.empty((self.c.E, 9 * Q3), dtype=self.t.float64, device="cuda")
+        mq = self.t.empty((self.c.E, Q3), dtype=self.t.float64, device="cuda")
+        fe.fe_export_qdata(self.ctx, S, mq)
+        return S.cpu().numpy(), mq.cpu().numpy()
+
+    def force(self, e=None):
+        y = self.empty_h1()
+        fe.fe_force_mult(self.ctx, None if e is None else dev(self.t, e), y)
+        return y.cpu().numpy()
+
+    def force_t(self, v):
+        z = self.t.empty((self.c.E, self.c.p ** 3), dtype=self.t.float64, device="cuda")
+        fe.fe_force_mult_T(self.ctx, dev(self.t, v), z)
+        return z.cpu().numpy()
+
+    def mass(self, x):
+        y = self.empty_h1()
+        fe.fe_mass_mult(self.ctx, dev(self.t, x), y)
+        return y.cpu().numpy()
+
+
+ALL_PQ = [(1, 2), (1, 3), (1, 4), (2, 3), (2, 4), (2, 5), (3, 4), (3, 5), (3, 6), (4, 5), (4, 6),
+          (4, 7)]
+
+
+@pytest.mark.parametrize("p,Q", ALL_PQ)
+def test_all_actions_match_oracle(torch_cuda, p, Q):
+    n = 3 if p <= 3 else 2
+    c = make_case(n, p, Q, seed=11, permute=5 + p, compress=0.3)
+    g = GpuRun(torch_cuda, c)
+    qd = oracle_qdata(c)
+    S, mq = g.qdata()
+    print(f"p={p} Q={Q} E={c.E}", flush=True)
+    assert rel_elem(S, qd["S"].reshape(c.E, -1)) < TOL
+    assert rel_elem(mq, qd["mq"]) < TOL
+    M, S_or = c.mesh.elem_nodes, qd["S"]
+    y1 = O.force_mult(M, p, Q, c.N, S_or)
+    assert rel_cw(g.force(), y1, O.force_mult(M, p, Q, c.N, S_or, absmode=True)) < TOL
+    ye = O.force_mult(M, p, Q, c.N, S_or, c.e)
+    assert rel_cw(g.force(c.e), ye, O.force_mult(M, p, Q, c.N, S_or, c.e, absmode=True)) < TOL
+    z = O.force_mult_T(M, p, Q, c.N, S_or, c.v)
+    assert rel_cw(g.force_t(c.v), z, O.force_mult_T(M, p, Q, c.N, S_or, c.v, absmode=True)) < TOL
+    xr = np.random.default_rng(p * 10 + Q).standard_normal((3, c.N))
+    ym = O.mass_mult(M, p, Q, c.N, qd["mq"], xr)
+    assert rel_cw(g.mass(xr), ym, O.mass_mult(M, p, Q, c.N, qd["mq"], xr, absmode=True)) < TOL
+
+
+def test_config_c1_parity_and_invariants(torch_cuda):
+    # 4x4x4 Q2-Q1, 4^3 points, +-0.1h seeded noise, Taylor-Green fields
+    c = make_case(4, 2, 4, amp=0.1, seed=0, move=0.0)
+    g = GpuRun(torch_cuda, c)
+    qd = oracle_qdata(c)
+    M = c.mesh.elem_nodes
+    y1 = g.force()
+    assert rel_cw(y1, O.force_mult(M, 2, 4, c.N, qd["S"]),
+                  O.force_mult(M, 2, 4, c.N, qd["S"], absmode=True)) < TOL
+    ya = O.force_mult(M, 2, 4, c.N, qd["S"], absmode=True)
+    # momentum conservation and the energy exchange identity v.(F 1) = 1.(F^T v)
+    assert np.abs(y1.sum(axis=1)).max() < 1e-13 * ya.sum()
+    z = g.force_t(c.v)
+    assert abs((c.v * y1).sum() - z.sum()) < 1e-12 * np.abs(c.v * ya).sum()
+    ye = g.force(c.e)
+    yea = O.force_mult(M, 2, 4, c.N, qd["S"], c.e, absmode=True)
+    assert abs((c.v * ye).sum() - (z * c.e).sum()) < 1e-12 * (np.abs(c.v) * yea).sum()
+    # 1^T M 1 = mass of the domain (rho0 = 1, volume 1)
+    m1 = g.mass(np.ones((3, c.N)))
+    assert np.abs(m1.sum(axis=1) - 1.0).max() < 1e-13
+    d = fe.fe_get_diag(g.ctx)
+    assert d["min_detj"] > 0 and d["nonfinite"] == 0
+    assert abs(d["min_detj"] - oracle_qdata(c)["detJ"].min()) < 1e-15
+
+
+@pytest.mark.parametrize("n,p", [(1, 1), (1, 2), (1, 4), (5, 2), (7, 1)])
+def test_single_and_ragged_element_counts(torch_cuda, n, p):
+    c = make_case(n, p, seed=3)
+    g = GpuRun(torch_cuda, c)
+    qd = oracle_qdata(c)
+    M = c.mesh.elem_nodes
+    assert rel_cw(g.force(c.e), O.force_mult(M, p, c.Q, c.N, qd["S"], c.e),
+                  O.force_mult(M, p, c.Q, c.N, qd["S"], c.e, absmode=True)) < TOL
+    assert rel_cw(g.force_t(c.v), O.force_mult_T(M, p, c.Q, c.N, qd["S"], c.v),
+                  O.force_mult_T(M, p, c.Q, c.N, qd["S"], c.v, absmode=True)) < TOL
+
+
+def test_free_stream_on_gpu(torch_cuda):
+    # v = 0, e = e0: interior nodes feel no force; faces carry -p0 n (closed form)
+    p, n = 2, 3
+    mesh = W.cube_mesh(n, p, 0.1, seed=4)
+    e0 = 3.0
+    p0 = (5.0 / 3.0 - 1.0) * e0
+    x0 = dev(torch_cuda, mesh.x0)
+    ctx = fe.fe_pa_setup(fe.MeshDesc(mesh.elem_nodes, x0, p, 4))
+    e = dev(torch_cuda, np.full((mesh.n_elem, p ** 3), e0))
+    fe.fe_qdata_update(ctx, x0, torch_cuda.zeros_like(x0), e)
+    y = torch_cuda.empty_like(x0)
+    fe.fe_force_mult(ctx, None, y)
+    y = y.cpu().numpy()
+    for c in range(3):
+        inner = (mesh.ref[c] > 0) & (mesh.ref[c] < 1)
+        assert np.abs(y[c, inner]).max() < 1e-13
+        assert abs(y[c, mesh.ref[c] == 1.0].sum() + p0) < 1e-13
+
+
+def test_multi_mesh_context(torch_cuda):
+    cases = [make_case(2, 1, 3, seed=21), make_case(3, 2, 4, seed=22, permute=3),
+             make_case(2, 3, 5, seed=23)]
+    x0 = dev(torch_cuda, np.concatenate([c.mesh.x0 for c in cases], axis=1))
+    offs = np.cumsum([0] + [c.N for c in cases])
+    descs = [fe.MeshDesc(c.mesh.elem_nodes, x0[:, offs[k]:offs[k + 1]].contiguous(), c.p, c.Q)
+             for k, c in enumerate(cases)]
+    ctx = fe.fe_pa_setup(descs, fe.Opts())
+    no, eo, lo = fe.fe_mesh_offsets(ctx)
+    assert list(no) == list(offs[:-1])
+    x = dev(torch_cuda, np.concatenate([c.x for c in cases], axis=1))
+    v = dev(torch_cuda, np.concatenate([c.v for c in cases], axis=1))
+    e = dev(torch_cuda, np.concatenate([c.e.ravel() for c in cases]))
+    fe.fe_qdata_update(ctx, x, v, e)
+    y = torch_cuda.empty_like(x)
+    fe.fe_force_mult(ctx, e, y)
+    z = torch_cuda.empty_like(e)
+    fe.fe_force_mult_T(ctx, v, z)
+    y, z = y.cpu().numpy(), z.cpu().numpy()
+    for k, c in enumerate(cases):
+        qd = oracle_qdata(c)
+        M = c.mesh.elem_nodes
+        yk = y[:, offs[k]:offs[k + 1]]
+        assert rel_cw(yk, O.force_mult(M, c.p, c.Q, c.N, qd["S"], c.e),
+                      O.force_mult(M, c.p, c.Q, c.N, qd["S"], c.e, absmode=True)) < TOL
+        zk = z[lo[k]:lo[k] + c.E * c.p ** 3]
+        assert rel_cw(zk, O.force_mult_T(M, c.p, c.Q, c.N, qd["S"], c.v),
+                      O.force_mult_T(M, c.p, c.Q, c.N, qd["S"], c.v, absmode=True)) < TOL
+
+
+@pytest.mark.parametrize("ess", [False, True])
+def test_mass_cg_matches_oracle(torch_cuda, ess):
+    c = make_case(4, 2, 4, seed=6)
+    g = GpuRun(torch_cuda, c)
+    mq = oracle_qdata(c)["mq"]
+    rng = np.random.default_rng(3)
+    xs = rng.standard_normal((3, c.N))
+    ess_idx = W.boundary_normal_dofs(c.mesh) if ess else None
+    if ess:
+        xs.ravel()[ess_idx] = 0.0
+    b = O.mass_mult(c.mesh.elem_nodes, 2, 4, c.N, mq, xs)
+    xo, it_o, rr_o, ok = O.mass_cg(c.mesh.elem_nodes, 2, 4, c.N, mq, b, ess=ess_idx, rel_tol=1e-12)
+    assert ok
+    xg = torch_cuda.zeros((3, c.N), dtype=torch_cuda.float64, device="cuda")
+    ess_t = None if ess_idx is None else dev(torch_cuda, ess_idx)
+    rc, it_g, rr_g = fe.fe_mass_cg(g.ctx, dev(torch_cuda, b), xg, ess_t, rel_tol=1e-12)
+    xg = xg.cpu().numpy()
+    assert rr_g < 2e-12
+    assert abs(it_g - it_o) <= 3
+    assert np.linalg.norm(xg - xs) < 1e-9 * np.linalg.norm(xs)
+    assert np.linalg.norm(xg - xo) < 1e-9 * np.linalg.norm(xo)
+    if ess:
+        assert np.all(xg.ravel()[ess_idx] == 0.0)
+
+
+def test_cg_iteration_limit_and_bad_dofs(torch_cuda):
+    c = make_case(3, 2, 4, seed=7)
+    g = GpuRun(torch_cuda, c)
+    b = dev(torch_cuda, np.random.default_rng(1).standard_normal((3, c.N)))
+    x = torch_cuda.zeros_like(b)
+    rc, it, rr = fe.fe_mass_cg(g.ctx, b, x, None, rel_tol=1e-14, max_iter=1, check=False)
+    assert rc == fe.FE_ENOTCONV and it == 1
+    bad = dev(torch_cuda, np.array([0, 3 * c.N + 5], dtype=np.int32))
+    with pytest.raises(fe.FepaError) as ei:
+        fe.fe_mass_cg(g.ctx, b, x, bad)
+    assert ei.value.status == fe.FE_EINVAL
+
+
+def test_inverted_mesh_and_nonfinite_flags(torch_cuda):
+    mesh = W.cube_mesh(2, 2, 0.0)
+    x0 = mesh.x0.copy()
+    x0[0] = 1.0 - x0[0]           # mirror: every Jacobian determinant is negative
+    with pytest.raises(fe.FepaError) as ei:
+        fe.fe_pa_setup(fe.MeshDesc(mesh.elem_nodes, dev(torch_cuda, x0), 2, 4))
+    assert ei.value.status == fe.FE_EBADMESH
+    c = make_case(2, 2, 4)
+    g = GpuRun(torch_cuda, c)
+    e = c.e.copy()
+    e[1, 2] = np.nan
+    fe.fe_qdata_update(g.ctx, g.x, g.v, dev(torch_cuda, e))
+    assert fe.fe_get_diag(g.ctx)["nonfinite"] == 1
+    fe.fe_qdata_update(g.ctx, g.x, g.v, g.e)
+    assert fe.fe_get_diag(g.ctx)["nonfinite"] == 0
+
+
+# ------------------------------------------------------------ full-size cases
+FULL = [("C2", 48, 2, 4), ("C3", 24, 4, 6), ("C4", 64, 3, 5)]
+
+
+@pytest.mark.parametrize("name,n,p,Q", FULL)
+def test_full_size_sampled_parity(torch_cuda, name, n, p, Q):
+    """The workloads at their full sizes, in the launch configuration the
+    benchmark times, checked on sampled elements and nodes the oracle computes
+    one by one."""
+    c = make_case(n, p, Q, seed=0, move=0.0)
+    print(f"{name}: E={c.E} N={c.N}", flush=True)
+    g = GpuRun(torch_cuda, c)
+    d = fe.fe_get_diag(g.ctx)
+    assert d["min_detj"] > 0 and d["nonfinite"] == 0
+    rng = np.random.default_rng(42)
+    el = np.unique(np.concatenate([[0, c.E - 1], rng.integers(0, c.E, 40)])).astype(np.int32)
+    nodes = np.unique(np.concatenate([[0, c.N - 1], rng.integers(0, c.N, 24)]))
+    touch = elems_touching(c.mesh, nodes)
+    sel = np.union1d(el, touch).astype(np.int32)
+    qd = oracle_qdata(c, elems=sel)
+    M = c.mesh.elem_nodes
+    # quadrature data on sampled elements
+    Q3 = Q ** 3
+    S_all = torch_cuda.empty((c.E, 9 * Q3), dtype=torch_cuda.float64, device="cuda")
+    fe.fe_export_qdata(g.ctx, S_all, None)
+    S_g = S_all[torch_cuda.from_numpy(el.astype(np.int64)).cuda()].cpu().numpy()
+    del S_all
+    assert rel_elem(S_g, qd["S"].reshape(c.E, -1)[el]) < TOL
+    # F^T v on sampled elements
+    z = g.force_t(c.v)
+    zo = O.force_mult_T(M, p, Q, c.N, qd["S"], c.v, elems=el)
+    za = O.force_mult_T(M, p, Q, c.N, qd["S"], c.v, elems=el, absmode=True)
+    assert rel_cw(z[el], zo[el], za[el]) < TOL
+    # F 1, F e and M x at sampled nodes (all their elements included)
+    for e in (None, c.e):
+        y = g.force(e)
+        yo = O.force_mult(M, p, Q, c.N, qd["S"], e, elems=touch)
+        ya = O.force_mult(M, p, Q, c.N, qd["S"], e, elems=touch, absmode=True)
+        assert rel_cw(y[:, nodes], yo[:, nodes], ya[:, nodes]) < TOL
+    xr = np.random.default_rng(5).standard_normal((3, c.N))
+    ym = g.mass(xr)
+    yo = O.mass_mult(M, p, Q, c.N, qd["mq"], xr, elems=touch)
+    ya = O.mass_mult(M, p, Q, c.N, qd["mq"], xr, elems=touch, absmode=True)
+    assert rel_cw(ym[:, nodes], yo[:, nodes], ya[:, nodes]) < TOL
+
+
+def test_full_size_c2_cg(torch_cuda):
+    """C2's CG solve to 1e-12: the true residual reported by the library, and
+    M x = b re-checked by the oracle at sampled nodes."""
+    c = make_case(48, 2, 4, seed=0, move=0.0)
+    g = GpuRun(torch_cuda, c)
+    y1 = torch_cuda.empty((3, c.N), dtype=torch_cuda.float64, device="cuda")
+    fe.fe_force_mult(g.ctx, None, y1)
+    b = -y1
+    x = torch_cuda.zeros_like(b)
+    ess = dev(torch_cuda, W.boundary_normal_dofs(c.mesh))
+    rc, it, rr = fe.fe_mass_cg(g.ctx, b, x, ess, rel_tol=1e-12, max_iter=2000)
+    print(f"C2 CG: {it} iterations, true rel residual {rr:.3e}", flush=True)
+    assert rr < 2e-12
+    rng = np.random.default_rng(8)
+    nodes = np.unique(rng.integers(0, c.N, 16))
+    inner = nodes[np.all((c.mesh.ref[:, nodes] > 0) & (c.mesh.ref[:, nodes] < 1), axis=0)]
+    touch = elems_touching(c.mesh, inner)
+    mq = O.qdata(c.mesh.elem_nodes, 2, 4, c.N, c.mesh.x0, c.mesh.x0, None, None, elems=touch,
+                 want=("mq",))["mq"]
+    xn = x.cpu().numpy()
+    Mx = O.mass_mult(c.mesh.elem_nodes, 2, 4, c.N, mq, xn, elems=touch)
+    bn = b.cpu().numpy()
+    scale = np.abs(bn).max()
+    assert np.abs(Mx[:, inner] - bn[:, inner]).max() < 1e-9 * scale
