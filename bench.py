@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the PA path here runs on a single MI355X "
@@ -89,6 +91,16 @@ def main():
     import torch
     import paper_2112_07075_amd as fe
     from paper_2112_07075_amd import workload as W
+
+    if args.copy_calib:
+        # reads 1 GiB and writes 1 GiB per launch: the reference for FETCH_SIZE/WRITE_SIZE
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes_each_way": src.numel() * 8, "launches": 3}))
+        return
 
     n, p, Q, label = CONFIGS[args.config]
     mesh = W.cube_mesh(n, p, W.default_amp(p), seed=0)
