@@ -17,6 +17,7 @@
 #include "basis.hpp"
 #include "kern_cg.hpp"
 #include "kern_fp64.hpp"
+#include "patch.hpp"
 
 using namespace fepa;
 
@@ -27,11 +28,13 @@ thread_local std::string g_setup_error;
 struct MeshRec {
     int E = 0, p = 0, Q = 0, N = 0;
     long long node_off = 0, elem_off = 0, l2_off = 0, S_off = 0, mq_off = 0;
-    long long map_off = 0;   // into the concatenated map (int32 entries)
-    long long part_off = 0;  // into the CG partial-sum array
+    long long part_off = 0;  // into the CG dot-partial array (one per patch)
     int tab_slot = 0;        // into the table buffer (doubles)
     const KernelSet *ks = nullptr;
     double rho0 = 1.0;
+    PatchDev pd;             // device patch plan
+    const int32_t *orphans = nullptr;
+    int n_orphans = 0;
 };
 
 struct TimerPool {
@@ -54,7 +57,7 @@ struct fe_ctx {
     bool uniform_pq = true;
     // device memory owned by the context
     double *S = nullptr, *mq = nullptr, *tabs = nullptr;
-    int32_t *maps = nullptr;
+    std::vector<void *> plan_bufs;  // per-mesh patch plan arrays
     long long *min_key = nullptr;
     int *nonfinite = nullptr;
     double *r = nullptr, *p = nullptr, *Ap = nullptr;
@@ -112,9 +115,11 @@ void free_all(fe_ctx *c)
 {
     if (!c) return;
     if (c->st) (void)hipStreamSynchronize(c->st);
-    void *dptrs[] = {c->S, c->mq, c->tabs, c->maps, c->min_key, c->nonfinite, c->r, c->p,
+    void *dptrs[] = {c->S, c->mq, c->tabs, c->min_key, c->nonfinite, c->r, c->p,
                      c->Ap, c->part, c->part2, c->scal, c->fr, c->cg, c->bad};
     for (void *d : dptrs)
+        if (d) (void)hipFree(d);
+    for (void *d : c->plan_bufs)
         if (d) (void)hipFree(d);
     void *hptrs[] = {c->h_cg, c->h_scal, c->h_key, c->h_flag};
     for (void *h : hptrs)
@@ -248,7 +253,6 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
     // layout of the concatenated vectors and context arrays
     std::map<std::pair<int, int>, int> slot_of;
     std::vector<double> tab_host;
-    long long map_len = 0;
     for (int m = 0; m < n_mesh; ++m) {
         const fe_mesh_desc_t &d = meshes[m];
         MeshRec r;
@@ -259,14 +263,11 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         r.rho0 = d.rho0;
         r.ks = fp64_kernels(r.p, r.Q);
         const long long Q3 = (long long)r.Q * r.Q * r.Q;
-        const long long D3 = (long long)(r.p + 1) * (r.p + 1) * (r.p + 1);
         r.node_off = ctx->N_tot;
         r.elem_off = ctx->E_tot;
         r.l2_off = ctx->L2_tot;
         r.S_off = ctx->S_len;
         r.mq_off = ctx->mq_len;
-        r.map_off = map_len;
-        r.part_off = ctx->n_parts;
         auto key = std::make_pair(r.p, r.Q);
         if (!slot_of.count(key)) {
             slot_of[key] = (int)tab_host.size();
@@ -280,8 +281,6 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         ctx->L2_tot += (long long)r.E * r.p * r.p * r.p;
         ctx->S_len += 9 * Q3 * r.E;
         ctx->mq_len += Q3 * r.E;
-        map_len += D3 * r.E;
-        ctx->n_parts += r.ks->mass_blocks(r.E);
         if (m > 0 && (r.p != ctx->mesh[0].p || r.Q != ctx->mesh[0].Q)) ctx->uniform_pq = false;
         ctx->mesh.push_back(r);
     }
@@ -294,17 +293,13 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
     int rc = FE_OK;
     if ((rc = dev_alloc(ctx, &ctx->S, ctx->S_len, &qb)) || (rc = dev_alloc(ctx, &ctx->mq, ctx->mq_len, &qb)) ||
         (rc = dev_alloc(ctx, &ctx->tabs, (long long)tab_host.size(), &wb)) ||
-        (rc = dev_alloc(ctx, &ctx->maps, map_len, &wb)) ||
         (rc = dev_alloc(ctx, &ctx->min_key, 1, &wb)) || (rc = dev_alloc(ctx, &ctx->nonfinite, 1, &wb)) ||
         (rc = dev_alloc(ctx, &ctx->r, 3 * ctx->N_tot, &wb)) || (rc = dev_alloc(ctx, &ctx->p, 3 * ctx->N_tot, &wb)) ||
         (rc = dev_alloc(ctx, &ctx->Ap, 3 * ctx->N_tot, &wb)) ||
-        (rc = dev_alloc(ctx, &ctx->part, std::max<long long>(ctx->n_parts, kVecBlocks), &wb)) ||
         (rc = dev_alloc(ctx, &ctx->part2, kVecBlocks, &wb)) || (rc = dev_alloc(ctx, &ctx->scal, 8, &wb)) ||
         (rc = dev_alloc(ctx, &ctx->fr, 3 * ctx->N_tot, &wb)) || (rc = dev_alloc(ctx, &ctx->cg, 1, &wb)) ||
         (rc = dev_alloc(ctx, &ctx->bad, 1, &wb)))
         return bail(rc);
-    ctx->qdata_bytes = qb;
-    ctx->work_bytes = wb;
     if (hipHostMalloc((void **)&ctx->h_cg, sizeof(CgState)) != hipSuccess ||
         hipHostMalloc((void **)&ctx->h_scal, 8 * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&ctx->h_key, sizeof(long long)) != hipSuccess ||
@@ -321,29 +316,81 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
                     return bail(FE_EDEVICE);
                 }
         }
-
-    // uploads: tables, maps with global node ids
-    std::vector<int32_t> map_host((size_t)map_len);
-    for (int m = 0; m < n_mesh; ++m) {
-        const MeshRec &r = ctx->mesh[m];
-        const long long D3 = (long long)(r.p + 1) * (r.p + 1) * (r.p + 1);
-        for (long long k = 0; k < D3 * r.E; ++k)
-            map_host[r.map_off + k] = (int32_t)(meshes[m].elem_nodes[k] + r.node_off);
-    }
     if (hipMemcpyAsync(ctx->tabs, tab_host.data(), tab_host.size() * sizeof(double),
-                       hipMemcpyHostToDevice, ctx->st) != hipSuccess ||
-        hipMemcpyAsync(ctx->maps, map_host.data(), map_host.size() * sizeof(int32_t),
                        hipMemcpyHostToDevice, ctx->st) != hipSuccess) {
         ctx->err = "upload failed";
         return bail(FE_EDEVICE);
     }
+
+    // patch plans (element order, distinct nodes, shared-node gather) per mesh
+    auto upload = [&](const void *src, size_t bytes, void **dst) -> int {
+        void *d = nullptr;
+        if (hipMalloc(&d, bytes ? bytes : 4) != hipSuccess) {
+            (void)hipGetLastError();
+            return FE_ENOMEM;
+        }
+        ctx->plan_bufs.push_back(d);
+        wb += (long long)(bytes ? bytes : 4);
+        *dst = d;
+        if (bytes && hipMemcpy(d, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return FE_EDEVICE;
+        return FE_OK;
+    };
+    for (int m = 0; m < n_mesh; ++m) {
+        MeshRec &r = ctx->mesh[m];
+        std::vector<double> x0h(3 * (size_t)r.N);
+        if (hipStreamSynchronize(ctx->st) != hipSuccess ||
+            hipMemcpy(x0h.data(), meshes[m].x0, x0h.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+            ctx->err = "cannot read x0";
+            return bail(FE_EDEVICE);
+        }
+        const int D3 = (r.p + 1) * (r.p + 1) * (r.p + 1);
+        // patch size: the largest Morton block (512, 64, 8 elements) allowed for this
+        // order that still leaves >= 1024 workgroups
+        const int bmax = r.p == 1 ? 512 : (r.p == 2 ? 64 : 8);
+        int B = 8;
+        for (int cand : {512, 64, 8})
+            if (cand <= bmax && (long long)r.E / cand >= 1024) { B = cand; break; }
+        PatchPlan pl = build_patch_plan(r.E, r.p, r.N, meshes[m].elem_nodes, x0h.data(), B, r.ks->umax);
+        for (auto &g : pl.map_int) g += (int32_t)r.node_off;
+        for (auto &g : pl.pn) g += (int32_t)r.node_off;
+        for (auto &g : pl.sh_node) g += (int32_t)r.node_off;
+        for (auto &g : pl.orphans) g += (int32_t)r.node_off;
+        void *dp = nullptr;
+        int urc = FE_OK;
+        if ((urc = upload(pl.perm.data(), pl.perm.size() * 4, &dp)) == FE_OK) r.pd.perm = (const int32_t *)dp;
+        if (!urc && (urc = upload(pl.map_int.data(), pl.map_int.size() * 4, &dp)) == FE_OK) r.pd.map = (const int32_t *)dp;
+        if (!urc && (urc = upload(pl.slot.data(), pl.slot.size() * 2, &dp)) == FE_OK) r.pd.slot = (const uint16_t *)dp;
+        if (!urc && (urc = upload(pl.pn.data(), pl.pn.size() * 4, &dp)) == FE_OK) r.pd.pn = (const int32_t *)dp;
+        if (!urc && (urc = upload(pl.patch.data(), pl.patch.size() * sizeof(PatchRec), &dp)) == FE_OK) r.pd.ptab = (const int32_t *)dp;
+        if (!urc && (urc = upload(pl.sh_node.data(), pl.sh_node.size() * 4, &dp)) == FE_OK) r.pd.sh_node = (const int32_t *)dp;
+        if (!urc && (urc = upload(pl.sh_ptr.data(), pl.sh_ptr.size() * 4, &dp)) == FE_OK) r.pd.sh_ptr = (const int32_t *)dp;
+        if (!urc && (urc = upload(pl.sh_idx.data(), pl.sh_idx.size() * 4, &dp)) == FE_OK) r.pd.sh_idx = (const int32_t *)dp;
+        if (!urc && (urc = upload(nullptr, (size_t)pl.n_entries * 3 * sizeof(double), &dp)) == FE_OK) r.pd.part = (double *)dp;
+        if (!urc && (urc = upload(pl.orphans.data(), pl.orphans.size() * 4, &dp)) == FE_OK) r.orphans = (const int32_t *)dp;
+        if (urc) {
+            ctx->err = "patch plan upload failed";
+            return bail(urc);
+        }
+        static_assert(sizeof(PatchRec) == 6 * sizeof(int32_t), "patch table rows are 6 int32");
+        r.pd.n_patch = (int)pl.patch.size();
+        r.pd.n_shared = (int)pl.sh_node.size();
+        r.n_orphans = (int)pl.orphans.size();
+        r.part_off = ctx->n_parts;
+        ctx->n_parts += r.pd.n_patch;
+        (void)D3;
+    }
+    if ((rc = dev_alloc(ctx, &ctx->part, std::max<long long>(ctx->n_parts, kVecBlocks), &wb)))
+        return bail(rc);
+    ctx->qdata_bytes = qb;
+    ctx->work_bytes = wb;
+
     // m_q = rho0 detJ0 w from x0 (qdata kernels in set-up mode)
     launch_reset_diag(ctx->min_key, ctx->nonfinite, ctx->st);
     for (int m = 0; m < n_mesh; ++m) {
         const MeshRec &r = ctx->mesh[m];
         QParams prm{r.rho0, o.gamma, o.gamma - 1.0, o.q1, o.q2, 1.0 / r.p};
-        r.ks->qdata(meshes[m].x0, nullptr, nullptr, ctx->maps + r.map_off, r.N, (int)r.node_off,
-                    ctx->mq + r.mq_off, nullptr, r.E, ctx->tabs + r.tab_slot, prm, ctx->min_key,
+        r.ks->qdata(meshes[m].x0, nullptr, nullptr, r.pd, r.E, r.N, (int)r.node_off,
+                    ctx->mq + r.mq_off, nullptr, ctx->tabs + r.tab_slot, prm, ctx->min_key,
                     ctx->nonfinite, true, ctx->st);
     }
     if (hipGetLastError() != hipSuccess ||
@@ -407,9 +454,9 @@ int fe_qdata_update(fe_ctx_t *ctx, const double *x, const double *v, const doubl
         for (const MeshRec &r : ctx->mesh) {
             QParams prm{r.rho0, ctx->opts.gamma, ctx->opts.gamma - 1.0, ctx->opts.q1, ctx->opts.q2,
                         1.0 / r.p};
-            r.ks->qdata(x, v, e + r.l2_off, ctx->maps + r.map_off, ctx->N_tot, 0,
-                        ctx->mq + r.mq_off, ctx->S + r.S_off, r.E, ctx->tabs + r.tab_slot, prm,
-                        ctx->min_key, ctx->nonfinite, false, ctx->st);
+            r.ks->qdata(x, v, e + r.l2_off, r.pd, r.E, ctx->N_tot, 0, ctx->mq + r.mq_off,
+                        ctx->S + r.S_off, ctx->tabs + r.tab_slot, prm, ctx->min_key,
+                        ctx->nonfinite, false, ctx->st);
         }
     }
     HIP_OK(hipGetLastError());
@@ -421,12 +468,14 @@ int fe_force_mult(fe_ctx_t *ctx, const double *e, double *y)
     if (!ctx) return FE_EINVAL;
     if (!y) return fail(ctx, FE_EINVAL, "NULL output%s");
     if ((const void *)e == (const void *)y) return fail(ctx, FE_EINVAL, "input aliases output%s");
-    launch_fill(y, 3 * ctx->N_tot, 0.0, ctx->st);
     {
         ScopedTimer tm(ctx, FE_TIMER_FORCE);
-        for (const MeshRec &r : ctx->mesh)
-            r.ks->force(ctx->S + r.S_off, e ? e + r.l2_off : nullptr, ctx->maps + r.map_off, y, r.E,
-                        ctx->N_tot, ctx->tabs + r.tab_slot, ctx->st);
+        for (const MeshRec &r : ctx->mesh) {
+            r.ks->force(ctx->S + r.S_off, e ? e + r.l2_off : nullptr, r.pd, y, ctx->N_tot,
+                        ctx->tabs + r.tab_slot, ctx->st);
+            launch_gather_shared(r.pd, y, ctx->N_tot, nullptr, ctx->st);
+            launch_zero_nodes(r.orphans, r.n_orphans, y, ctx->N_tot, nullptr, ctx->st);
+        }
     }
     HIP_OK(hipGetLastError());
     return FE_OK;
@@ -440,7 +489,7 @@ int fe_force_mult_T(fe_ctx_t *ctx, const double *v, double *z)
     {
         ScopedTimer tm(ctx, FE_TIMER_FORCE_T);
         for (const MeshRec &r : ctx->mesh)
-            r.ks->force_t(ctx->S + r.S_off, v, ctx->maps + r.map_off, z + r.l2_off, r.E, ctx->N_tot,
+            r.ks->force_t(ctx->S + r.S_off, v, r.pd, r.E, z + r.l2_off, ctx->N_tot,
                           ctx->tabs + r.tab_slot, ctx->st);
     }
     HIP_OK(hipGetLastError());
@@ -449,9 +498,12 @@ int fe_force_mult_T(fe_ctx_t *ctx, const double *v, double *z)
 
 static void mass_launch(fe_ctx *ctx, const double *x, double *y, bool dot, const int *skip)
 {
-    for (const MeshRec &r : ctx->mesh)
-        r.ks->mass(ctx->mq + r.mq_off, x, ctx->maps + r.map_off, y, r.E, ctx->N_tot,
-                   ctx->tabs + r.tab_slot, dot ? ctx->part + r.part_off : nullptr, skip, ctx->st);
+    for (const MeshRec &r : ctx->mesh) {
+        r.ks->mass(ctx->mq + r.mq_off, x, r.pd, y, ctx->N_tot, ctx->tabs + r.tab_slot,
+                   dot ? ctx->part + r.part_off : nullptr, skip, ctx->st);
+        launch_gather_shared(r.pd, y, ctx->N_tot, skip, ctx->st);
+        launch_zero_nodes(r.orphans, r.n_orphans, y, ctx->N_tot, skip, ctx->st);
+    }
 }
 
 int fe_mass_mult(fe_ctx_t *ctx, const double *x, double *y)
@@ -459,7 +511,6 @@ int fe_mass_mult(fe_ctx_t *ctx, const double *x, double *y)
     if (!ctx) return FE_EINVAL;
     if (!x || !y) return fail(ctx, FE_EINVAL, "NULL argument%s");
     if ((const void *)x == (const void *)y) return fail(ctx, FE_EINVAL, "input aliases output%s");
-    launch_fill(y, 3 * ctx->N_tot, 0.0, ctx->st);
     {
         ScopedTimer tm(ctx, FE_TIMER_MASS);
         mass_launch(ctx, x, y, false, nullptr);
@@ -480,11 +531,9 @@ int fe_mass_cg(fe_ctx_t *ctx, const double *b, double *x, const int32_t *ess_dof
     launch_reset_diag(nullptr, ctx->bad, ctx->st);
     cg_mask(ctx->fr, n, ess_dofs, n_ess, ctx->bad, ctx->st);
     cg_mask_apply(x, ctx->fr, n, ctx->st);
-    launch_fill(ctx->Ap, n, 0.0, ctx->st);
     mass_launch(ctx, x, ctx->Ap, false, nullptr);
     cg_start(b, ctx->Ap, ctx->r, ctx->p, ctx->fr, n, ctx->part, ctx->part2, ctx->cg, rel_tol,
              max_iter, ctx->st);
-    launch_fill(ctx->Ap, n, 0.0, ctx->st);
     HIP_OK(hipGetLastError());
     const int *skip = &ctx->cg->done;
     int batch = 4;
@@ -497,7 +546,7 @@ int fe_mass_cg(fe_ctx_t *ctx, const double *b, double *x, const int32_t *ess_dof
             cg_alpha(ctx->part, (int)ctx->n_parts, ctx->cg, ctx->st);
             cg_update(x, ctx->r, ctx->p, ctx->Ap, ctx->fr, n, ctx->cg, ctx->part2, ctx->st);
             cg_beta(ctx->part2, ctx->cg, ctx->st);
-            cg_direction(ctx->p, ctx->r, ctx->Ap, n, ctx->cg, ctx->st);
+            cg_direction(ctx->p, ctx->r, n, ctx->cg, ctx->st);
         }
         HIP_OK(hipGetLastError());
         HIP_OK(hipMemcpyAsync(ctx->h_cg, ctx->cg, sizeof(CgState), hipMemcpyDeviceToHost, ctx->st));
@@ -509,7 +558,6 @@ int fe_mass_cg(fe_ctx_t *ctx, const double *b, double *x, const int32_t *ess_dof
     }
     const CgState st = *ctx->h_cg;
     // true residual of the free system
-    launch_fill(ctx->Ap, n, 0.0, ctx->st);
     mass_launch(ctx, x, ctx->Ap, false, nullptr);
     resid_norm2(b, ctx->Ap, ctx->fr, n, ctx->part2, ctx->scal, ctx->st);
     HIP_OK(hipMemcpyAsync(ctx->h_scal, ctx->scal, sizeof(double), hipMemcpyDeviceToHost, ctx->st));
@@ -540,10 +588,14 @@ int fe_export_qdata(fe_ctx_t *ctx, double *S_out, double *mq_out)
 {
     if (!ctx) return FE_EINVAL;
     if (!ctx->uniform_pq) return fail(ctx, FE_EINVAL, "export needs one (order, q1d) for all meshes%s");
-    if (S_out)
-        HIP_OK(hipMemcpyAsync(S_out, ctx->S, sizeof(double) * ctx->S_len, hipMemcpyDeviceToDevice, ctx->st));
-    if (mq_out)
-        HIP_OK(hipMemcpyAsync(mq_out, ctx->mq, sizeof(double) * ctx->mq_len, hipMemcpyDeviceToDevice, ctx->st));
+    for (const MeshRec &r : ctx->mesh) {
+        const int Q3 = r.Q * r.Q * r.Q;
+        if (S_out)
+            launch_unpermute_rows(ctx->S + r.S_off, r.pd.perm, r.E, 9 * Q3, S_out + r.S_off, ctx->st);
+        if (mq_out)
+            launch_unpermute_rows(ctx->mq + r.mq_off, r.pd.perm, r.E, Q3, mq_out + r.mq_off, ctx->st);
+    }
+    HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(ctx->st));
     return FE_OK;
 }

@@ -153,18 +153,15 @@ __global__ void k_cg_beta(const double *__restrict__ part, int nparts, CgState *
     }
 }
 
-// p = r + beta p; Ap = 0 for the next mass application
-__global__ void k_cg_direction(double *__restrict__ p, const double *__restrict__ r,
-                               double *__restrict__ Ap, long long n,
+// p = r + beta p
+__global__ void k_cg_direction(double *__restrict__ p, const double *__restrict__ r, long long n,
                                const CgState *__restrict__ st)
 {
     if (st->done) return;
     const double beta = st->beta;
     const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
         p[i] = r[i] + beta * p[i];
-        Ap[i] = 0.0;
-    }
 }
 
 // partials of the free-DOF residual norm ||b - Ax||^2
@@ -233,10 +230,9 @@ void cg_beta(const double *part, CgState *state, hipStream_t st)
     hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1024), 0, st, part, kVecBlocks, state);
 }
 
-void cg_direction(double *p, const double *r, double *Ap, long long n, const CgState *state,
-                  hipStream_t st)
+void cg_direction(double *p, const double *r, long long n, const CgState *state, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cg_direction, dim3(kVecBlocks), dim3(256), 0, st, p, r, Ap, n, state);
+    hipLaunchKernelGGL(k_cg_direction, dim3(kVecBlocks), dim3(256), 0, st, p, r, n, state);
 }
 
 void resid_norm2(const double *b, const double *Ax, const unsigned char *fr, long long n,

@@ -24,8 +24,7 @@ void cg_alpha(const double *part, int nparts, CgState *state, hipStream_t st);
 void cg_update(double *x, double *r, const double *p, const double *Ap, const unsigned char *fr,
                long long n, const CgState *state, double *part, hipStream_t st);
 void cg_beta(const double *part, CgState *state, hipStream_t st);
-void cg_direction(double *p, const double *r, double *Ap, long long n, const CgState *state,
-                  hipStream_t st);
+void cg_direction(double *p, const double *r, long long n, const CgState *state, hipStream_t st);
 void resid_norm2(const double *b, const double *Ax, const unsigned char *fr, long long n,
                  double *part, double *out, hipStream_t st);
 

@@ -25,28 +25,84 @@ __global__ void k_fill(double *__restrict__ y, long long n, double val)
     for (; i < n; i += stride) y[i] = val;
 }
 
+// ---------------------------------------------------------------- patches
+// Distinct-node slots per patch (UMAX) and the elements a workgroup handles
+// per pass (NE) are chosen so that the static LDS of a workgroup stays below
+// 60 KiB: at most two workgroups' worth of LDS fit a 160 KiB CU at once.
+__host__ __device__ constexpr int patch_umax(int D) { return D == 4 ? 512 : 768; }
+__host__ __device__ constexpr int fit_ne(int Q, int per_elem, int fixed)
+{
+    int ne = col_ne(Q);
+    while (ne > 1 && fixed + ne * per_elem > 60 * 1024) --ne;
+    return ne;
+}
+__host__ __device__ constexpr int force_ne(int D, int Q)
+{
+    return fit_ne(Q, 8 * (3 * D * Q * Q + 2 * D * D * Q), 24 * patch_umax(D));
+}
+__host__ __device__ constexpr int mass_ne(int D, int Q)
+{
+    return fit_ne(Q, 8 * (2 * D * D * Q + D * Q * Q) + 4 * D * D * D, 48 * patch_umax(D) + 256);
+}
+
+// One row of the patch table: first element, element count, offset of the
+// distinct-node list, distinct nodes U, private nodes P, shared-partial offset.
+struct PatchRow {
+    int eb, cnt, pno, U, P, sho;
+};
+__device__ __forceinline__ PatchRow load_patch(const int32_t *__restrict__ ptab, int k)
+{
+    const int32_t *r = ptab + 6 * (long long)k;
+    return PatchRow{r[0], r[1], r[2], r[3], r[4], r[5]};
+}
+
+// R^T of one patch: private nodes are stored, shared nodes leave a partial.
+template <int UMAX>
+__device__ __forceinline__ void patch_write(const double *acc, const PatchRow &pr,
+                                            const int32_t *__restrict__ pn,
+                                            double *__restrict__ y, double *__restrict__ part,
+                                            long long ncomp)
+{
+    for (int u = threadIdx.x; u < pr.U; u += blockDim.x) {
+        const double a0 = acc[3 * u], a1 = acc[3 * u + 1], a2 = acc[3 * u + 2];
+        if (u < pr.P) {
+            const long long g = pn[pr.pno + u];
+            y[g] = a0;
+            y[ncomp + g] = a1;
+            y[2 * ncomp + g] = a2;
+        } else {
+            double *dst = part + 3 * (long long)(pr.sho + u - pr.P);
+            dst[0] = a0;
+            dst[1] = a1;
+            dst[2] = a2;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ force F e
-// y[c][g] += sum_E sum_q sum_d S[c][d](q) dw_i/dxi_d(q) (B_l e)(q)
-// Three H1 contraction stages per component with the three derivative terms
-// fused: z-stage -> (B, B, G), y-stage -> (B | G + B), x-stage -> (G + B).
+// y[c][g] = sum_E sum_q sum_d S[c][d](q) dw_i/dxi_d(q) (B_l e)(q), one patch
+// per workgroup. Three H1 contraction stages per component with the three
+// derivative terms fused: z-stage -> (B, B, G), y-stage -> (B | G + B),
+// x-stage -> (G + B); element results are summed into the patch's LDS slots.
 template <int D, int Q, bool ONE>
-__global__ void __launch_bounds__(col_ne(Q) * Q * Q)
+__global__ void __launch_bounds__(force_ne(D, Q) * Q * Q)
 k_force(const double *__restrict__ S, const double *__restrict__ e,
-        const int32_t *__restrict__ map, double *__restrict__ y, int E, long long ncomp,
+        const int32_t *__restrict__ perm, const uint16_t *__restrict__ slot,
+        const int32_t *__restrict__ pn, const int32_t *__restrict__ ptab,
+        double *__restrict__ y, double *__restrict__ part, long long ncomp,
         const double *__restrict__ tab)
 {
-    constexpr int NE = col_ne(Q), DL = D - 1, QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D;
-    constexpr int DL3 = DL * DL * DL;
+    constexpr int NE = force_ne(D, Q), UMAX = patch_umax(D);
+    constexpr int DL = D - 1, QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D, DL3 = DL * DL * DL;
     using T = Tab<D, Q>;
+    __shared__ double acc[3 * UMAX];
     __shared__ double sA[NE][3][D][QQ];
     __shared__ double sC[NE][2][D][D * Q];
 
     const int tid = threadIdx.x, le = tid / QQ, t = tid % QQ, qx = t % Q, qy = t / Q;
-    const long long el = (long long)xcd_block(blockIdx.x, gridDim.x) * NE + le;
-    const bool act = el < E;
-    const double *__restrict__ Se = S + (act ? el : 0) * 9 * Q3;
+    const PatchRow pr = load_patch(ptab, xcd_block(blockIdx.x, gridDim.x));
+    for (int k = tid; k < 3 * pr.U; k += blockDim.x) acc[k] = 0.0;
 
-    // per-thread columns of the 1-D tables
     double cBy[Q], cGy[Q], cBx[Q], cGx[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
@@ -55,107 +111,109 @@ k_force(const double *__restrict__ S, const double *__restrict__ e,
         cBx[k] = qx < D ? tab[T::B + k * D + qx] : 0.0;
         cGx[k] = qx < D ? tab[T::G + k * D + qx] : 0.0;
     }
-    int gnode[D];
-#pragma unroll
-    for (int iz = 0; iz < D; ++iz)
-        gnode[iz] = (act && qx < D && qy < D) ? map[el * D3 + iz * D * D + qy * D + qx] : 0;
-
-    // energy at the points of this column: (B_l x B_l x B_l) e
-    double eq[Q];
-    if (ONE) {
-#pragma unroll
-        for (int k = 0; k < Q; ++k) eq[k] = 1.0;
-    } else {
-        double ex[DL3];
-#pragma unroll
-        for (int j = 0; j < DL3; ++j) ex[j] = act ? e[el * DL3 + j] : 0.0;
-        double rx[DL], ry[DL];
-#pragma unroll
-        for (int j = 0; j < DL; ++j) {
-            rx[j] = tab[T::BL + qx * DL + j];
-            ry[j] = tab[T::BL + qy * DL + j];
-        }
-        double tz[DL];
-#pragma unroll
-        for (int jz = 0; jz < DL; ++jz) {
-            double s = 0.0;
-#pragma unroll
-            for (int jy = 0; jy < DL; ++jy) {
-                double u = 0.0;
-#pragma unroll
-                for (int jx = 0; jx < DL; ++jx) u += rx[jx] * ex[(jz * DL + jy) * DL + jx];
-                s += ry[jy] * u;
-            }
-            tz[jz] = s;
-        }
-#pragma unroll
-        for (int qz = 0; qz < Q; ++qz) {
-            double s = 0.0;
-#pragma unroll
-            for (int jz = 0; jz < DL; ++jz) s += tab[T::BL + qz * DL + jz] * tz[jz];
-            eq[qz] = s;
-        }
-    }
+    __syncthreads();
 
 #pragma unroll 1
-    for (int c = 0; c < 3; ++c) {
-        double a0[D], a1[D], a2[D];
+    for (int base = 0; base < pr.cnt; base += NE) {
+        const int idx = base + le;
+        const bool act = idx < pr.cnt;
+        const long long el = pr.eb + (act ? idx : 0);
+        const double *__restrict__ Se = S + el * 9 * Q3;
+        int sl[D];
 #pragma unroll
-        for (int i = 0; i < D; ++i) a0[i] = a1[i] = a2[i] = 0.0;
+        for (int iz = 0; iz < D; ++iz)
+            sl[iz] = (act && qx < D && qy < D) ? slot[el * D3 + iz * D * D + qy * D + qx] : 0;
+        double eq[Q];
+        if (ONE) {
 #pragma unroll
-        for (int qz = 0; qz < Q; ++qz) {
-            const double s0 = act ? Se[(c * 3 + 0) * Q3 + qz * QQ + t] * eq[qz] : 0.0;
-            const double s1 = act ? Se[(c * 3 + 1) * Q3 + qz * QQ + t] * eq[qz] : 0.0;
-            const double s2 = act ? Se[(c * 3 + 2) * Q3 + qz * QQ + t] * eq[qz] : 0.0;
+            for (int k = 0; k < Q; ++k) eq[k] = 1.0;
+        } else {
+            const double *__restrict__ ee = e + (long long)perm[el] * DL3;
+            double tz[DL];
 #pragma unroll
-            for (int iz = 0; iz < D; ++iz) {
-                const double b = tab[T::B + qz * D + iz], g = tab[T::G + qz * D + iz];
-                a0[iz] += b * s0;
-                a1[iz] += b * s1;
-                a2[iz] += g * s2;
-            }
-        }
+            for (int jz = 0; jz < DL; ++jz) {
+                double s = 0.0;
 #pragma unroll
-        for (int iz = 0; iz < D; ++iz) {
-            sA[le][0][iz][t] = a0[iz];
-            sA[le][1][iz][t] = a1[iz];
-            sA[le][2][iz][t] = a2[iz];
-        }
-        __syncthreads();
-        if (qy < D) {
+                for (int jy = 0; jy < DL; ++jy) {
+                    double u = 0.0;
 #pragma unroll
-            for (int iz = 0; iz < D; ++iz) {
-                double c0 = 0.0, c1 = 0.0;
-#pragma unroll
-                for (int k = 0; k < Q; ++k) {
-                    c0 += cBy[k] * sA[le][0][iz][k * Q + qx];
-                    c1 += cGy[k] * sA[le][1][iz][k * Q + qx] + cBy[k] * sA[le][2][iz][k * Q + qx];
+                    for (int jx = 0; jx < DL; ++jx)
+                        u += tab[T::BL + qx * DL + jx] * (act ? ee[(jz * DL + jy) * DL + jx] : 0.0);
+                    s += tab[T::BL + qy * DL + jy] * u;
                 }
-                sC[le][0][iz][qy * Q + qx] = c0;
-                sC[le][1][iz][qy * Q + qx] = c1;
+                tz[jz] = s;
+            }
+#pragma unroll
+            for (int qz = 0; qz < Q; ++qz) {
+                double s = 0.0;
+#pragma unroll
+                for (int jz = 0; jz < DL; ++jz) s += tab[T::BL + qz * DL + jz] * tz[jz];
+                eq[qz] = s;
             }
         }
-        __syncthreads();
-        if (act && qx < D && qy < D) {
+#pragma unroll 1
+        for (int c = 0; c < 3; ++c) {
+            double a0[D], a1[D], a2[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) a0[i] = a1[i] = a2[i] = 0.0;
+#pragma unroll
+            for (int qz = 0; qz < Q; ++qz) {
+                const double s0 = act ? Se[(c * 3 + 0) * Q3 + qz * QQ + t] * eq[qz] : 0.0;
+                const double s1 = act ? Se[(c * 3 + 1) * Q3 + qz * QQ + t] * eq[qz] : 0.0;
+                const double s2 = act ? Se[(c * 3 + 2) * Q3 + qz * QQ + t] * eq[qz] : 0.0;
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) {
+                    const double b = tab[T::B + qz * D + iz], g = tab[T::G + qz * D + iz];
+                    a0[iz] += b * s0;
+                    a1[iz] += b * s1;
+                    a2[iz] += g * s2;
+                }
+            }
 #pragma unroll
             for (int iz = 0; iz < D; ++iz) {
-                double r = 0.0;
+                sA[le][0][iz][t] = a0[iz];
+                sA[le][1][iz][t] = a1[iz];
+                sA[le][2][iz][t] = a2[iz];
+            }
+            __syncthreads();
+            if (qy < D) {
 #pragma unroll
-                for (int k = 0; k < Q; ++k)
-                    r += cGx[k] * sC[le][0][iz][qy * Q + k] + cBx[k] * sC[le][1][iz][qy * Q + k];
-                atomicAdd(&y[c * ncomp + gnode[iz]], r);
+                for (int iz = 0; iz < D; ++iz) {
+                    double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+                    for (int k = 0; k < Q; ++k) {
+                        c0 += cBy[k] * sA[le][0][iz][k * Q + qx];
+                        c1 += cGy[k] * sA[le][1][iz][k * Q + qx] + cBy[k] * sA[le][2][iz][k * Q + qx];
+                    }
+                    sC[le][0][iz][qy * Q + qx] = c0;
+                    sC[le][1][iz][qy * Q + qx] = c1;
+                }
+            }
+            __syncthreads();
+            if (act && qx < D && qy < D) {
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) {
+                    double r = 0.0;
+#pragma unroll
+                    for (int k = 0; k < Q; ++k)
+                        r += cGx[k] * sC[le][0][iz][qy * Q + k] + cBx[k] * sC[le][1][iz][qy * Q + k];
+                    atomicAdd(&acc[3 * sl[iz] + c], r);
+                }
             }
         }
     }
+    __syncthreads();
+    patch_write<UMAX>(acc, pr, pn, y, part, ncomp);
 }
 
 // ---------------------------------------------------------- force^T F^T v
-// z[E][j] = sum_q phi_j(q) sum_{c,d} S[c][d](q) (grad_xi v_c)_d(q)
+// z[E][j] = sum_q phi_j(q) sum_{c,d} S[c][d](q) (grad_xi v_c)_d(q); elements in patch
+// order, rows of z in caller order.
 template <int D, int Q>
 __global__ void __launch_bounds__(col_ne(Q) * Q * Q)
 k_force_t(const double *__restrict__ S, const double *__restrict__ v,
-          const int32_t *__restrict__ map, double *__restrict__ z, int E, long long ncomp,
-          const double *__restrict__ tab)
+          const int32_t *__restrict__ map, const int32_t *__restrict__ perm,
+          double *__restrict__ z, int E, long long ncomp, const double *__restrict__ tab)
 {
     constexpr int NE = col_ne(Q), DL = D - 1, QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D;
     constexpr int DL3 = DL * DL * DL;
@@ -265,37 +323,45 @@ k_force_t(const double *__restrict__ S, const double *__restrict__ v,
             double a = 0.0;
 #pragma unroll
             for (int k = 0; k < Q; ++k) a += tab[T::BL + k * DL + qx] * sT2[le][jz][qy * Q + k];
-            z[el * DL3 + (jz * DL + qy) * DL + qx] = a;
+            z[(long long)perm[el] * DL3 + (jz * DL + qy) * DL + qx] = a;
         }
     }
 }
 
 // -------------------------------------------------------------- mass M_v x
-// y_c += R^T B^T diag(m_q) B R x_c for c = 0..2 (block diagonal over components).
-// With DOT, also accumulates sum_E x_E^T (M_E x_E) per workgroup into part[].
+// y_c = R^T B^T diag(m_q) B R x_c for c = 0..2, one patch per workgroup. The
+// patch's distinct nodes are read once into LDS. With DOT, the workgroup also
+// writes sum_E x_E^T (M_E x_E) (= x^T M x over its elements) to part_dot.
 template <int D, int Q, bool DOT>
-__global__ void __launch_bounds__(col_ne(Q) * Q * Q)
+__global__ void __launch_bounds__(mass_ne(D, Q) * Q * Q)
 k_mass(const double *__restrict__ mq, const double *__restrict__ x,
-       const int32_t *__restrict__ map, double *__restrict__ y, int E, long long ncomp,
-       const double *__restrict__ tab, double *__restrict__ part, const int *__restrict__ skip)
+       const uint16_t *__restrict__ slot, const int32_t *__restrict__ pn,
+       const int32_t *__restrict__ ptab, double *__restrict__ y, double *__restrict__ part,
+       long long ncomp, const double *__restrict__ tab, double *__restrict__ part_dot,
+       const int *__restrict__ skip)
 {
-    constexpr int NE = col_ne(Q), QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D;
+    constexpr int NE = mass_ne(D, Q), UMAX = patch_umax(D);
+    constexpr int QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D;
     using T = Tab<D, Q>;
     if (skip && *skip) return;  // a finished CG solve
-    __shared__ double sU[NE][3][D3];
+    __shared__ double acc[3 * UMAX];
+    __shared__ double xs[3 * UMAX];
+    __shared__ int sSl[NE][D3];
     __shared__ double sX[NE][D][D * Q];
     __shared__ double sZ[NE][D][QQ];
     __shared__ double sY[NE][D][D * Q];
+    __shared__ double sred[8];
 
     const int tid = threadIdx.x, le = tid / QQ, t = tid % QQ, qx = t % Q, qy = t / Q;
-    const long long el = (long long)xcd_block(blockIdx.x, gridDim.x) * NE + le;
-    const bool act = el < E;
-
-    for (int k = t; k < 3 * D3; k += QQ) {
-        const int c = k / D3, i = k % D3;
-        sU[le][c][i] = act ? x[c * ncomp + map[el * D3 + i]] : 0.0;
+    const PatchRow pr = load_patch(ptab, xcd_block(blockIdx.x, gridDim.x));
+    for (int u = tid; u < pr.U; u += blockDim.x) {
+        const long long g = pn[pr.pno + u];
+        xs[3 * u] = x[g];
+        xs[3 * u + 1] = x[ncomp + g];
+        xs[3 * u + 2] = x[2 * ncomp + g];
+        acc[3 * u] = acc[3 * u + 1] = acc[3 * u + 2] = 0.0;
     }
-    double rBx[D], rBy[D], cBy[Q], cBx[Q], m[Q];
+    double rBx[D], rBy[D], cBy[Q], cBx[Q];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
         rBx[i] = tab[T::B + qx * D + i];
@@ -305,83 +371,139 @@ k_mass(const double *__restrict__ mq, const double *__restrict__ x,
     for (int k = 0; k < Q; ++k) {
         cBy[k] = qy < D ? tab[T::B + k * D + qy] : 0.0;
         cBx[k] = qx < D ? tab[T::B + k * D + qx] : 0.0;
-        m[k] = act ? mq[el * Q3 + k * QQ + t] : 0.0;
     }
-    int gnode[D];
-#pragma unroll
-    for (int iz = 0; iz < D; ++iz)
-        gnode[iz] = (act && qx < D && qy < D) ? map[el * D3 + iz * D * D + qy * D + qx] : 0;
     double dot = 0.0;
-    __syncthreads();
 
 #pragma unroll 1
-    for (int c = 0; c < 3; ++c) {
-        if (qy < D) {
+    for (int base = 0; base < pr.cnt; base += NE) {
+        const int idx = base + le;
+        const bool act = idx < pr.cnt;
+        const long long el = pr.eb + (act ? idx : 0);
+        for (int i = t; i < D3; i += QQ) sSl[le][i] = act ? slot[el * D3 + i] : 0;
+        double m[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) m[k] = act ? mq[el * Q3 + k * QQ + t] : 0.0;
+        __syncthreads();
+#pragma unroll 1
+        for (int c = 0; c < 3; ++c) {
+            if (qy < D) {
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) {
+                    double a = 0.0;
+#pragma unroll
+                    for (int ix = 0; ix < D; ++ix)
+                        a += rBx[ix] * xs[3 * sSl[le][(iz * D + qy) * D + ix] + c];
+                    sX[le][iz][qy * Q + qx] = a;
+                }
+            }
+            __syncthreads();
+            double w[D];
 #pragma unroll
             for (int iz = 0; iz < D; ++iz) {
                 double a = 0.0;
 #pragma unroll
-                for (int ix = 0; ix < D; ++ix) a += rBx[ix] * sU[le][c][(iz * D + qy) * D + ix];
-                sX[le][iz][qy * Q + qx] = a;
+                for (int iy = 0; iy < D; ++iy) a += rBy[iy] * sX[le][iz][iy * Q + qx];
+                w[iz] = a;
+            }
+            double a[D];
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) a[iz] = 0.0;
+#pragma unroll
+            for (int qz = 0; qz < Q; ++qz) {
+                double u = 0.0;
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) u += tab[T::B + qz * D + iz] * w[iz];
+                u *= m[qz];
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) a[iz] += tab[T::B + qz * D + iz] * u;
+            }
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) sZ[le][iz][t] = a[iz];
+            __syncthreads();
+            if (qy < D) {
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) {
+                    double b = 0.0;
+#pragma unroll
+                    for (int k = 0; k < Q; ++k) b += cBy[k] * sZ[le][iz][k * Q + qx];
+                    sY[le][iz][qy * Q + qx] = b;
+                }
+            }
+            __syncthreads();
+            if (act && qx < D && qy < D) {
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) {
+                    double r = 0.0;
+#pragma unroll
+                    for (int k = 0; k < Q; ++k) r += cBx[k] * sY[le][iz][qy * Q + k];
+                    const int s = sSl[le][(iz * D + qy) * D + qx];
+                    atomicAdd(&acc[3 * s + c], r);
+                    if (DOT) dot += r * xs[3 * s + c];
+                }
             }
         }
-        __syncthreads();
-        double w[D];
-#pragma unroll
-        for (int iz = 0; iz < D; ++iz) {
-            double a = 0.0;
-#pragma unroll
-            for (int iy = 0; iy < D; ++iy) a += rBy[iy] * sX[le][iz][iy * Q + qx];
-            w[iz] = a;
-        }
-        double a[D];
-#pragma unroll
-        for (int iz = 0; iz < D; ++iz) a[iz] = 0.0;
-#pragma unroll
-        for (int qz = 0; qz < Q; ++qz) {
-            double u = 0.0;
-#pragma unroll
-            for (int iz = 0; iz < D; ++iz) u += tab[T::B + qz * D + iz] * w[iz];
-            u *= m[qz];
-#pragma unroll
-            for (int iz = 0; iz < D; ++iz) a[iz] += tab[T::B + qz * D + iz] * u;
-        }
-#pragma unroll
-        for (int iz = 0; iz < D; ++iz) sZ[le][iz][t] = a[iz];
-        __syncthreads();
-        if (qy < D) {
-#pragma unroll
-            for (int iz = 0; iz < D; ++iz) {
-                double b = 0.0;
-#pragma unroll
-                for (int k = 0; k < Q; ++k) b += cBy[k] * sZ[le][iz][k * Q + qx];
-                sY[le][iz][qy * Q + qx] = b;
-            }
-        }
-        __syncthreads();
-        if (act && qx < D && qy < D) {
-#pragma unroll
-            for (int iz = 0; iz < D; ++iz) {
-                double r = 0.0;
-#pragma unroll
-                for (int k = 0; k < Q; ++k) r += cBx[k] * sY[le][iz][qy * Q + k];
-                atomicAdd(&y[c * ncomp + gnode[iz]], r);
-                if (DOT) dot += r * sU[le][c][(iz * D + qy) * D + qx];
-            }
-        }
+        __syncthreads();  // sSl is rewritten by the next pass
     }
+    __syncthreads();
+    patch_write<UMAX>(acc, pr, pn, y, part, ncomp);
     if (DOT) {
-        // workgroup sum: wave reduction by DPP-backed shuffles, then LDS
         for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off);
-        __shared__ double sred[16];
         const int lane = tid & 63, wv = tid >> 6;
         if (lane == 0) sred[wv] = dot;
         __syncthreads();
         if (tid == 0) {
             double s = 0.0;
             for (int k = 0; k < (int)((blockDim.x + 63) >> 6); ++k) s += sred[k];
-            part[blockIdx.x] = s;
+            part_dot[blockIdx.x] = s;
         }
+    }
+}
+
+// Shared nodes: y[c][g] = sum of the patch partials of g, in ascending patch order.
+__global__ void k_gather_shared(const double *__restrict__ part, const int32_t *__restrict__ sh_node,
+                                const int32_t *__restrict__ sh_ptr,
+                                const int32_t *__restrict__ sh_idx, int n_shared,
+                                double *__restrict__ y, long long ncomp,
+                                const int *__restrict__ skip)
+{
+    if (skip && *skip) return;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_shared) return;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int j = sh_ptr[s]; j < sh_ptr[s + 1]; ++j) {
+        const double *src = part + 3 * (long long)sh_idx[j];
+        a0 += src[0];
+        a1 += src[1];
+        a2 += src[2];
+    }
+    const long long g = sh_node[s];
+    y[g] = a0;
+    y[ncomp + g] = a1;
+    y[2 * ncomp + g] = a2;
+}
+
+// y[c][g] = 0 for nodes that no element references
+__global__ void k_zero_nodes(const int32_t *__restrict__ nodes, int n, double *__restrict__ y,
+                             long long ncomp, const int *__restrict__ skip)
+{
+    if (skip && *skip) return;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const long long g = nodes[s];
+    y[g] = 0.0;
+    y[ncomp + g] = 0.0;
+    y[2 * ncomp + g] = 0.0;
+}
+
+// out[perm[k]][:] = in[k][:] (patch order -> caller order)
+__global__ void k_unpermute_rows(const double *__restrict__ in, const int32_t *__restrict__ perm,
+                                 long long rows, int len, double *__restrict__ out)
+{
+    const long long n = rows * len;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const long long r = i / len, j = i % len;
+        out[(long long)perm[r] * len + j] = in[i];
     }
 }
 
@@ -397,7 +519,8 @@ k_mass(const double *__restrict__ mq, const double *__restrict__ x,
 template <int D, int Q, bool INIT>
 __global__ void __launch_bounds__(pt_ne(Q) * Q * Q * Q)
 k_qdata(const double *__restrict__ x, const double *__restrict__ v,
-        const double *__restrict__ e, const int32_t *__restrict__ map, long long ncomp,
+        const double *__restrict__ e, const int32_t *__restrict__ map,
+        const int32_t *__restrict__ perm, long long ncomp,
         int node_off, double *__restrict__ mq, double *__restrict__ S, int E,
         const double *__restrict__ tab, QParams prm, long long *__restrict__ min_key,
         int *__restrict__ nonfinite)
@@ -434,7 +557,7 @@ k_qdata(const double *__restrict__ x, const double *__restrict__ v,
         sU[le][f][i] = val;
     }
     if (!INIT)
-        for (int k = q; k < DL3; k += Q3) sE[le][k] = act ? e[el * DL3 + k] : 0.0;
+        for (int k = q; k < DL3; k += Q3) sE[le][k] = act ? e[(long long)perm[el] * DL3 + k] : 0.0;
     __syncthreads();
 
     // x-stage: items (f, iz, iy, qx')
@@ -561,52 +684,50 @@ k_qdata(const double *__restrict__ x, const double *__restrict__ v,
 // ---------------------------------------------------------------- launchers
 template <int D, int Q>
 struct Launch {
-    static constexpr int NEc = col_ne(Q), NEp = pt_ne(Q);
-    static int blocks_col(int E) { return (E + NEc - 1) / NEc; }
-    static int blocks_pt(int E) { return (E + NEp - 1) / NEp; }
+    static constexpr int NEp = pt_ne(Q);
 
-    static void force(const double *S, const double *e, const int32_t *map, double *y, int E,
+    static void force(const double *S, const double *e, const PatchDev &pd, double *y,
                       long long ncomp, const double *tab, hipStream_t st)
     {
+        const dim3 grid(pd.n_patch), block(force_ne(D, Q) * Q * Q);
         if (e)
-            hipLaunchKernelGGL((k_force<D, Q, false>), dim3(blocks_col(E)), dim3(NEc * Q * Q), 0,
-                               st, S, e, map, y, E, ncomp, tab);
+            hipLaunchKernelGGL((k_force<D, Q, false>), grid, block, 0, st, S, e, pd.perm, pd.slot,
+                               pd.pn, pd.ptab, y, pd.part, ncomp, tab);
         else
-            hipLaunchKernelGGL((k_force<D, Q, true>), dim3(blocks_col(E)), dim3(NEc * Q * Q), 0,
-                               st, S, e, map, y, E, ncomp, tab);
+            hipLaunchKernelGGL((k_force<D, Q, true>), grid, block, 0, st, S, e, pd.perm, pd.slot,
+                               pd.pn, pd.ptab, y, pd.part, ncomp, tab);
     }
-    static void force_t(const double *S, const double *v, const int32_t *map, double *z, int E,
+    static void force_t(const double *S, const double *v, const PatchDev &pd, int E, double *z,
                         long long ncomp, const double *tab, hipStream_t st)
     {
-        hipLaunchKernelGGL((k_force_t<D, Q>), dim3(blocks_col(E)), dim3(NEc * Q * Q), 0, st, S, v,
-                           map, z, E, ncomp, tab);
+        constexpr int NE = col_ne(Q);
+        hipLaunchKernelGGL((k_force_t<D, Q>), dim3((E + NE - 1) / NE), dim3(NE * Q * Q), 0, st, S,
+                           v, pd.map, pd.perm, z, E, ncomp, tab);
     }
-    static void mass(const double *mq, const double *x, const int32_t *map, double *y, int E,
-                     long long ncomp, const double *tab, double *part, const int *skip,
+    static void mass(const double *mq, const double *x, const PatchDev &pd, double *y,
+                     long long ncomp, const double *tab, double *part_dot, const int *skip,
                      hipStream_t st)
     {
-        if (part)
-            hipLaunchKernelGGL((k_mass<D, Q, true>), dim3(blocks_col(E)), dim3(NEc * Q * Q), 0,
-                               st, mq, x, map, y, E, ncomp, tab, part, skip);
+        const dim3 grid(pd.n_patch), block(mass_ne(D, Q) * Q * Q);
+        if (part_dot)
+            hipLaunchKernelGGL((k_mass<D, Q, true>), grid, block, 0, st, mq, x, pd.slot, pd.pn,
+                               pd.ptab, y, pd.part, ncomp, tab, part_dot, skip);
         else
-            hipLaunchKernelGGL((k_mass<D, Q, false>), dim3(blocks_col(E)), dim3(NEc * Q * Q), 0,
-                               st, mq, x, map, y, E, ncomp, tab, part, skip);
+            hipLaunchKernelGGL((k_mass<D, Q, false>), grid, block, 0, st, mq, x, pd.slot, pd.pn,
+                               pd.ptab, y, pd.part, ncomp, tab, part_dot, skip);
     }
-    static void qdata(const double *x, const double *v, const double *e, const int32_t *map,
-                      long long ncomp, int node_off, double *mq, double *S, int E,
-                      const double *tab, QParams prm, long long *min_key, int *nonfinite,
-                      bool init, hipStream_t st)
+    static void qdata(const double *x, const double *v, const double *e, const PatchDev &pd, int E,
+                      long long ncomp, int node_off, double *mq, double *S, const double *tab,
+                      QParams prm, long long *min_key, int *nonfinite, bool init, hipStream_t st)
     {
+        const dim3 grid((E + NEp - 1) / NEp), block(NEp * Q * Q * Q);
         if (init)
-            hipLaunchKernelGGL((k_qdata<D, Q, true>), dim3(blocks_pt(E)), dim3(NEp * Q * Q * Q), 0,
-                               st, x, v, e, map, ncomp, node_off, mq, S, E, tab, prm, min_key,
-                               nonfinite);
+            hipLaunchKernelGGL((k_qdata<D, Q, true>), grid, block, 0, st, x, v, e, pd.map, pd.perm,
+                               ncomp, node_off, mq, S, E, tab, prm, min_key, nonfinite);
         else
-            hipLaunchKernelGGL((k_qdata<D, Q, false>), dim3(blocks_pt(E)), dim3(NEp * Q * Q * Q),
-                               0, st, x, v, e, map, ncomp, node_off, mq, S, E, tab, prm, min_key,
-                               nonfinite);
+            hipLaunchKernelGGL((k_qdata<D, Q, false>), grid, block, 0, st, x, v, e, pd.map,
+                               pd.perm, ncomp, node_off, mq, S, E, tab, prm, min_key, nonfinite);
     }
-    static int mass_blocks(int E) { return blocks_col(E); }
 };
 
 #define FEPA_PQ_LIST(X) \
@@ -614,14 +735,40 @@ struct Launch {
 
 const KernelSet *fp64_kernels(int p, int Q)
 {
-#define FEPA_ENTRY(P, QQ)                                                                  \
+#define FEPA_ENTRY(P, QQ)                                                                    \
     static const KernelSet ks_##P##_##QQ = {Launch<P + 1, QQ>::force, Launch<P + 1, QQ>::force_t, \
-                                            Launch<P + 1, QQ>::mass, Launch<P + 1, QQ>::qdata,  \
-                                            Launch<P + 1, QQ>::mass_blocks};                   \
+                                            Launch<P + 1, QQ>::mass, Launch<P + 1, QQ>::qdata,   \
+                                            patch_umax(P + 1)};                                  \
     if (p == P && Q == QQ) return &ks_##P##_##QQ;
     FEPA_PQ_LIST(FEPA_ENTRY)
 #undef FEPA_ENTRY
     return nullptr;
+}
+
+void launch_gather_shared(const PatchDev &pd, double *y, long long ncomp, const int *skip,
+                          hipStream_t st)
+{
+    if (pd.n_shared <= 0) return;
+    hipLaunchKernelGGL(k_gather_shared, dim3((pd.n_shared + 255) / 256), dim3(256), 0, st, pd.part,
+                       pd.sh_node, pd.sh_ptr, pd.sh_idx, pd.n_shared, y, ncomp, skip);
+}
+
+void launch_zero_nodes(const int32_t *nodes, int n, double *y, long long ncomp, const int *skip,
+                       hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_zero_nodes, dim3((n + 255) / 256), dim3(256), 0, st, nodes, n, y, ncomp,
+                       skip);
+}
+
+void launch_unpermute_rows(const double *in, const int32_t *perm, long long rows, int len,
+                           double *out, hipStream_t st)
+{
+    long long blocks = (rows * len + 255) / 256;
+    if (blocks > 65535) blocks = 65535;
+    if (blocks < 1) return;
+    hipLaunchKernelGGL(k_unpermute_rows, dim3((unsigned)blocks), dim3(256), 0, st, in, perm, rows,
+                       len, out);
 }
 
 __global__ void k_reset_diag(long long *__restrict__ key, int *__restrict__ flag)

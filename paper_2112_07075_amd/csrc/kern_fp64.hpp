@@ -14,26 +14,47 @@ struct QParams {
     double inv_order;  // 1/p (length scale l = detJ^(1/3) / p)
 };
 
-// Launchers of one (p, Q) instance. Pointers are device pointers already
-// offset to the mesh; ncomp is the component stride of H1 vectors.
+// Device arrays of one mesh's patch plan. Element indices are local to the
+// mesh and in patch order; node ids are global (offset by the mesh's first node).
+struct PatchDev {
+    const int32_t *perm = nullptr;   // patch-order element -> caller element of the mesh
+    const int32_t *map = nullptr;    // [E][D^3] node ids, patch order
+    const uint16_t *slot = nullptr;  // [E][D^3] LDS slot of each element node
+    const int32_t *pn = nullptr;     // distinct nodes of every patch
+    const int32_t *ptab = nullptr;   // [n_patch][6] patch table
+    int n_patch = 0;
+    const int32_t *sh_node = nullptr, *sh_ptr = nullptr, *sh_idx = nullptr;
+    int n_shared = 0;
+    double *part = nullptr;          // [entries][3] shared-node partials
+};
+
+// Launchers of one (p, Q) instance; ncomp is the component stride of H1 vectors.
 struct KernelSet {
-    void (*force)(const double *S, const double *e, const int32_t *map, double *y, int E,
+    void (*force)(const double *S, const double *e, const PatchDev &pd, double *y,
                   long long ncomp, const double *tab, hipStream_t st);
-    void (*force_t)(const double *S, const double *v, const int32_t *map, double *z, int E,
+    void (*force_t)(const double *S, const double *v, const PatchDev &pd, int E, double *z,
                     long long ncomp, const double *tab, hipStream_t st);
-    void (*mass)(const double *mq, const double *x, const int32_t *map, double *y, int E,
-                 long long ncomp, const double *tab, double *part, const int *skip,
+    void (*mass)(const double *mq, const double *x, const PatchDev &pd, double *y,
+                 long long ncomp, const double *tab, double *part_dot, const int *skip,
                  hipStream_t st);
-    void (*qdata)(const double *x, const double *v, const double *e, const int32_t *map,
-                  long long ncomp, int node_off, double *mq, double *S, int E,
-                  const double *tab, QParams prm, long long *min_key, int *nonfinite, bool init,
-                  hipStream_t st);
-    int (*mass_blocks)(int E);  // workgroups of one mass launch (for partial sums)
+    void (*qdata)(const double *x, const double *v, const double *e, const PatchDev &pd, int E,
+                  long long ncomp, int node_off, double *mq, double *S, const double *tab,
+                  QParams prm, long long *min_key, int *nonfinite, bool init, hipStream_t st);
+    int umax;  // distinct-node capacity of a patch for this order
 };
 
 // nullptr when (p, Q) is not instantiated.
 const KernelSet *fp64_kernels(int p, int Q);
 
+// y[c][g] for the shared nodes of a patch plan (after force or mass patches).
+void launch_gather_shared(const PatchDev &pd, double *y, long long ncomp, const int *skip,
+                          hipStream_t st);
+// y[c][g] = 0 for the listed nodes
+void launch_zero_nodes(const int32_t *nodes, int n, double *y, long long ncomp, const int *skip,
+                       hipStream_t st);
+// out[perm[k]][:] = in[k][:]
+void launch_unpermute_rows(const double *in, const int32_t *perm, long long rows, int len,
+                           double *out, hipStream_t st);
 void launch_fill(double *y, long long n, double val, hipStream_t st);
 // *key = INT64_MAX (empty min of ordered detJ keys), *flag = 0; either may be NULL.
 void launch_reset_diag(long long *key, int *flag, hipStream_t st);

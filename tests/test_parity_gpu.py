@@ -303,3 +303,24 @@ def test_full_size_c2_cg(torch_cuda):
     bn = b.cpu().numpy()
     scale = np.abs(bn).max()
     assert np.abs(Mx[:, inner] - bn[:, inner]).max() < 1e-9 * scale
+
+
+def test_unreferenced_node_gets_zero(torch_cuda):
+    # an extra node that no element references: outputs there are 0 (overwrite semantics)
+    c = make_case(2, 2, 4, seed=12)
+    x0 = np.concatenate([c.mesh.x0, np.full((3, 1), 0.5)], axis=1)
+    N1 = c.N + 1
+    ctx = fe.fe_pa_setup(fe.MeshDesc(c.mesh.elem_nodes, dev(torch_cuda, x0), 2, 4))
+    x = dev(torch_cuda, np.concatenate([c.x, np.zeros((3, 1))], axis=1))
+    v = dev(torch_cuda, np.concatenate([c.v, np.ones((3, 1))], axis=1))
+    fe.fe_qdata_update(ctx, x, v, dev(torch_cuda, c.e))
+    y = torch_cuda.full((3, N1), 7.0, dtype=torch_cuda.float64, device="cuda")
+    fe.fe_force_mult(ctx, None, y)
+    ym = torch_cuda.full((3, N1), 7.0, dtype=torch_cuda.float64, device="cuda")
+    fe.fe_mass_mult(ctx, v, ym)
+    y, ym = y.cpu().numpy(), ym.cpu().numpy()
+    assert np.all(y[:, -1] == 0.0) and np.all(ym[:, -1] == 0.0)
+    qd = oracle_qdata(c)
+    M = c.mesh.elem_nodes
+    assert rel_cw(y[:, :-1], O.force_mult(M, 2, 4, c.N, qd["S"]),
+                  O.force_mult(M, 2, 4, c.N, qd["S"], absmode=True)) < TOL
