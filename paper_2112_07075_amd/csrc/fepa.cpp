@@ -332,7 +332,8 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         ctx->plan_bufs.push_back(d);
         wb += (long long)(bytes ? bytes : 4);
         *dst = d;
-        if (bytes && hipMemcpy(d, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return FE_EDEVICE;
+        if (src && bytes && hipMemcpy(d, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+            return FE_EDEVICE;
         return FE_OK;
     };
     for (int m = 0; m < n_mesh; ++m) {
