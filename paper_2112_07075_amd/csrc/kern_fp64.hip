@@ -40,10 +40,6 @@ __host__ __device__ constexpr int force_ne(int D, int Q)
 {
     return fit_ne(Q, 8 * (3 * D * Q * Q + 2 * D * D * Q), 24 * patch_umax(D));
 }
-__host__ __device__ constexpr int mass_ne(int D, int Q)
-{
-    return fit_ne(Q, 8 * (2 * D * D * Q + D * Q * Q) + 4 * D * D * D, 48 * patch_umax(D) + 256);
-}
 
 // One row of the patch table: first element, element count, offset of the
 // distinct-node list, distinct nodes U, private nodes P, shared-partial offset.
@@ -118,7 +114,14 @@ k_force(const double *__restrict__ S, const double *__restrict__ e,
         const int idx = base + le;
         const bool act = idx < pr.cnt;
         const long long el = pr.eb + (act ? idx : 0);
-        const double *__restrict__ Se = S + el * 9 * Q3;
+        // the element's whole S column first: 9*Q independent streaming loads in flight
+        const double *__restrict__ Se = S + el * 9 * Q3 + t;
+        double sv[9][Q];
+#pragma unroll
+        for (int cd = 0; cd < 9; ++cd)
+#pragma unroll
+            for (int qz = 0; qz < Q; ++qz)
+                sv[cd][qz] = act ? __builtin_nontemporal_load(Se + cd * Q3 + qz * QQ) : 0.0;
         int sl[D];
 #pragma unroll
         for (int iz = 0; iz < D; ++iz)
@@ -151,16 +154,16 @@ k_force(const double *__restrict__ S, const double *__restrict__ e,
                 eq[qz] = s;
             }
         }
-#pragma unroll 1
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
             double a0[D], a1[D], a2[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) a0[i] = a1[i] = a2[i] = 0.0;
 #pragma unroll
             for (int qz = 0; qz < Q; ++qz) {
-                const double s0 = act ? Se[(c * 3 + 0) * Q3 + qz * QQ + t] * eq[qz] : 0.0;
-                const double s1 = act ? Se[(c * 3 + 1) * Q3 + qz * QQ + t] * eq[qz] : 0.0;
-                const double s2 = act ? Se[(c * 3 + 2) * Q3 + qz * QQ + t] * eq[qz] : 0.0;
+                const double s0 = sv[c * 3 + 0][qz] * eq[qz];
+                const double s1 = sv[c * 3 + 1][qz] * eq[qz];
+                const double s2 = sv[c * 3 + 2][qz] * eq[qz];
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
                     const double b = tab[T::B + qz * D + iz], g = tab[T::G + qz * D + iz];
@@ -207,30 +210,38 @@ k_force(const double *__restrict__ S, const double *__restrict__ e,
 }
 
 // ---------------------------------------------------------- force^T F^T v
-// z[E][j] = sum_q phi_j(q) sum_{c,d} S[c][d](q) (grad_xi v_c)_d(q); elements in patch
-// order, rows of z in caller order.
-template <int D, int Q>
-__global__ void __launch_bounds__(col_ne(Q) * Q * Q)
-k_force_t(const double *__restrict__ S, const double *__restrict__ v,
-          const int32_t *__restrict__ map, const int32_t *__restrict__ perm,
-          double *__restrict__ z, int E, long long ncomp, const double *__restrict__ tab)
+// z[E][j] = sum_q phi_j(q) sum_{c,d} S[c][d](q) (grad_xi v_c)_d(q), one patch per
+// workgroup: the patch's distinct nodes of v are read once into LDS; rows of z
+// are written in caller element order.
+__host__ __device__ constexpr int force_t_ne(int D, int Q)
 {
-    constexpr int NE = col_ne(Q), DL = D - 1, QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D;
-    constexpr int DL3 = DL * DL * DL;
+    return fit_ne(Q, 8 * (2 * D * D * Q + (D - 1) * Q * Q + (D - 1) * (D - 1) * Q) + 4 * D * D * D,
+                  24 * patch_umax(D));
+}
+
+template <int D, int Q>
+__global__ void __launch_bounds__(force_t_ne(D, Q) * Q * Q)
+k_force_t(const double *__restrict__ S, const double *__restrict__ v,
+          const int32_t *__restrict__ perm, const uint16_t *__restrict__ slot,
+          const int32_t *__restrict__ pn, const int32_t *__restrict__ ptab,
+          double *__restrict__ z, long long ncomp, const double *__restrict__ tab)
+{
+    constexpr int NE = force_t_ne(D, Q), UMAX = patch_umax(D);
+    constexpr int DL = D - 1, QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D, DL3 = DL * DL * DL;
     using T = Tab<D, Q>;
-    __shared__ double sU[NE][3][D3];
+    __shared__ double vs[3 * UMAX];
+    __shared__ int sSl[NE][D3];
     __shared__ double sX[NE][2][D][D * Q];
     __shared__ double sT[NE][DL][QQ];
     __shared__ double sT2[NE][DL][DL * Q];
 
     const int tid = threadIdx.x, le = tid / QQ, t = tid % QQ, qx = t % Q, qy = t / Q;
-    const long long el = (long long)xcd_block(blockIdx.x, gridDim.x) * NE + le;
-    const bool act = el < E;
-    const double *__restrict__ Se = S + (act ? el : 0) * 9 * Q3;
-
-    for (int k = t; k < 3 * D3; k += QQ) {
-        const int c = k / D3, i = k % D3;
-        sU[le][c][i] = act ? v[c * ncomp + map[el * D3 + i]] : 0.0;
+    const PatchRow pr = load_patch(ptab, xcd_block(blockIdx.x, gridDim.x));
+    for (int u = tid; u < pr.U; u += blockDim.x) {
+        const long long g = pn[pr.pno + u];
+        vs[3 * u] = v[g];
+        vs[3 * u + 1] = v[ncomp + g];
+        vs[3 * u + 2] = v[2 * ncomp + g];
     }
     double rBx[D], rGx[D], rBy[D], rGy[D];
 #pragma unroll
@@ -240,98 +251,114 @@ k_force_t(const double *__restrict__ S, const double *__restrict__ v,
         rBy[i] = tab[T::B + qy * D + i];
         rGy[i] = tab[T::G + qy * D + i];
     }
-    __syncthreads();
-
-    double s[Q];
-#pragma unroll
-    for (int k = 0; k < Q; ++k) s[k] = 0.0;
 
 #pragma unroll 1
-    for (int c = 0; c < 3; ++c) {
-        // x-stage: thread (qx, iy = qy)
-        if (qy < D) {
+    for (int base = 0; base < pr.cnt; base += NE) {
+        const int idx = base + le;
+        const bool act = idx < pr.cnt;
+        const long long el = pr.eb + (act ? idx : 0);
+        const double *__restrict__ Se = S + el * 9 * Q3 + t;
+        double sv[9][Q];
 #pragma unroll
-            for (int iz = 0; iz < D; ++iz) {
-                double ub = 0.0, ug = 0.0;
+        for (int cd = 0; cd < 9; ++cd)
 #pragma unroll
-                for (int ix = 0; ix < D; ++ix) {
-                    const double u = sU[le][c][(iz * D + qy) * D + ix];
-                    ub += rBx[ix] * u;
-                    ug += rGx[ix] * u;
+            for (int qz = 0; qz < Q; ++qz)
+                sv[cd][qz] = act ? __builtin_nontemporal_load(Se + cd * Q3 + qz * QQ) : 0.0;
+        for (int i = t; i < D3; i += QQ) sSl[le][i] = act ? slot[el * D3 + i] : 0;
+        __syncthreads();
+        double s[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) s[k] = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            // x-stage: thread (qx, iy = qy)
+            if (qy < D) {
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) {
+                    double ub = 0.0, ug = 0.0;
+#pragma unroll
+                    for (int ix = 0; ix < D; ++ix) {
+                        const double u = vs[3 * sSl[le][(iz * D + qy) * D + ix] + c];
+                        ub += rBx[ix] * u;
+                        ug += rGx[ix] * u;
+                    }
+                    sX[le][0][iz][qy * Q + qx] = ub;
+                    sX[le][1][iz][qy * Q + qx] = ug;
                 }
-                sX[le][0][iz][qy * Q + qx] = ub;
-                sX[le][1][iz][qy * Q + qx] = ug;
             }
-        }
-        __syncthreads();
-        // y-stage into registers: thread (qx, qy)
-        double vx[D], vy[D], vz[D];
-#pragma unroll
-        for (int iz = 0; iz < D; ++iz) {
-            double a = 0.0, b = 0.0, cc = 0.0;
-#pragma unroll
-            for (int iy = 0; iy < D; ++iy) {
-                const double ub = sX[le][0][iz][iy * Q + qx], ug = sX[le][1][iz][iy * Q + qx];
-                a += rBy[iy] * ug;
-                b += rGy[iy] * ub;
-                cc += rBy[iy] * ub;
-            }
-            vx[iz] = a;
-            vy[iz] = b;
-            vz[iz] = cc;
-        }
-        // z-stage and the pointwise S : grad v
-#pragma unroll
-        for (int qz = 0; qz < Q; ++qz) {
-            double dx = 0.0, dy = 0.0, dz = 0.0;
+            __syncthreads();
+            // y-stage into registers, then z-stage and the pointwise S : grad v
+            double vx[D], vy[D], vz[D];
 #pragma unroll
             for (int iz = 0; iz < D; ++iz) {
-                const double bb = tab[T::B + qz * D + iz], gg = tab[T::G + qz * D + iz];
-                dx += bb * vx[iz];
-                dy += bb * vy[iz];
-                dz += gg * vz[iz];
+                double a = 0.0, b = 0.0, cc = 0.0;
+#pragma unroll
+                for (int iy = 0; iy < D; ++iy) {
+                    const double ub = sX[le][0][iz][iy * Q + qx], ug = sX[le][1][iz][iy * Q + qx];
+                    a += rBy[iy] * ug;
+                    b += rGy[iy] * ub;
+                    cc += rBy[iy] * ub;
+                }
+                vx[iz] = a;
+                vy[iz] = b;
+                vz[iz] = cc;
             }
-            if (act)
-                s[qz] += Se[(c * 3 + 0) * Q3 + qz * QQ + t] * dx +
-                         Se[(c * 3 + 1) * Q3 + qz * QQ + t] * dy +
-                         Se[(c * 3 + 2) * Q3 + qz * QQ + t] * dz;
+            __syncthreads();  // sX is rewritten by the next component
+#pragma unroll
+            for (int qz = 0; qz < Q; ++qz) {
+                double dx = 0.0, dy = 0.0, dz = 0.0;
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) {
+                    const double bb = tab[T::B + qz * D + iz], gg = tab[T::G + qz * D + iz];
+                    dx += bb * vx[iz];
+                    dy += bb * vy[iz];
+                    dz += gg * vz[iz];
+                }
+                s[qz] += sv[c * 3 + 0][qz] * dx + sv[c * 3 + 1][qz] * dy + sv[c * 3 + 2][qz] * dz;
+            }
+        }
+        // L2 test functions: B_l^T in z (registers), y and x (LDS)
+#pragma unroll
+        for (int jz = 0; jz < DL; ++jz) {
+            double a = 0.0;
+#pragma unroll
+            for (int qz = 0; qz < Q; ++qz) a += tab[T::BL + qz * DL + jz] * s[qz];
+            sT[le][jz][t] = a;
         }
         __syncthreads();
-    }
-    // L2 test functions: B_l^T in z (registers), y and x (LDS)
+        if (qy < DL) {
 #pragma unroll
-    for (int jz = 0; jz < DL; ++jz) {
-        double a = 0.0;
+            for (int jz = 0; jz < DL; ++jz) {
+                double a = 0.0;
 #pragma unroll
-        for (int qz = 0; qz < Q; ++qz) a += tab[T::BL + qz * DL + jz] * s[qz];
-        sT[le][jz][t] = a;
-    }
-    __syncthreads();
-    if (qy < DL) {
-#pragma unroll
-        for (int jz = 0; jz < DL; ++jz) {
-            double a = 0.0;
-#pragma unroll
-            for (int k = 0; k < Q; ++k) a += tab[T::BL + k * DL + qy] * sT[le][jz][k * Q + qx];
-            sT2[le][jz][qy * Q + qx] = a;
+                for (int k = 0; k < Q; ++k) a += tab[T::BL + k * DL + qy] * sT[le][jz][k * Q + qx];
+                sT2[le][jz][qy * Q + qx] = a;
+            }
         }
-    }
-    __syncthreads();
-    if (act && qx < DL && qy < DL) {
+        __syncthreads();
+        if (act && qx < DL && qy < DL) {
+            double *__restrict__ zr = z + (long long)perm[el] * DL3;
 #pragma unroll
-        for (int jz = 0; jz < DL; ++jz) {
-            double a = 0.0;
+            for (int jz = 0; jz < DL; ++jz) {
+                double a = 0.0;
 #pragma unroll
-            for (int k = 0; k < Q; ++k) a += tab[T::BL + k * DL + qx] * sT2[le][jz][qy * Q + k];
-            z[(long long)perm[el] * DL3 + (jz * DL + qy) * DL + qx] = a;
+                for (int k = 0; k < Q; ++k) a += tab[T::BL + k * DL + qx] * sT2[le][jz][qy * Q + k];
+                zr[(jz * DL + qy) * DL + qx] = a;
+            }
         }
     }
 }
 
 // -------------------------------------------------------------- mass M_v x
-// y_c = R^T B^T diag(m_q) B R x_c for c = 0..2, one patch per workgroup. The
-// patch's distinct nodes are read once into LDS. With DOT, the workgroup also
-// writes sum_E x_E^T (M_E x_E) (= x^T M x over its elements) to part_dot.
+// y_c = R^T B^T diag(m_q) B R x_c for c = 0..2, one patch per workgroup, the
+// three components side by side in every stage. The patch's distinct nodes are
+// read once into LDS. With DOT, the workgroup also writes
+// sum_E x_E^T (M_E x_E) (= x^T M x over its elements) to part_dot.
+__host__ __device__ constexpr int mass_ne(int D, int Q)
+{
+    return fit_ne(Q, 8 * 3 * (D * D * Q + D * Q * Q) + 4 * D * D * D, 48 * patch_umax(D) + 256);
+}
+
 template <int D, int Q, bool DOT>
 __global__ void __launch_bounds__(mass_ne(D, Q) * Q * Q)
 k_mass(const double *__restrict__ mq, const double *__restrict__ x,
@@ -347,9 +374,8 @@ k_mass(const double *__restrict__ mq, const double *__restrict__ x,
     __shared__ double acc[3 * UMAX];
     __shared__ double xs[3 * UMAX];
     __shared__ int sSl[NE][D3];
-    __shared__ double sX[NE][D][D * Q];
-    __shared__ double sZ[NE][D][QQ];
-    __shared__ double sY[NE][D][D * Q];
+    __shared__ double sX[NE][3][D][D * Q];  // x-stage out, then y^T out
+    __shared__ double sZ[NE][3][D][QQ];
     __shared__ double sred[8];
 
     const int tid = threadIdx.x, le = tid / QQ, t = tid % QQ, qx = t % Q, qy = t / Q;
@@ -379,30 +405,39 @@ k_mass(const double *__restrict__ mq, const double *__restrict__ x,
         const int idx = base + le;
         const bool act = idx < pr.cnt;
         const long long el = pr.eb + (act ? idx : 0);
-        for (int i = t; i < D3; i += QQ) sSl[le][i] = act ? slot[el * D3 + i] : 0;
         double m[Q];
 #pragma unroll
-        for (int k = 0; k < Q; ++k) m[k] = act ? mq[el * Q3 + k * QQ + t] : 0.0;
+        for (int k = 0; k < Q; ++k)
+            m[k] = act ? __builtin_nontemporal_load(mq + el * Q3 + k * QQ + t) : 0.0;
+        for (int i = t; i < D3; i += QQ) sSl[le][i] = act ? slot[el * D3 + i] : 0;
         __syncthreads();
-#pragma unroll 1
-        for (int c = 0; c < 3; ++c) {
-            if (qy < D) {
+        // x-stage: thread (qx, iy = qy)
+        if (qy < D) {
 #pragma unroll
-                for (int iz = 0; iz < D; ++iz) {
-                    double a = 0.0;
+            for (int iz = 0; iz < D; ++iz) {
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #pragma unroll
-                    for (int ix = 0; ix < D; ++ix)
-                        a += rBx[ix] * xs[3 * sSl[le][(iz * D + qy) * D + ix] + c];
-                    sX[le][iz][qy * Q + qx] = a;
+                for (int ix = 0; ix < D; ++ix) {
+                    const int sidx = 3 * sSl[le][(iz * D + qy) * D + ix];
+                    a0 += rBx[ix] * xs[sidx];
+                    a1 += rBx[ix] * xs[sidx + 1];
+                    a2 += rBx[ix] * xs[sidx + 2];
                 }
+                sX[le][0][iz][qy * Q + qx] = a0;
+                sX[le][1][iz][qy * Q + qx] = a1;
+                sX[le][2][iz][qy * Q + qx] = a2;
             }
-            __syncthreads();
+        }
+        __syncthreads();
+        // y-stage, z-stage, weights, z^T: registers of thread (qx, qy)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
             double w[D];
 #pragma unroll
             for (int iz = 0; iz < D; ++iz) {
                 double a = 0.0;
 #pragma unroll
-                for (int iy = 0; iy < D; ++iy) a += rBy[iy] * sX[le][iz][iy * Q + qx];
+                for (int iy = 0; iy < D; ++iy) a += rBy[iy] * sX[le][c][iz][iy * Q + qx];
                 w[iz] = a;
             }
             double a[D];
@@ -418,33 +453,39 @@ k_mass(const double *__restrict__ mq, const double *__restrict__ x,
                 for (int iz = 0; iz < D; ++iz) a[iz] += tab[T::B + qz * D + iz] * u;
             }
 #pragma unroll
-            for (int iz = 0; iz < D; ++iz) sZ[le][iz][t] = a[iz];
-            __syncthreads();
-            if (qy < D) {
+            for (int iz = 0; iz < D; ++iz) sZ[le][c][iz][t] = a[iz];
+        }
+        __syncthreads();
+        // y^T: thread (qx, iy = qy), into sX
+        if (qy < D) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
                     double b = 0.0;
 #pragma unroll
-                    for (int k = 0; k < Q; ++k) b += cBy[k] * sZ[le][iz][k * Q + qx];
-                    sY[le][iz][qy * Q + qx] = b;
+                    for (int k = 0; k < Q; ++k) b += cBy[k] * sZ[le][c][iz][k * Q + qx];
+                    sX[le][c][iz][qy * Q + qx] = b;
                 }
-            }
-            __syncthreads();
-            if (act && qx < D && qy < D) {
+        }
+        __syncthreads();
+        // x^T: thread (ix = qx, iy = qy), summed into the patch slots
+        if (act && qx < D && qy < D) {
 #pragma unroll
-                for (int iz = 0; iz < D; ++iz) {
+            for (int iz = 0; iz < D; ++iz) {
+                const int sidx = 3 * sSl[le][(iz * D + qy) * D + qx];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
                     double r = 0.0;
 #pragma unroll
-                    for (int k = 0; k < Q; ++k) r += cBx[k] * sY[le][iz][qy * Q + k];
-                    const int s = sSl[le][(iz * D + qy) * D + qx];
-                    atomicAdd(&acc[3 * s + c], r);
-                    if (DOT) dot += r * xs[3 * s + c];
+                    for (int k = 0; k < Q; ++k) r += cBx[k] * sX[le][c][iz][qy * Q + k];
+                    atomicAdd(&acc[sidx + c], r);
+                    if (DOT) dot += r * xs[sidx + c];
                 }
             }
         }
-        __syncthreads();  // sSl is rewritten by the next pass
+        __syncthreads();  // sSl and sX are rewritten by the next pass
     }
-    __syncthreads();
     patch_write<UMAX>(acc, pr, pn, y, part, ncomp);
     if (DOT) {
         for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off);
@@ -700,9 +741,9 @@ struct Launch {
     static void force_t(const double *S, const double *v, const PatchDev &pd, int E, double *z,
                         long long ncomp, const double *tab, hipStream_t st)
     {
-        constexpr int NE = col_ne(Q);
-        hipLaunchKernelGGL((k_force_t<D, Q>), dim3((E + NE - 1) / NE), dim3(NE * Q * Q), 0, st, S,
-                           v, pd.map, pd.perm, z, E, ncomp, tab);
+        (void)E;
+        hipLaunchKernelGGL((k_force_t<D, Q>), dim3(pd.n_patch), dim3(force_t_ne(D, Q) * Q * Q), 0,
+                           st, S, v, pd.perm, pd.slot, pd.pn, pd.ptab, z, ncomp, tab);
     }
     static void mass(const double *mq, const double *x, const PatchDev &pd, double *y,
                      long long ncomp, const double *tab, double *part_dot, const int *skip,
