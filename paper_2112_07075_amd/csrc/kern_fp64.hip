@@ -30,15 +30,48 @@ __global__ void k_fill(double *__restrict__ y, long long n, double val)
 // per pass (NE) are chosen so that the static LDS of a workgroup stays below
 // 60 KiB: at most two workgroups' worth of LDS fit a 160 KiB CU at once.
 __host__ __device__ constexpr int patch_umax(int D) { return D == 4 ? 512 : 768; }
-__host__ __device__ constexpr int fit_ne(int Q, int per_elem, int fixed)
+
+
+// Elements whose threads sit in one wave exchange data through LDS with only a
+// wave-level fence: DS instructions of a wave execute in order, so a wave never
+// waits for the other waves of its workgroup inside a patch.
+__device__ __forceinline__ void wave_sync()
 {
-    int ne = col_ne(Q);
-    while (ne > 1 && fixed + ne * per_elem > 60 * 1024) --ne;
-    return ne;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-__host__ __device__ constexpr int force_ne(int D, int Q)
+
+// Wave-local element layout: 64/Q^2 elements per wave, 4 waves per workgroup.
+__host__ __device__ constexpr int wave_ne(int Q) { return 64 / (Q * Q); }
+struct Lane {
+    int le;      // element slot in the workgroup (valid lanes only)
+    int t;       // point column qx + Q*qy
+    bool valid;  // lane carries an element column
+};
+// Idle lanes (64 not a multiple of Q^2) point at a spare slot NE whose LDS
+// scratch nobody reads.
+template <int Q, int NE>
+__device__ __forceinline__ Lane lane_map()
 {
-    return fit_ne(Q, 8 * (3 * D * Q * Q + 2 * D * D * Q), 24 * patch_umax(D));
+    constexpr int NW = wave_ne(Q), QQ = Q * Q;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    Lane L;
+    L.valid = lane < NW * QQ;
+    L.le = L.valid ? w * NW + lane / QQ : NE;
+    L.t = L.valid ? lane % QQ : 0;
+    return L;
+}
+__host__ __device__ constexpr int fit_waves(int Q, int per_elem, int fixed)
+{
+    int w = 4;
+    while (w > 1 && fixed + (w * wave_ne(Q) + 1) * per_elem > 60 * 1024) --w;
+    return w;
+}
+
+__host__ __device__ constexpr int force_waves(int D, int Q)
+{
+    return fit_waves(Q, 8 * (3 * D * Q * Q + 2 * D * D * Q), 24 * patch_umax(D));
 }
 
 // One row of the patch table: first element, element count, offset of the
@@ -81,21 +114,22 @@ __device__ __forceinline__ void patch_write(const double *acc, const PatchRow &p
 // derivative terms fused: z-stage -> (B, B, G), y-stage -> (B | G + B),
 // x-stage -> (G + B); element results are summed into the patch's LDS slots.
 template <int D, int Q, bool ONE>
-__global__ void __launch_bounds__(force_ne(D, Q) * Q * Q)
+__global__ void __launch_bounds__(force_waves(D, Q) * 64)
 k_force(const double *__restrict__ S, const double *__restrict__ e,
         const int32_t *__restrict__ perm, const uint16_t *__restrict__ slot,
         const int32_t *__restrict__ pn, const int32_t *__restrict__ ptab,
         double *__restrict__ y, double *__restrict__ part, long long ncomp,
         const double *__restrict__ tab)
 {
-    constexpr int NE = force_ne(D, Q), UMAX = patch_umax(D);
+    constexpr int NE = force_waves(D, Q) * wave_ne(Q), UMAX = patch_umax(D);
     constexpr int DL = D - 1, QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D, DL3 = DL * DL * DL;
     using T = Tab<D, Q>;
     __shared__ double acc[3 * UMAX];
-    __shared__ double sA[NE][3][D][QQ];
-    __shared__ double sC[NE][2][D][D * Q];
+    __shared__ double sA[NE + 1][3][D][QQ];
+    __shared__ double sC[NE + 1][2][D][D * Q];
 
-    const int tid = threadIdx.x, le = tid / QQ, t = tid % QQ, qx = t % Q, qy = t / Q;
+    const Lane L = lane_map<Q, NE>();
+    const int tid = threadIdx.x, le = L.le, t = L.t, qx = t % Q, qy = t / Q;
     const PatchRow pr = load_patch(ptab, xcd_block(blockIdx.x, gridDim.x));
     for (int k = tid; k < 3 * pr.U; k += blockDim.x) acc[k] = 0.0;
 
@@ -112,7 +146,7 @@ k_force(const double *__restrict__ S, const double *__restrict__ e,
 #pragma unroll 1
     for (int base = 0; base < pr.cnt; base += NE) {
         const int idx = base + le;
-        const bool act = idx < pr.cnt;
+        const bool act = L.valid && idx < pr.cnt;
         const long long el = pr.eb + (act ? idx : 0);
         // the element's whole S column first: 9*Q independent streaming loads in flight
         const double *__restrict__ Se = S + el * 9 * Q3 + t;
@@ -178,7 +212,7 @@ k_force(const double *__restrict__ S, const double *__restrict__ e,
                 sA[le][1][iz][t] = a1[iz];
                 sA[le][2][iz][t] = a2[iz];
             }
-            __syncthreads();
+            wave_sync();
             if (qy < D) {
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
@@ -192,7 +226,7 @@ k_force(const double *__restrict__ S, const double *__restrict__ e,
                     sC[le][1][iz][qy * Q + qx] = c1;
                 }
             }
-            __syncthreads();
+            wave_sync();
             if (act && qx < D && qy < D) {
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
@@ -213,29 +247,30 @@ k_force(const double *__restrict__ S, const double *__restrict__ e,
 // z[E][j] = sum_q phi_j(q) sum_{c,d} S[c][d](q) (grad_xi v_c)_d(q), one patch per
 // workgroup: the patch's distinct nodes of v are read once into LDS; rows of z
 // are written in caller element order.
-__host__ __device__ constexpr int force_t_ne(int D, int Q)
+__host__ __device__ constexpr int force_t_waves(int D, int Q)
 {
-    return fit_ne(Q, 8 * (2 * D * D * Q + (D - 1) * Q * Q + (D - 1) * (D - 1) * Q) + 4 * D * D * D,
-                  24 * patch_umax(D));
+    return fit_waves(Q, 8 * (2 * D * D * Q + (D - 1) * Q * Q + (D - 1) * (D - 1) * Q) + 4 * D * D * D,
+                     24 * patch_umax(D));
 }
 
 template <int D, int Q>
-__global__ void __launch_bounds__(force_t_ne(D, Q) * Q * Q)
+__global__ void __launch_bounds__(force_t_waves(D, Q) * 64)
 k_force_t(const double *__restrict__ S, const double *__restrict__ v,
           const int32_t *__restrict__ perm, const uint16_t *__restrict__ slot,
           const int32_t *__restrict__ pn, const int32_t *__restrict__ ptab,
           double *__restrict__ z, long long ncomp, const double *__restrict__ tab)
 {
-    constexpr int NE = force_t_ne(D, Q), UMAX = patch_umax(D);
+    constexpr int NE = force_t_waves(D, Q) * wave_ne(Q), UMAX = patch_umax(D);
     constexpr int DL = D - 1, QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D, DL3 = DL * DL * DL;
     using T = Tab<D, Q>;
     __shared__ double vs[3 * UMAX];
-    __shared__ int sSl[NE][D3];
-    __shared__ double sX[NE][2][D][D * Q];
-    __shared__ double sT[NE][DL][QQ];
-    __shared__ double sT2[NE][DL][DL * Q];
+    __shared__ int sSl[NE + 1][D3];
+    __shared__ double sX[NE + 1][2][D][D * Q];
+    __shared__ double sT[NE + 1][DL][QQ];
+    __shared__ double sT2[NE + 1][DL][DL * Q];
 
-    const int tid = threadIdx.x, le = tid / QQ, t = tid % QQ, qx = t % Q, qy = t / Q;
+    const Lane L = lane_map<Q, NE>();
+    const int tid = threadIdx.x, le = L.le, t = L.t, qx = t % Q, qy = t / Q;
     const PatchRow pr = load_patch(ptab, xcd_block(blockIdx.x, gridDim.x));
     for (int u = tid; u < pr.U; u += blockDim.x) {
         const long long g = pn[pr.pno + u];
@@ -252,10 +287,12 @@ k_force_t(const double *__restrict__ S, const double *__restrict__ v,
         rGy[i] = tab[T::G + qy * D + i];
     }
 
+    __syncthreads();
+
 #pragma unroll 1
     for (int base = 0; base < pr.cnt; base += NE) {
         const int idx = base + le;
-        const bool act = idx < pr.cnt;
+        const bool act = L.valid && idx < pr.cnt;
         const long long el = pr.eb + (act ? idx : 0);
         const double *__restrict__ Se = S + el * 9 * Q3 + t;
         double sv[9][Q];
@@ -265,7 +302,7 @@ k_force_t(const double *__restrict__ S, const double *__restrict__ v,
             for (int qz = 0; qz < Q; ++qz)
                 sv[cd][qz] = act ? __builtin_nontemporal_load(Se + cd * Q3 + qz * QQ) : 0.0;
         for (int i = t; i < D3; i += QQ) sSl[le][i] = act ? slot[el * D3 + i] : 0;
-        __syncthreads();
+        wave_sync();
         double s[Q];
 #pragma unroll
         for (int k = 0; k < Q; ++k) s[k] = 0.0;
@@ -286,7 +323,7 @@ k_force_t(const double *__restrict__ S, const double *__restrict__ v,
                     sX[le][1][iz][qy * Q + qx] = ug;
                 }
             }
-            __syncthreads();
+            wave_sync();
             // y-stage into registers, then z-stage and the pointwise S : grad v
             double vx[D], vy[D], vz[D];
 #pragma unroll
@@ -303,7 +340,7 @@ k_force_t(const double *__restrict__ S, const double *__restrict__ v,
                 vy[iz] = b;
                 vz[iz] = cc;
             }
-            __syncthreads();  // sX is rewritten by the next component
+            wave_sync();  // sX is rewritten by the next component
 #pragma unroll
             for (int qz = 0; qz < Q; ++qz) {
                 double dx = 0.0, dy = 0.0, dz = 0.0;
@@ -325,7 +362,7 @@ k_force_t(const double *__restrict__ S, const double *__restrict__ v,
             for (int qz = 0; qz < Q; ++qz) a += tab[T::BL + qz * DL + jz] * s[qz];
             sT[le][jz][t] = a;
         }
-        __syncthreads();
+        wave_sync();
         if (qy < DL) {
 #pragma unroll
             for (int jz = 0; jz < DL; ++jz) {
@@ -335,7 +372,7 @@ k_force_t(const double *__restrict__ S, const double *__restrict__ v,
                 sT2[le][jz][qy * Q + qx] = a;
             }
         }
-        __syncthreads();
+        wave_sync();
         if (act && qx < DL && qy < DL) {
             double *__restrict__ zr = z + (long long)perm[el] * DL3;
 #pragma unroll
@@ -350,43 +387,40 @@ k_force_t(const double *__restrict__ S, const double *__restrict__ v,
 }
 
 // -------------------------------------------------------------- mass M_v x
-// y_c = R^T B^T diag(m_q) B R x_c for c = 0..2, one patch per workgroup, the
-// three components side by side in every stage. The patch's distinct nodes are
-// read once into LDS. With DOT, the workgroup also writes
-// sum_E x_E^T (M_E x_E) (= x^T M x over its elements) to part_dot.
-__host__ __device__ constexpr int mass_ne(int D, int Q)
+// y_c = R^T B^T diag(m_q) B R x_c for c = 0..2, one patch per workgroup; each
+// wave works through its own elements (per-element node gather, one component
+// at a time) and sums into the patch's LDS slots. With DOT, the workgroup also
+// writes sum_E x_E^T (M_E x_E) (= x^T M x over its elements) to part_dot.
+__host__ __device__ constexpr int mass_waves(int D, int Q)
 {
-    return fit_ne(Q, 8 * 3 * (D * D * Q + D * Q * Q) + 4 * D * D * D, 48 * patch_umax(D) + 256);
+    return fit_waves(Q, 8 * (3 * D * D * D + 2 * D * D * Q + D * Q * Q) + 4 * D * D * D,
+                     24 * patch_umax(D) + 256);
 }
 
 template <int D, int Q, bool DOT>
-__global__ void __launch_bounds__(mass_ne(D, Q) * Q * Q)
+__global__ void __launch_bounds__(mass_waves(D, Q) * 64)
 k_mass(const double *__restrict__ mq, const double *__restrict__ x,
-       const uint16_t *__restrict__ slot, const int32_t *__restrict__ pn,
-       const int32_t *__restrict__ ptab, double *__restrict__ y, double *__restrict__ part,
-       long long ncomp, const double *__restrict__ tab, double *__restrict__ part_dot,
+       const int32_t *__restrict__ map, const uint16_t *__restrict__ slot,
+       const int32_t *__restrict__ pn, const int32_t *__restrict__ ptab,
+       double *__restrict__ y, double *__restrict__ part, long long ncomp,
+       const double *__restrict__ tab, double *__restrict__ part_dot,
        const int *__restrict__ skip)
 {
-    constexpr int NE = mass_ne(D, Q), UMAX = patch_umax(D);
+    constexpr int NE = mass_waves(D, Q) * wave_ne(Q), UMAX = patch_umax(D);
     constexpr int QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D;
     using T = Tab<D, Q>;
     if (skip && *skip) return;  // a finished CG solve
     __shared__ double acc[3 * UMAX];
-    __shared__ double xs[3 * UMAX];
-    __shared__ int sSl[NE][D3];
-    __shared__ double sX[NE][3][D][D * Q];  // x-stage out, then y^T out
-    __shared__ double sZ[NE][3][D][QQ];
+    __shared__ double sU[NE + 1][3][D3];
+    __shared__ int sSl[NE + 1][D3];
+    __shared__ double sX[NE + 1][D][D * Q];  // x-stage out, then y^T out
+    __shared__ double sZ[NE + 1][D][QQ];
     __shared__ double sred[8];
 
-    const int tid = threadIdx.x, le = tid / QQ, t = tid % QQ, qx = t % Q, qy = t / Q;
+    const Lane L = lane_map<Q, NE>();
+    const int tid = threadIdx.x, le = L.le, t = L.t, qx = t % Q, qy = t / Q;
     const PatchRow pr = load_patch(ptab, xcd_block(blockIdx.x, gridDim.x));
-    for (int u = tid; u < pr.U; u += blockDim.x) {
-        const long long g = pn[pr.pno + u];
-        xs[3 * u] = x[g];
-        xs[3 * u + 1] = x[ncomp + g];
-        xs[3 * u + 2] = x[2 * ncomp + g];
-        acc[3 * u] = acc[3 * u + 1] = acc[3 * u + 2] = 0.0;
-    }
+    for (int k = tid; k < 3 * pr.U; k += blockDim.x) acc[k] = 0.0;
     double rBx[D], rBy[D], cBy[Q], cBx[Q];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -399,45 +433,45 @@ k_mass(const double *__restrict__ mq, const double *__restrict__ x,
         cBx[k] = qx < D ? tab[T::B + k * D + qx] : 0.0;
     }
     double dot = 0.0;
+    __syncthreads();
 
 #pragma unroll 1
     for (int base = 0; base < pr.cnt; base += NE) {
         const int idx = base + le;
-        const bool act = idx < pr.cnt;
+        const bool act = L.valid && idx < pr.cnt;
         const long long el = pr.eb + (act ? idx : 0);
         double m[Q];
 #pragma unroll
         for (int k = 0; k < Q; ++k)
             m[k] = act ? __builtin_nontemporal_load(mq + el * Q3 + k * QQ + t) : 0.0;
-        for (int i = t; i < D3; i += QQ) sSl[le][i] = act ? slot[el * D3 + i] : 0;
-        __syncthreads();
-        // x-stage: thread (qx, iy = qy)
-        if (qy < D) {
-#pragma unroll
-            for (int iz = 0; iz < D; ++iz) {
-                double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-#pragma unroll
-                for (int ix = 0; ix < D; ++ix) {
-                    const int sidx = 3 * sSl[le][(iz * D + qy) * D + ix];
-                    a0 += rBx[ix] * xs[sidx];
-                    a1 += rBx[ix] * xs[sidx + 1];
-                    a2 += rBx[ix] * xs[sidx + 2];
-                }
-                sX[le][0][iz][qy * Q + qx] = a0;
-                sX[le][1][iz][qy * Q + qx] = a1;
-                sX[le][2][iz][qy * Q + qx] = a2;
-            }
+        for (int i = t; i < D3; i += QQ) {
+            const long long g = act ? map[el * D3 + i] : 0;
+            sSl[le][i] = act ? slot[el * D3 + i] : 0;
+            sU[le][0][i] = act ? x[g] : 0.0;
+            sU[le][1][i] = act ? x[ncomp + g] : 0.0;
+            sU[le][2][i] = act ? x[2 * ncomp + g] : 0.0;
         }
-        __syncthreads();
-        // y-stage, z-stage, weights, z^T: registers of thread (qx, qy)
-#pragma unroll
+        wave_sync();
+#pragma unroll 1
         for (int c = 0; c < 3; ++c) {
+            // x-stage: thread (qx, iy = qy)
+            if (qy < D) {
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) {
+                    double a = 0.0;
+#pragma unroll
+                    for (int ix = 0; ix < D; ++ix) a += rBx[ix] * sU[le][c][(iz * D + qy) * D + ix];
+                    sX[le][iz][qy * Q + qx] = a;
+                }
+            }
+            wave_sync();
+            // y-stage, z-stage, weights, z^T in registers of thread (qx, qy)
             double w[D];
 #pragma unroll
             for (int iz = 0; iz < D; ++iz) {
                 double a = 0.0;
 #pragma unroll
-                for (int iy = 0; iy < D; ++iy) a += rBy[iy] * sX[le][c][iz][iy * Q + qx];
+                for (int iy = 0; iy < D; ++iy) a += rBy[iy] * sX[le][iz][iy * Q + qx];
                 w[iz] = a;
             }
             double a[D];
@@ -453,39 +487,35 @@ k_mass(const double *__restrict__ mq, const double *__restrict__ x,
                 for (int iz = 0; iz < D; ++iz) a[iz] += tab[T::B + qz * D + iz] * u;
             }
 #pragma unroll
-            for (int iz = 0; iz < D; ++iz) sZ[le][c][iz][t] = a[iz];
-        }
-        __syncthreads();
-        // y^T: thread (qx, iy = qy), into sX
-        if (qy < D) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
+            for (int iz = 0; iz < D; ++iz) sZ[le][iz][t] = a[iz];
+            wave_sync();
+            // y^T: thread (qx, iy = qy), into sX
+            if (qy < D) {
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
                     double b = 0.0;
 #pragma unroll
-                    for (int k = 0; k < Q; ++k) b += cBy[k] * sZ[le][c][iz][k * Q + qx];
-                    sX[le][c][iz][qy * Q + qx] = b;
-                }
-        }
-        __syncthreads();
-        // x^T: thread (ix = qx, iy = qy), summed into the patch slots
-        if (act && qx < D && qy < D) {
-#pragma unroll
-            for (int iz = 0; iz < D; ++iz) {
-                const int sidx = 3 * sSl[le][(iz * D + qy) * D + qx];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    double r = 0.0;
-#pragma unroll
-                    for (int k = 0; k < Q; ++k) r += cBx[k] * sX[le][c][iz][qy * Q + k];
-                    atomicAdd(&acc[sidx + c], r);
-                    if (DOT) dot += r * xs[sidx + c];
+                    for (int k = 0; k < Q; ++k) b += cBy[k] * sZ[le][iz][k * Q + qx];
+                    sX[le][iz][qy * Q + qx] = b;
                 }
             }
+            wave_sync();
+            // x^T: thread (ix = qx, iy = qy), summed into the patch slots
+            if (act && qx < D && qy < D) {
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) {
+                    const int li = (iz * D + qy) * D + qx;
+                    double r = 0.0;
+#pragma unroll
+                    for (int k = 0; k < Q; ++k) r += cBx[k] * sX[le][iz][qy * Q + k];
+                    atomicAdd(&acc[3 * sSl[le][li] + c], r);
+                    if (DOT) dot += r * sU[le][c][li];
+                }
+            }
+            wave_sync();  // sX is rewritten by the next component
         }
-        __syncthreads();  // sSl and sX are rewritten by the next pass
     }
+    __syncthreads();
     patch_write<UMAX>(acc, pr, pn, y, part, ncomp);
     if (DOT) {
         for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off);
@@ -730,7 +760,7 @@ struct Launch {
     static void force(const double *S, const double *e, const PatchDev &pd, double *y,
                       long long ncomp, const double *tab, hipStream_t st)
     {
-        const dim3 grid(pd.n_patch), block(force_ne(D, Q) * Q * Q);
+        const dim3 grid(pd.n_patch), block(force_waves(D, Q) * 64);
         if (e)
             hipLaunchKernelGGL((k_force<D, Q, false>), grid, block, 0, st, S, e, pd.perm, pd.slot,
                                pd.pn, pd.ptab, y, pd.part, ncomp, tab);
@@ -742,20 +772,20 @@ struct Launch {
                         long long ncomp, const double *tab, hipStream_t st)
     {
         (void)E;
-        hipLaunchKernelGGL((k_force_t<D, Q>), dim3(pd.n_patch), dim3(force_t_ne(D, Q) * Q * Q), 0,
+        hipLaunchKernelGGL((k_force_t<D, Q>), dim3(pd.n_patch), dim3(force_t_waves(D, Q) * 64), 0,
                            st, S, v, pd.perm, pd.slot, pd.pn, pd.ptab, z, ncomp, tab);
     }
     static void mass(const double *mq, const double *x, const PatchDev &pd, double *y,
                      long long ncomp, const double *tab, double *part_dot, const int *skip,
                      hipStream_t st)
     {
-        const dim3 grid(pd.n_patch), block(mass_ne(D, Q) * Q * Q);
+        const dim3 grid(pd.n_patch), block(mass_waves(D, Q) * 64);
         if (part_dot)
-            hipLaunchKernelGGL((k_mass<D, Q, true>), grid, block, 0, st, mq, x, pd.slot, pd.pn,
-                               pd.ptab, y, pd.part, ncomp, tab, part_dot, skip);
+            hipLaunchKernelGGL((k_mass<D, Q, true>), grid, block, 0, st, mq, x, pd.map, pd.slot,
+                               pd.pn, pd.ptab, y, pd.part, ncomp, tab, part_dot, skip);
         else
-            hipLaunchKernelGGL((k_mass<D, Q, false>), grid, block, 0, st, mq, x, pd.slot, pd.pn,
-                               pd.ptab, y, pd.part, ncomp, tab, part_dot, skip);
+            hipLaunchKernelGGL((k_mass<D, Q, false>), grid, block, 0, st, mq, x, pd.map, pd.slot,
+                               pd.pn, pd.ptab, y, pd.part, ncomp, tab, part_dot, skip);
     }
     static void qdata(const double *x, const double *v, const double *e, const PatchDev &pd, int E,
                       long long ncomp, int node_off, double *mq, double *S, const double *tab,
