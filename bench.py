@@ -99,7 +99,25 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_calib_bytes_each_way": src.numel() * 8, "launches": 3}))
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        ev0.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        # a read-only pass: the sum streams 1 GiB
+        s_ = src.sum()
+        ev0.record()
+        for _ in range(reps):
+            s_ = src.sum()
+        ev1.record()
+        torch.cuda.synchronize()
+        ms_r = ev0.elapsed_time(ev1) / reps
+        print(json.dumps({"copy_calib_bytes_each_way": src.numel() * 8, "launches": 3 + reps,
+                          "copy_GBps": 2 * src.numel() * 8 / (ms * 1e-3) / 1e9,
+                          "read_GBps": src.numel() * 8 / (ms_r * 1e-3) / 1e9}))
         return
 
     n, p, Q, label = CONFIGS[args.config]
