@@ -30,7 +30,8 @@ struct MeshRec {
     long long node_off = 0, elem_off = 0, l2_off = 0, S_off = 0, mq_off = 0;
     long long part_off = 0;  // into the CG dot-partial array (one per patch)
     int tab_slot = 0;        // into the table buffer (doubles)
-    const KernelSet *ks = nullptr;
+    const KernelSet *ks = nullptr;   // FP64 kernels
+    const KernelSet *ksl = nullptr;  // kernels of the context's precision (== ks for FP64)
     double rho0 = 1.0;
     PatchDev pd;             // device patch plan
     const int32_t *orphans = nullptr;
@@ -56,7 +57,11 @@ struct fe_ctx {
     long long E_tot = 0, N_tot = 0, L2_tot = 0, S_len = 0, mq_len = 0;
     bool uniform_pq = true;
     // device memory owned by the context
-    double *S = nullptr, *mq = nullptr, *tabs = nullptr;
+    bool lo = false;                  // FP32 storage and contractions (precision form)
+    void *S = nullptr;                // [E][9][Q^3], double or float
+    double *mq = nullptr, *tabs = nullptr;
+    float *mq32 = nullptr, *tabs32 = nullptr;
+    double *ref_r = nullptr, *ref_d = nullptr;  // refinement vectors
     std::vector<void *> plan_bufs;  // per-mesh patch plan arrays
     long long *min_key = nullptr;
     int *nonfinite = nullptr;
@@ -115,8 +120,9 @@ void free_all(fe_ctx *c)
 {
     if (!c) return;
     if (c->st) (void)hipStreamSynchronize(c->st);
-    void *dptrs[] = {c->S, c->mq, c->tabs, c->min_key, c->nonfinite, c->r, c->p,
-                     c->Ap, c->part, c->part2, c->scal, c->fr, c->cg, c->bad};
+    void *dptrs[] = {c->S, c->mq, c->tabs, c->mq32, c->tabs32, c->ref_r, c->ref_d, c->min_key,
+                     c->nonfinite, c->r, c->p, c->Ap, c->part, c->part2, c->scal, c->fr, c->cg,
+                     c->bad};
     for (void *d : dptrs)
         if (d) (void)hipFree(d);
     for (void *d : c->plan_bufs)
@@ -172,6 +178,20 @@ bool supported_pq(int p, int Q) { return fp64_kernels(p, Q) != nullptr; }
 
 }  // namespace
 
+// typed views of the context's stored data for one mesh
+static void *S_of(fe_ctx *c, const MeshRec &r)
+{
+    return c->lo ? (void *)((float *)c->S + r.S_off) : (void *)((double *)c->S + r.S_off);
+}
+static const void *tab_of(fe_ctx *c, const MeshRec &r)
+{
+    return c->lo ? (const void *)(c->tabs32 + r.tab_slot) : (const void *)(c->tabs + r.tab_slot);
+}
+
+namespace {
+
+}  // namespace
+
 // ======================================================================= ABI
 extern "C" {
 
@@ -213,7 +233,7 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
     }
     if (!(o.gamma > 1.0) || !(o.q1 >= 0.0) || !(o.q2 >= 0.0))
         return fail(nullptr, FE_EINVAL, "gamma must be > 1 and q1, q2 >= 0%s");
-    if (o.precision != FE_PREC_FP64)
+    if (o.precision != FE_PREC_FP64 && o.precision != FE_PREC_FP32)
         return fail(nullptr, FE_EUNSUPPORTED, "precision not provided by this build%s");
     if (o.flags & ~(FE_OPT_TIMERS | FE_OPT_BATCHED | FE_OPT_GRAPH))
         return fail(nullptr, FE_EINVAL, "unknown option flags%s");
@@ -238,6 +258,7 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
     ctx = new (std::nothrow) fe_ctx();
     if (!ctx) return fail(nullptr, FE_ENOMEM, "host allocation failed%s");
     ctx->opts = o;
+    ctx->lo = o.precision != FE_PREC_FP64;
     ctx->st = (hipStream_t)hip_stream;
     auto bail = [&](int code) {
         g_setup_error = ctx->err;
@@ -262,6 +283,7 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         r.N = d.n_nodes;
         r.rho0 = d.rho0;
         r.ks = fp64_kernels(r.p, r.Q);
+        r.ksl = ctx->lo ? fp32_kernels(r.p, r.Q) : r.ks;
         const long long Q3 = (long long)r.Q * r.Q * r.Q;
         r.node_off = ctx->N_tot;
         r.elem_off = ctx->E_tot;
@@ -291,7 +313,23 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
 
     long long qb = 0, wb = 0;
     int rc = FE_OK;
-    if ((rc = dev_alloc(ctx, &ctx->S, ctx->S_len, &qb)) || (rc = dev_alloc(ctx, &ctx->mq, ctx->mq_len, &qb)) ||
+    if (ctx->lo) {
+        float *S32 = nullptr;
+        if ((rc = dev_alloc(ctx, &S32, ctx->S_len, &qb)) || (rc = dev_alloc(ctx, &ctx->mq32, ctx->mq_len, &qb)) ||
+            (rc = dev_alloc(ctx, &ctx->tabs32, (long long)tab_host.size(), &wb)) ||
+            (rc = dev_alloc(ctx, &ctx->ref_r, 3 * ctx->N_tot, &wb)) ||
+            (rc = dev_alloc(ctx, &ctx->ref_d, 3 * ctx->N_tot, &wb))) {
+            ctx->S = S32;
+            return bail(rc);
+        }
+        ctx->S = S32;
+    } else {
+        double *S64 = nullptr;
+        rc = dev_alloc(ctx, &S64, ctx->S_len, &qb);
+        ctx->S = S64;
+        if (rc) return bail(rc);
+    }
+    if ((rc = dev_alloc(ctx, &ctx->mq, ctx->mq_len, &qb)) ||
         (rc = dev_alloc(ctx, &ctx->tabs, (long long)tab_host.size(), &wb)) ||
         (rc = dev_alloc(ctx, &ctx->min_key, 1, &wb)) || (rc = dev_alloc(ctx, &ctx->nonfinite, 1, &wb)) ||
         (rc = dev_alloc(ctx, &ctx->r, 3 * ctx->N_tot, &wb)) || (rc = dev_alloc(ctx, &ctx->p, 3 * ctx->N_tot, &wb)) ||
@@ -321,6 +359,7 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         ctx->err = "upload failed";
         return bail(FE_EDEVICE);
     }
+    if (ctx->lo) launch_f64_to_f32(ctx->tabs, ctx->tabs32, (long long)tab_host.size(), ctx->st);
 
     // patch plans (element order, distinct nodes, shared-node gather) per mesh
     auto upload = [&](const void *src, size_t bytes, void **dst) -> int {
@@ -401,6 +440,13 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         ctx->err = "set-up kernels failed";
         return bail(FE_EDEVICE);
     }
+    if (ctx->lo) {
+        launch_f64_to_f32(ctx->mq, ctx->mq32, ctx->mq_len, ctx->st);
+        if (hipStreamSynchronize(ctx->st) != hipSuccess) {
+            ctx->err = "set-up kernels failed";
+            return bail(FE_EDEVICE);
+        }
+    }
     const double min0 = key_to_double(*ctx->h_key);
     if (!(min0 > 0.0) || *ctx->h_flag) {
         char buf[128];
@@ -455,8 +501,8 @@ int fe_qdata_update(fe_ctx_t *ctx, const double *x, const double *v, const doubl
         for (const MeshRec &r : ctx->mesh) {
             QParams prm{r.rho0, ctx->opts.gamma, ctx->opts.gamma - 1.0, ctx->opts.q1, ctx->opts.q2,
                         1.0 / r.p};
-            r.ks->qdata(x, v, e + r.l2_off, r.pd, r.E, ctx->N_tot, 0, ctx->mq + r.mq_off,
-                        ctx->S + r.S_off, ctx->tabs + r.tab_slot, prm, ctx->min_key,
+            r.ksl->qdata(x, v, e + r.l2_off, r.pd, r.E, ctx->N_tot, 0, ctx->mq + r.mq_off,
+                        S_of(ctx, r), ctx->tabs + r.tab_slot, prm, ctx->min_key,
                         ctx->nonfinite, false, ctx->st);
         }
     }
@@ -472,8 +518,8 @@ int fe_force_mult(fe_ctx_t *ctx, const double *e, double *y)
     {
         ScopedTimer tm(ctx, FE_TIMER_FORCE);
         for (const MeshRec &r : ctx->mesh) {
-            r.ks->force(ctx->S + r.S_off, e ? e + r.l2_off : nullptr, r.pd, y, ctx->N_tot,
-                        ctx->tabs + r.tab_slot, ctx->st);
+            r.ksl->force(S_of(ctx, r), e ? e + r.l2_off : nullptr, r.pd, y, ctx->N_tot,
+                         tab_of(ctx, r), ctx->st);
             launch_gather_shared(r.pd, y, ctx->N_tot, nullptr, ctx->st);
             launch_zero_nodes(r.orphans, r.n_orphans, y, ctx->N_tot, nullptr, ctx->st);
         }
@@ -490,18 +536,24 @@ int fe_force_mult_T(fe_ctx_t *ctx, const double *v, double *z)
     {
         ScopedTimer tm(ctx, FE_TIMER_FORCE_T);
         for (const MeshRec &r : ctx->mesh)
-            r.ks->force_t(ctx->S + r.S_off, v, r.pd, r.E, z + r.l2_off, ctx->N_tot,
-                          ctx->tabs + r.tab_slot, ctx->st);
+            r.ksl->force_t(S_of(ctx, r), v, r.pd, r.E, z + r.l2_off, ctx->N_tot, tab_of(ctx, r),
+                           ctx->st);
     }
     HIP_OK(hipGetLastError());
     return FE_OK;
 }
 
-static void mass_launch(fe_ctx *ctx, const double *x, double *y, bool dot, const int *skip)
+// lo: the FP32 operator (precision form); otherwise the FP64 operator
+static void mass_launch(fe_ctx *ctx, const double *x, double *y, bool dot, const int *skip,
+                        bool lo = false)
 {
     for (const MeshRec &r : ctx->mesh) {
-        r.ks->mass(ctx->mq + r.mq_off, x, r.pd, y, ctx->N_tot, ctx->tabs + r.tab_slot,
-                   dot ? ctx->part + r.part_off : nullptr, skip, ctx->st);
+        if (lo)
+            r.ksl->mass(ctx->mq32 + r.mq_off, x, r.pd, y, ctx->N_tot, ctx->tabs32 + r.tab_slot,
+                        dot ? ctx->part + r.part_off : nullptr, skip, ctx->st);
+        else
+            r.ks->mass(ctx->mq + r.mq_off, x, r.pd, y, ctx->N_tot, ctx->tabs + r.tab_slot,
+                       dot ? ctx->part + r.part_off : nullptr, skip, ctx->st);
         launch_gather_shared(r.pd, y, ctx->N_tot, skip, ctx->st);
         launch_zero_nodes(r.orphans, r.n_orphans, y, ctx->N_tot, skip, ctx->st);
     }
@@ -514,25 +566,22 @@ int fe_mass_mult(fe_ctx_t *ctx, const double *x, double *y)
     if ((const void *)x == (const void *)y) return fail(ctx, FE_EINVAL, "input aliases output%s");
     {
         ScopedTimer tm(ctx, FE_TIMER_MASS);
-        mass_launch(ctx, x, y, false, nullptr);
+        mass_launch(ctx, x, y, false, nullptr, ctx->lo);
     }
     HIP_OK(hipGetLastError());
     return FE_OK;
 }
 
-int fe_mass_cg(fe_ctx_t *ctx, const double *b, double *x, const int32_t *ess_dofs, int32_t n_ess,
-               double rel_tol, int32_t max_iter, int32_t *iters, double *rel_res)
+}  // extern "C"
+
+// CG on the free DOFs (mask already built, x already zero on essential DOFs)
+// with the FP64 operator, or the FP32 one when lo. On return *out holds the
+// final device state (iterations, ||b_free||^2, done flag).
+static int cg_run(fe_ctx *ctx, const double *b, double *x, double rel_tol, int max_iter, bool lo,
+                  CgState *out)
 {
-    if (!ctx) return FE_EINVAL;
-    if (!b || !x) return fail(ctx, FE_EINVAL, "NULL argument%s");
-    if ((const void *)b == (const void *)x) return fail(ctx, FE_EINVAL, "b aliases x%s");
-    if (n_ess < 0 || (n_ess > 0 && !ess_dofs)) return fail(ctx, FE_EINVAL, "bad essential DOF list%s");
-    if (!(rel_tol >= 0.0) || max_iter < 0) return fail(ctx, FE_EINVAL, "bad tolerance or max_iter%s");
     const long long n = 3 * ctx->N_tot;
-    launch_reset_diag(nullptr, ctx->bad, ctx->st);
-    cg_mask(ctx->fr, n, ess_dofs, n_ess, ctx->bad, ctx->st);
-    cg_mask_apply(x, ctx->fr, n, ctx->st);
-    mass_launch(ctx, x, ctx->Ap, false, nullptr);
+    mass_launch(ctx, x, ctx->Ap, false, nullptr, lo);
     cg_start(b, ctx->Ap, ctx->r, ctx->p, ctx->fr, n, ctx->part, ctx->part2, ctx->cg, rel_tol,
              max_iter, ctx->st);
     HIP_OK(hipGetLastError());
@@ -542,7 +591,7 @@ int fe_mass_cg(fe_ctx_t *ctx, const double *b, double *x, const int32_t *ess_dof
         for (int k = 0; k < batch; ++k) {
             {
                 ScopedTimer tm(ctx, FE_TIMER_MASS);
-                mass_launch(ctx, ctx->p, ctx->Ap, true, skip);
+                mass_launch(ctx, ctx->p, ctx->Ap, true, skip, lo);
             }
             cg_alpha(ctx->part, (int)ctx->n_parts, ctx->cg, ctx->st);
             cg_update(x, ctx->r, ctx->p, ctx->Ap, ctx->fr, n, ctx->cg, ctx->part2, ctx->st);
@@ -557,18 +606,79 @@ int fe_mass_cg(fe_ctx_t *ctx, const double *b, double *x, const int32_t *ess_dof
         if (ctx->h_cg->done) break;
         if (batch < 32) batch *= 2;
     }
-    const CgState st = *ctx->h_cg;
-    // true residual of the free system
-    mass_launch(ctx, x, ctx->Ap, false, nullptr);
+    *out = *ctx->h_cg;
+    return FE_OK;
+}
+
+// ||b_free - (M x)_free||^2 with the FP64 operator (synchronises)
+static int true_resid2(fe_ctx *ctx, const double *b, const double *x, double *res2)
+{
+    const long long n = 3 * ctx->N_tot;
+    mass_launch(ctx, x, ctx->Ap, false, nullptr, false);
     resid_norm2(b, ctx->Ap, ctx->fr, n, ctx->part2, ctx->scal, ctx->st);
     HIP_OK(hipMemcpyAsync(ctx->h_scal, ctx->scal, sizeof(double), hipMemcpyDeviceToHost, ctx->st));
     HIP_OK(hipStreamSynchronize(ctx->st));
-    const double res = std::sqrt(*ctx->h_scal / (st.bb > 0.0 ? st.bb : 1.0));
-    ctx->last_iters = st.iter;
+    *res2 = *ctx->h_scal;
+    return FE_OK;
+}
+
+extern "C" {
+
+int fe_mass_cg(fe_ctx_t *ctx, const double *b, double *x, const int32_t *ess_dofs, int32_t n_ess,
+               double rel_tol, int32_t max_iter, int32_t *iters, double *rel_res)
+{
+    if (!ctx) return FE_EINVAL;
+    if (!b || !x) return fail(ctx, FE_EINVAL, "NULL argument%s");
+    if ((const void *)b == (const void *)x) return fail(ctx, FE_EINVAL, "b aliases x%s");
+    if (n_ess < 0 || (n_ess > 0 && !ess_dofs)) return fail(ctx, FE_EINVAL, "bad essential DOF list%s");
+    if (!(rel_tol >= 0.0) || max_iter < 0) return fail(ctx, FE_EINVAL, "bad tolerance or max_iter%s");
+    const long long n = 3 * ctx->N_tot;
+    launch_reset_diag(nullptr, ctx->bad, ctx->st);
+    cg_mask(ctx->fr, n, ess_dofs, n_ess, ctx->bad, ctx->st);
+    cg_mask_apply(x, ctx->fr, n, ctx->st);
+    int rc = FE_OK, total = 0;
+    bool limit = false;
+    double res = 0.0;
+    if (!ctx->lo) {
+        CgState st{};
+        if ((rc = cg_run(ctx, b, x, rel_tol, max_iter, false, &st))) return rc;
+        double r2 = 0.0;
+        if ((rc = true_resid2(ctx, b, x, &r2))) return rc;
+        res = std::sqrt(r2 / (st.bb > 0.0 ? st.bb : 1.0));
+        total = st.iter;
+        limit = st.done == 2;
+    } else {
+        // iterative refinement: FP64 residual r = b - M x, inner CG on the FP32
+        // operator for M d = r to a relative 1e-5 (or rel_tol if looser), x += d
+        const double inner_tol = rel_tol > 1e-5 ? rel_tol : 1e-5;
+        launch_fill(ctx->ref_d, n, 0.0, ctx->st);
+        resid_norm2(b, ctx->ref_d, ctx->fr, n, ctx->part2, ctx->scal, ctx->st);
+        HIP_OK(hipMemcpyAsync(ctx->h_scal, ctx->scal, sizeof(double), hipMemcpyDeviceToHost, ctx->st));
+        HIP_OK(hipStreamSynchronize(ctx->st));
+        const double bb = *ctx->h_scal;
+        for (int sweep = 0;; ++sweep) {
+            double r2 = 0.0;
+            if ((rc = true_resid2(ctx, b, x, &r2))) return rc;  // leaves Ap = M x
+            res = std::sqrt(r2 / (bb > 0.0 ? bb : 1.0));
+            if (res <= rel_tol) break;
+            if (total >= max_iter || sweep >= 60) {
+                limit = true;
+                break;
+            }
+            vec_sub_masked(b, ctx->Ap, ctx->fr, ctx->ref_r, n, ctx->st);
+            launch_fill(ctx->ref_d, n, 0.0, ctx->st);
+            CgState st{};
+            if ((rc = cg_run(ctx, ctx->ref_r, ctx->ref_d, inner_tol, max_iter - total, true, &st)))
+                return rc;
+            total += st.iter;
+            vec_add(x, ctx->ref_d, n, ctx->st);
+        }
+    }
+    ctx->last_iters = total;
     ctx->last_res = res;
-    if (iters) *iters = st.iter;
+    if (iters) *iters = total;
     if (rel_res) *rel_res = res;
-    if (st.done == 2) return fail(ctx, FE_ENOTCONV, "iteration limit reached%s");
+    if (limit) return fail(ctx, FE_ENOTCONV, "iteration limit reached%s");
     return FE_OK;
 }
 
@@ -592,9 +702,11 @@ int fe_export_qdata(fe_ctx_t *ctx, double *S_out, double *mq_out)
     for (const MeshRec &r : ctx->mesh) {
         const int Q3 = r.Q * r.Q * r.Q;
         if (S_out)
-            launch_unpermute_rows(ctx->S + r.S_off, r.pd.perm, r.E, 9 * Q3, S_out + r.S_off, ctx->st);
+            launch_unpermute_rows(S_of(ctx, r), ctx->lo, r.pd.perm, r.E, 9 * Q3, S_out + r.S_off,
+                                  ctx->st);
         if (mq_out)
-            launch_unpermute_rows(ctx->mq + r.mq_off, r.pd.perm, r.E, Q3, mq_out + r.mq_off, ctx->st);
+            launch_unpermute_rows(ctx->mq + r.mq_off, false, r.pd.perm, r.E, Q3, mq_out + r.mq_off,
+                                  ctx->st);
     }
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(ctx->st));

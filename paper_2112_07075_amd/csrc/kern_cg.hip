@@ -190,6 +190,35 @@ __global__ void k_sum_final(const double *__restrict__ part, int nparts, double 
     if (threadIdx.x == 0) *out = s;
 }
 
+// out = (b - Ax) on free DOFs, 0 elsewhere
+__global__ void k_sub_masked(const double *__restrict__ b, const double *__restrict__ Ax,
+                             const unsigned char *__restrict__ fr, double *__restrict__ out,
+                             long long n)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = fr[i] ? b[i] - Ax[i] : 0.0;
+}
+
+// x += d
+__global__ void k_add(double *__restrict__ x, const double *__restrict__ d, long long n)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        x[i] += d[i];
+}
+
+void vec_sub_masked(const double *b, const double *Ax, const unsigned char *fr, double *out,
+                    long long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sub_masked, dim3(kVecBlocks), dim3(256), 0, st, b, Ax, fr, out, n);
+}
+
+void vec_add(double *x, const double *d, long long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_add, dim3(kVecBlocks), dim3(256), 0, st, x, d, n);
+}
+
 void cg_mask(unsigned char *fr, long long n, const int32_t *ess, int n_ess, int *bad,
              hipStream_t st)
 {

@@ -25,6 +25,9 @@ void cg_update(double *x, double *r, const double *p, const double *Ap, const un
                long long n, const CgState *state, double *part, hipStream_t st);
 void cg_beta(const double *part, CgState *state, hipStream_t st);
 void cg_direction(double *p, const double *r, long long n, const CgState *state, hipStream_t st);
+void vec_sub_masked(const double *b, const double *Ax, const unsigned char *fr, double *out,
+                    long long n, hipStream_t st);
+void vec_add(double *x, const double *d, long long n, hipStream_t st);
 void resid_norm2(const double *b, const double *Ax, const unsigned char *fr, long long n,
                  double *part, double *out, hipStream_t st);
 

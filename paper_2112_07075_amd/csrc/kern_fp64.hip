@@ -69,9 +69,10 @@ __host__ __device__ constexpr int fit_waves(int Q, int per_elem, int fixed)
     return w;
 }
 
-__host__ __device__ constexpr int force_waves(int D, int Q)
+// rs = bytes of the real type of the stored data and the contractions
+__host__ __device__ constexpr int force_waves(int D, int Q, int rs)
 {
-    return fit_waves(Q, 8 * (3 * D * Q * Q + 2 * D * D * Q), 24 * patch_umax(D));
+    return fit_waves(Q, rs * (3 * D * Q * Q + 2 * D * D * Q), 3 * rs * patch_umax(D));
 }
 
 // One row of the patch table: first element, element count, offset of the
@@ -86,14 +87,14 @@ __device__ __forceinline__ PatchRow load_patch(const int32_t *__restrict__ ptab,
 }
 
 // R^T of one patch: private nodes are stored, shared nodes leave a partial.
-template <int UMAX>
-__device__ __forceinline__ void patch_write(const double *acc, const PatchRow &pr,
+template <int UMAX, typename R>
+__device__ __forceinline__ void patch_write(const R *acc, const PatchRow &pr,
                                             const int32_t *__restrict__ pn,
                                             double *__restrict__ y, double *__restrict__ part,
                                             long long ncomp)
 {
     for (int u = threadIdx.x; u < pr.U; u += blockDim.x) {
-        const double a0 = acc[3 * u], a1 = acc[3 * u + 1], a2 = acc[3 * u + 2];
+        const double a0 = (double)acc[3 * u], a1 = (double)acc[3 * u + 1], a2 = (double)acc[3 * u + 2];
         if (u < pr.P) {
             const long long g = pn[pr.pno + u];
             y[g] = a0;
@@ -113,27 +114,27 @@ __device__ __forceinline__ void patch_write(const double *acc, const PatchRow &p
 // per workgroup. Three H1 contraction stages per component with the three
 // derivative terms fused: z-stage -> (B, B, G), y-stage -> (B | G + B),
 // x-stage -> (G + B); element results are summed into the patch's LDS slots.
-template <int D, int Q, bool ONE>
-__global__ void __launch_bounds__(force_waves(D, Q) * 64)
-k_force(const double *__restrict__ S, const double *__restrict__ e,
+template <int D, int Q, bool ONE, typename R>
+__global__ void __launch_bounds__(force_waves(D, Q, sizeof(R)) * 64)
+k_force(const R *__restrict__ S, const double *__restrict__ e,
         const int32_t *__restrict__ perm, const uint16_t *__restrict__ slot,
         const int32_t *__restrict__ pn, const int32_t *__restrict__ ptab,
         double *__restrict__ y, double *__restrict__ part, long long ncomp,
-        const double *__restrict__ tab)
+        const R *__restrict__ tab)
 {
-    constexpr int NE = force_waves(D, Q) * wave_ne(Q), UMAX = patch_umax(D);
+    constexpr int NE = force_waves(D, Q, sizeof(R)) * wave_ne(Q), UMAX = patch_umax(D);
     constexpr int DL = D - 1, QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D, DL3 = DL * DL * DL;
     using T = Tab<D, Q>;
-    __shared__ double acc[3 * UMAX];
-    __shared__ double sA[NE + 1][3][D][QQ];
-    __shared__ double sC[NE + 1][2][D][D * Q];
+    __shared__ R acc[3 * UMAX];
+    __shared__ R sA[NE + 1][3][D][QQ];
+    __shared__ R sC[NE + 1][2][D][D * Q];
 
     const Lane L = lane_map<Q, NE>();
     const int tid = threadIdx.x, le = L.le, t = L.t, qx = t % Q, qy = t / Q;
     const PatchRow pr = load_patch(ptab, xcd_block(blockIdx.x, gridDim.x));
     for (int k = tid; k < 3 * pr.U; k += blockDim.x) acc[k] = 0.0;
 
-    double cBy[Q], cGy[Q], cBx[Q], cGx[Q];
+    R cBy[Q], cGy[Q], cBx[Q], cGx[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
         cBy[k] = qy < D ? tab[T::B + k * D + qy] : 0.0;
@@ -149,40 +150,40 @@ k_force(const double *__restrict__ S, const double *__restrict__ e,
         const bool act = L.valid && idx < pr.cnt;
         const long long el = pr.eb + (act ? idx : 0);
         // the element's whole S column first: 9*Q independent streaming loads in flight
-        const double *__restrict__ Se = S + el * 9 * Q3 + t;
-        double sv[9][Q];
+        const R *__restrict__ Se = S + el * 9 * Q3 + t;
+        R sv[9][Q];
 #pragma unroll
         for (int cd = 0; cd < 9; ++cd)
 #pragma unroll
             for (int qz = 0; qz < Q; ++qz)
-                sv[cd][qz] = act ? __builtin_nontemporal_load(Se + cd * Q3 + qz * QQ) : 0.0;
+                sv[cd][qz] = act ? __builtin_nontemporal_load(Se + cd * Q3 + qz * QQ) : (R)0;
         int sl[D];
 #pragma unroll
         for (int iz = 0; iz < D; ++iz)
             sl[iz] = (act && qx < D && qy < D) ? slot[el * D3 + iz * D * D + qy * D + qx] : 0;
-        double eq[Q];
+        R eq[Q];
         if (ONE) {
 #pragma unroll
             for (int k = 0; k < Q; ++k) eq[k] = 1.0;
         } else {
             const double *__restrict__ ee = e + (long long)perm[el] * DL3;
-            double tz[DL];
+            R tz[DL];
 #pragma unroll
             for (int jz = 0; jz < DL; ++jz) {
-                double s = 0.0;
+                R s = 0.0;
 #pragma unroll
                 for (int jy = 0; jy < DL; ++jy) {
-                    double u = 0.0;
+                    R u = 0.0;
 #pragma unroll
                     for (int jx = 0; jx < DL; ++jx)
-                        u += tab[T::BL + qx * DL + jx] * (act ? ee[(jz * DL + jy) * DL + jx] : 0.0);
+                        u += tab[T::BL + qx * DL + jx] * (R)(act ? ee[(jz * DL + jy) * DL + jx] : 0.0);
                     s += tab[T::BL + qy * DL + jy] * u;
                 }
                 tz[jz] = s;
             }
 #pragma unroll
             for (int qz = 0; qz < Q; ++qz) {
-                double s = 0.0;
+                R s = 0.0;
 #pragma unroll
                 for (int jz = 0; jz < DL; ++jz) s += tab[T::BL + qz * DL + jz] * tz[jz];
                 eq[qz] = s;
@@ -190,17 +191,17 @@ k_force(const double *__restrict__ S, const double *__restrict__ e,
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            double a0[D], a1[D], a2[D];
+            R a0[D], a1[D], a2[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) a0[i] = a1[i] = a2[i] = 0.0;
 #pragma unroll
             for (int qz = 0; qz < Q; ++qz) {
-                const double s0 = sv[c * 3 + 0][qz] * eq[qz];
-                const double s1 = sv[c * 3 + 1][qz] * eq[qz];
-                const double s2 = sv[c * 3 + 2][qz] * eq[qz];
+                const R s0 = sv[c * 3 + 0][qz] * eq[qz];
+                const R s1 = sv[c * 3 + 1][qz] * eq[qz];
+                const R s2 = sv[c * 3 + 2][qz] * eq[qz];
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
-                    const double b = tab[T::B + qz * D + iz], g = tab[T::G + qz * D + iz];
+                    const R b = tab[T::B + qz * D + iz], g = tab[T::G + qz * D + iz];
                     a0[iz] += b * s0;
                     a1[iz] += b * s1;
                     a2[iz] += g * s2;
@@ -216,7 +217,7 @@ k_force(const double *__restrict__ S, const double *__restrict__ e,
             if (qy < D) {
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
-                    double c0 = 0.0, c1 = 0.0;
+                    R c0 = 0.0, c1 = 0.0;
 #pragma unroll
                     for (int k = 0; k < Q; ++k) {
                         c0 += cBy[k] * sA[le][0][iz][k * Q + qx];
@@ -230,7 +231,7 @@ k_force(const double *__restrict__ S, const double *__restrict__ e,
             if (act && qx < D && qy < D) {
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
-                    double r = 0.0;
+                    R r = 0.0;
 #pragma unroll
                     for (int k = 0; k < Q; ++k)
                         r += cGx[k] * sC[le][0][iz][qy * Q + k] + cBx[k] * sC[le][1][iz][qy * Q + k];
@@ -247,38 +248,38 @@ k_force(const double *__restrict__ S, const double *__restrict__ e,
 // z[E][j] = sum_q phi_j(q) sum_{c,d} S[c][d](q) (grad_xi v_c)_d(q), one patch per
 // workgroup: the patch's distinct nodes of v are read once into LDS; rows of z
 // are written in caller element order.
-__host__ __device__ constexpr int force_t_waves(int D, int Q)
+__host__ __device__ constexpr int force_t_waves(int D, int Q, int rs)
 {
-    return fit_waves(Q, 8 * (2 * D * D * Q + (D - 1) * Q * Q + (D - 1) * (D - 1) * Q) + 4 * D * D * D,
-                     24 * patch_umax(D));
+    return fit_waves(Q, rs * (2 * D * D * Q + (D - 1) * Q * Q + (D - 1) * (D - 1) * Q) + 4 * D * D * D,
+                     3 * rs * patch_umax(D));
 }
 
-template <int D, int Q>
-__global__ void __launch_bounds__(force_t_waves(D, Q) * 64)
-k_force_t(const double *__restrict__ S, const double *__restrict__ v,
+template <int D, int Q, typename R>
+__global__ void __launch_bounds__(force_t_waves(D, Q, sizeof(R)) * 64)
+k_force_t(const R *__restrict__ S, const double *__restrict__ v,
           const int32_t *__restrict__ perm, const uint16_t *__restrict__ slot,
           const int32_t *__restrict__ pn, const int32_t *__restrict__ ptab,
-          double *__restrict__ z, long long ncomp, const double *__restrict__ tab)
+          double *__restrict__ z, long long ncomp, const R *__restrict__ tab)
 {
-    constexpr int NE = force_t_waves(D, Q) * wave_ne(Q), UMAX = patch_umax(D);
+    constexpr int NE = force_t_waves(D, Q, sizeof(R)) * wave_ne(Q), UMAX = patch_umax(D);
     constexpr int DL = D - 1, QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D, DL3 = DL * DL * DL;
     using T = Tab<D, Q>;
-    __shared__ double vs[3 * UMAX];
+    __shared__ R vs[3 * UMAX];
     __shared__ int sSl[NE + 1][D3];
-    __shared__ double sX[NE + 1][2][D][D * Q];
-    __shared__ double sT[NE + 1][DL][QQ];
-    __shared__ double sT2[NE + 1][DL][DL * Q];
+    __shared__ R sX[NE + 1][2][D][D * Q];
+    __shared__ R sT[NE + 1][DL][QQ];
+    __shared__ R sT2[NE + 1][DL][DL * Q];
 
     const Lane L = lane_map<Q, NE>();
     const int tid = threadIdx.x, le = L.le, t = L.t, qx = t % Q, qy = t / Q;
     const PatchRow pr = load_patch(ptab, xcd_block(blockIdx.x, gridDim.x));
     for (int u = tid; u < pr.U; u += blockDim.x) {
         const long long g = pn[pr.pno + u];
-        vs[3 * u] = v[g];
-        vs[3 * u + 1] = v[ncomp + g];
-        vs[3 * u + 2] = v[2 * ncomp + g];
+        vs[3 * u] = (R)v[g];
+        vs[3 * u + 1] = (R)v[ncomp + g];
+        vs[3 * u + 2] = (R)v[2 * ncomp + g];
     }
-    double rBx[D], rGx[D], rBy[D], rGy[D];
+    R rBx[D], rGx[D], rBy[D], rGy[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
         rBx[i] = tab[T::B + qx * D + i];
@@ -294,16 +295,16 @@ k_force_t(const double *__restrict__ S, const double *__restrict__ v,
         const int idx = base + le;
         const bool act = L.valid && idx < pr.cnt;
         const long long el = pr.eb + (act ? idx : 0);
-        const double *__restrict__ Se = S + el * 9 * Q3 + t;
-        double sv[9][Q];
+        const R *__restrict__ Se = S + el * 9 * Q3 + t;
+        R sv[9][Q];
 #pragma unroll
         for (int cd = 0; cd < 9; ++cd)
 #pragma unroll
             for (int qz = 0; qz < Q; ++qz)
-                sv[cd][qz] = act ? __builtin_nontemporal_load(Se + cd * Q3 + qz * QQ) : 0.0;
+                sv[cd][qz] = act ? __builtin_nontemporal_load(Se + cd * Q3 + qz * QQ) : (R)0;
         for (int i = t; i < D3; i += QQ) sSl[le][i] = act ? slot[el * D3 + i] : 0;
         wave_sync();
-        double s[Q];
+        R s[Q];
 #pragma unroll
         for (int k = 0; k < Q; ++k) s[k] = 0.0;
 #pragma unroll
@@ -312,10 +313,10 @@ k_force_t(const double *__restrict__ S, const double *__restrict__ v,
             if (qy < D) {
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
-                    double ub = 0.0, ug = 0.0;
+                    R ub = 0.0, ug = 0.0;
 #pragma unroll
                     for (int ix = 0; ix < D; ++ix) {
-                        const double u = vs[3 * sSl[le][(iz * D + qy) * D + ix] + c];
+                        const R u = vs[3 * sSl[le][(iz * D + qy) * D + ix] + c];
                         ub += rBx[ix] * u;
                         ug += rGx[ix] * u;
                     }
@@ -325,13 +326,13 @@ k_force_t(const double *__restrict__ S, const double *__restrict__ v,
             }
             wave_sync();
             // y-stage into registers, then z-stage and the pointwise S : grad v
-            double vx[D], vy[D], vz[D];
+            R vx[D], vy[D], vz[D];
 #pragma unroll
             for (int iz = 0; iz < D; ++iz) {
-                double a = 0.0, b = 0.0, cc = 0.0;
+                R a = 0.0, b = 0.0, cc = 0.0;
 #pragma unroll
                 for (int iy = 0; iy < D; ++iy) {
-                    const double ub = sX[le][0][iz][iy * Q + qx], ug = sX[le][1][iz][iy * Q + qx];
+                    const R ub = sX[le][0][iz][iy * Q + qx], ug = sX[le][1][iz][iy * Q + qx];
                     a += rBy[iy] * ug;
                     b += rGy[iy] * ub;
                     cc += rBy[iy] * ub;
@@ -343,10 +344,10 @@ k_force_t(const double *__restrict__ S, const double *__restrict__ v,
             wave_sync();  // sX is rewritten by the next component
 #pragma unroll
             for (int qz = 0; qz < Q; ++qz) {
-                double dx = 0.0, dy = 0.0, dz = 0.0;
+                R dx = 0.0, dy = 0.0, dz = 0.0;
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
-                    const double bb = tab[T::B + qz * D + iz], gg = tab[T::G + qz * D + iz];
+                    const R bb = tab[T::B + qz * D + iz], gg = tab[T::G + qz * D + iz];
                     dx += bb * vx[iz];
                     dy += bb * vy[iz];
                     dz += gg * vz[iz];
@@ -357,7 +358,7 @@ k_force_t(const double *__restrict__ S, const double *__restrict__ v,
         // L2 test functions: B_l^T in z (registers), y and x (LDS)
 #pragma unroll
         for (int jz = 0; jz < DL; ++jz) {
-            double a = 0.0;
+            R a = 0.0;
 #pragma unroll
             for (int qz = 0; qz < Q; ++qz) a += tab[T::BL + qz * DL + jz] * s[qz];
             sT[le][jz][t] = a;
@@ -366,7 +367,7 @@ k_force_t(const double *__restrict__ S, const double *__restrict__ v,
         if (qy < DL) {
 #pragma unroll
             for (int jz = 0; jz < DL; ++jz) {
-                double a = 0.0;
+                R a = 0.0;
 #pragma unroll
                 for (int k = 0; k < Q; ++k) a += tab[T::BL + k * DL + qy] * sT[le][jz][k * Q + qx];
                 sT2[le][jz][qy * Q + qx] = a;
@@ -377,10 +378,10 @@ k_force_t(const double *__restrict__ S, const double *__restrict__ v,
             double *__restrict__ zr = z + (long long)perm[el] * DL3;
 #pragma unroll
             for (int jz = 0; jz < DL; ++jz) {
-                double a = 0.0;
+                R a = 0.0;
 #pragma unroll
                 for (int k = 0; k < Q; ++k) a += tab[T::BL + k * DL + qx] * sT2[le][jz][qy * Q + k];
-                zr[(jz * DL + qy) * DL + qx] = a;
+                zr[(jz * DL + qy) * DL + qx] = (double)a;
             }
         }
     }
@@ -391,37 +392,37 @@ k_force_t(const double *__restrict__ S, const double *__restrict__ v,
 // wave works through its own elements (per-element node gather, one component
 // at a time) and sums into the patch's LDS slots. With DOT, the workgroup also
 // writes sum_E x_E^T (M_E x_E) (= x^T M x over its elements) to part_dot.
-__host__ __device__ constexpr int mass_waves(int D, int Q)
+__host__ __device__ constexpr int mass_waves(int D, int Q, int rs)
 {
-    return fit_waves(Q, 8 * (3 * D * D * D + 2 * D * D * Q + D * Q * Q) + 4 * D * D * D,
-                     24 * patch_umax(D) + 256);
+    return fit_waves(Q, rs * (3 * D * D * D + 2 * D * D * Q + D * Q * Q) + 4 * D * D * D,
+                     3 * rs * patch_umax(D) + 256);
 }
 
-template <int D, int Q, bool DOT>
-__global__ void __launch_bounds__(mass_waves(D, Q) * 64)
-k_mass(const double *__restrict__ mq, const double *__restrict__ x,
+template <int D, int Q, bool DOT, typename R>
+__global__ void __launch_bounds__(mass_waves(D, Q, sizeof(R)) * 64)
+k_mass(const R *__restrict__ mq, const double *__restrict__ x,
        const int32_t *__restrict__ map, const uint16_t *__restrict__ slot,
        const int32_t *__restrict__ pn, const int32_t *__restrict__ ptab,
        double *__restrict__ y, double *__restrict__ part, long long ncomp,
-       const double *__restrict__ tab, double *__restrict__ part_dot,
+       const R *__restrict__ tab, double *__restrict__ part_dot,
        const int *__restrict__ skip)
 {
-    constexpr int NE = mass_waves(D, Q) * wave_ne(Q), UMAX = patch_umax(D);
+    constexpr int NE = mass_waves(D, Q, sizeof(R)) * wave_ne(Q), UMAX = patch_umax(D);
     constexpr int QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D;
     using T = Tab<D, Q>;
     if (skip && *skip) return;  // a finished CG solve
-    __shared__ double acc[3 * UMAX];
-    __shared__ double sU[NE + 1][3][D3];
+    __shared__ R acc[3 * UMAX];
+    __shared__ R sU[NE + 1][3][D3];
     __shared__ int sSl[NE + 1][D3];
-    __shared__ double sX[NE + 1][D][D * Q];  // x-stage out, then y^T out
-    __shared__ double sZ[NE + 1][D][QQ];
+    __shared__ R sX[NE + 1][D][D * Q];  // x-stage out, then y^T out
+    __shared__ R sZ[NE + 1][D][QQ];
     __shared__ double sred[8];
 
     const Lane L = lane_map<Q, NE>();
     const int tid = threadIdx.x, le = L.le, t = L.t, qx = t % Q, qy = t / Q;
     const PatchRow pr = load_patch(ptab, xcd_block(blockIdx.x, gridDim.x));
     for (int k = tid; k < 3 * pr.U; k += blockDim.x) acc[k] = 0.0;
-    double rBx[D], rBy[D], cBy[Q], cBx[Q];
+    R rBx[D], rBy[D], cBy[Q], cBx[Q];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
         rBx[i] = tab[T::B + qx * D + i];
@@ -440,16 +441,16 @@ k_mass(const double *__restrict__ mq, const double *__restrict__ x,
         const int idx = base + le;
         const bool act = L.valid && idx < pr.cnt;
         const long long el = pr.eb + (act ? idx : 0);
-        double m[Q];
+        R m[Q];
 #pragma unroll
         for (int k = 0; k < Q; ++k)
-            m[k] = act ? __builtin_nontemporal_load(mq + el * Q3 + k * QQ + t) : 0.0;
+            m[k] = act ? __builtin_nontemporal_load(mq + el * Q3 + k * QQ + t) : (R)0;
         for (int i = t; i < D3; i += QQ) {
             const long long g = act ? map[el * D3 + i] : 0;
             sSl[le][i] = act ? slot[el * D3 + i] : 0;
-            sU[le][0][i] = act ? x[g] : 0.0;
-            sU[le][1][i] = act ? x[ncomp + g] : 0.0;
-            sU[le][2][i] = act ? x[2 * ncomp + g] : 0.0;
+            sU[le][0][i] = act ? (R)x[g] : (R)0;
+            sU[le][1][i] = act ? (R)x[ncomp + g] : (R)0;
+            sU[le][2][i] = act ? (R)x[2 * ncomp + g] : (R)0;
         }
         wave_sync();
 #pragma unroll 1
@@ -458,7 +459,7 @@ k_mass(const double *__restrict__ mq, const double *__restrict__ x,
             if (qy < D) {
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
-                    double a = 0.0;
+                    R a = 0.0;
 #pragma unroll
                     for (int ix = 0; ix < D; ++ix) a += rBx[ix] * sU[le][c][(iz * D + qy) * D + ix];
                     sX[le][iz][qy * Q + qx] = a;
@@ -466,20 +467,20 @@ k_mass(const double *__restrict__ mq, const double *__restrict__ x,
             }
             wave_sync();
             // y-stage, z-stage, weights, z^T in registers of thread (qx, qy)
-            double w[D];
+            R w[D];
 #pragma unroll
             for (int iz = 0; iz < D; ++iz) {
-                double a = 0.0;
+                R a = 0.0;
 #pragma unroll
                 for (int iy = 0; iy < D; ++iy) a += rBy[iy] * sX[le][iz][iy * Q + qx];
                 w[iz] = a;
             }
-            double a[D];
+            R a[D];
 #pragma unroll
             for (int iz = 0; iz < D; ++iz) a[iz] = 0.0;
 #pragma unroll
             for (int qz = 0; qz < Q; ++qz) {
-                double u = 0.0;
+                R u = 0.0;
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) u += tab[T::B + qz * D + iz] * w[iz];
                 u *= m[qz];
@@ -493,7 +494,7 @@ k_mass(const double *__restrict__ mq, const double *__restrict__ x,
             if (qy < D) {
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
-                    double b = 0.0;
+                    R b = 0.0;
 #pragma unroll
                     for (int k = 0; k < Q; ++k) b += cBy[k] * sZ[le][iz][k * Q + qx];
                     sX[le][iz][qy * Q + qx] = b;
@@ -505,11 +506,11 @@ k_mass(const double *__restrict__ mq, const double *__restrict__ x,
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
                     const int li = (iz * D + qy) * D + qx;
-                    double r = 0.0;
+                    R r = 0.0;
 #pragma unroll
                     for (int k = 0; k < Q; ++k) r += cBx[k] * sX[le][iz][qy * Q + k];
                     atomicAdd(&acc[3 * sSl[le][li] + c], r);
-                    if (DOT) dot += r * sU[le][c][li];
+                    if (DOT) dot += (double)r * (double)sU[le][c][li];
                 }
             }
             wave_sync();  // sX is rewritten by the next component
@@ -566,15 +567,16 @@ __global__ void k_zero_nodes(const int32_t *__restrict__ nodes, int n, double *_
     y[2 * ncomp + g] = 0.0;
 }
 
-// out[perm[k]][:] = in[k][:] (patch order -> caller order)
-__global__ void k_unpermute_rows(const double *__restrict__ in, const int32_t *__restrict__ perm,
+// out[perm[k]][:] = in[k][:] (patch order -> caller order), widened to FP64
+template <typename R>
+__global__ void k_unpermute_rows(const R *__restrict__ in, const int32_t *__restrict__ perm,
                                  long long rows, int len, double *__restrict__ out)
 {
     const long long n = rows * len;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const long long r = i / len, j = i % len;
-        out[(long long)perm[r] * len + j] = in[i];
+        out[(long long)perm[r] * len + j] = (double)in[i];
     }
 }
 
@@ -587,12 +589,12 @@ __global__ void k_unpermute_rows(const double *__restrict__ in, const int32_t *_
 //   mu = rho l (q1 c_s + q2 l max(0, -tr eps)); sigma = -p I + mu eps;
 //   S = w detJ sigma J^-T.
 // INIT mode writes m_q = rho0 detJ0 w instead of S.
-template <int D, int Q, bool INIT>
+template <int D, int Q, bool INIT, typename RS>
 __global__ void __launch_bounds__(pt_ne(Q) * Q * Q * Q)
 k_qdata(const double *__restrict__ x, const double *__restrict__ v,
         const double *__restrict__ e, const int32_t *__restrict__ map,
         const int32_t *__restrict__ perm, long long ncomp,
-        int node_off, double *__restrict__ mq, double *__restrict__ S, int E,
+        int node_off, double *__restrict__ mq, RS *__restrict__ S, int E,
         const double *__restrict__ tab, QParams prm, long long *__restrict__ min_key,
         int *__restrict__ nonfinite)
 {
@@ -725,7 +727,7 @@ k_qdata(const double *__restrict__ x, const double *__restrict__ v,
         const double ell = cbrt(detJ) * prm.inv_order;
         const double mu = rho * ell * (prm.q1 * cs + prm.q2 * ell * fmax(-tr, 0.0));
         const double wd = w * detJ;
-        double *__restrict__ Se = S + el * 9 * Q3;
+        RS *__restrict__ Se = S + el * 9 * Q3;
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -738,7 +740,7 @@ k_qdata(const double *__restrict__ x, const double *__restrict__ v,
                 }
                 sv *= wd;
                 if (!isfinite(sv)) nf = true;
-                Se[(c * 3 + d) * Q3 + q] = sv;
+                Se[(c * 3 + d) * Q3 + q] = (RS)sv;
             }
     }
     if (act) {
@@ -753,67 +755,94 @@ k_qdata(const double *__restrict__ x, const double *__restrict__ v,
 }
 
 // ---------------------------------------------------------------- launchers
-template <int D, int Q>
+// R: real type of S, m_q and the contractions (double, or float in the
+// FP32 precision form); the quadrature-data algebra always runs in FP64.
+template <int D, int Q, typename R>
 struct Launch {
     static constexpr int NEp = pt_ne(Q);
 
-    static void force(const double *S, const double *e, const PatchDev &pd, double *y,
-                      long long ncomp, const double *tab, hipStream_t st)
+    static void force(const void *S, const double *e, const PatchDev &pd, double *y,
+                      long long ncomp, const void *tab, hipStream_t st)
     {
-        const dim3 grid(pd.n_patch), block(force_waves(D, Q) * 64);
+        const dim3 grid(pd.n_patch), block(force_waves(D, Q, sizeof(R)) * 64);
         if (e)
-            hipLaunchKernelGGL((k_force<D, Q, false>), grid, block, 0, st, S, e, pd.perm, pd.slot,
-                               pd.pn, pd.ptab, y, pd.part, ncomp, tab);
+            hipLaunchKernelGGL((k_force<D, Q, false, R>), grid, block, 0, st, (const R *)S, e,
+                               pd.perm, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab);
         else
-            hipLaunchKernelGGL((k_force<D, Q, true>), grid, block, 0, st, S, e, pd.perm, pd.slot,
-                               pd.pn, pd.ptab, y, pd.part, ncomp, tab);
+            hipLaunchKernelGGL((k_force<D, Q, true, R>), grid, block, 0, st, (const R *)S, e,
+                               pd.perm, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab);
     }
-    static void force_t(const double *S, const double *v, const PatchDev &pd, int E, double *z,
-                        long long ncomp, const double *tab, hipStream_t st)
+    static void force_t(const void *S, const double *v, const PatchDev &pd, int E, double *z,
+                        long long ncomp, const void *tab, hipStream_t st)
     {
         (void)E;
-        hipLaunchKernelGGL((k_force_t<D, Q>), dim3(pd.n_patch), dim3(force_t_waves(D, Q) * 64), 0,
-                           st, S, v, pd.perm, pd.slot, pd.pn, pd.ptab, z, ncomp, tab);
+        hipLaunchKernelGGL((k_force_t<D, Q, R>), dim3(pd.n_patch),
+                           dim3(force_t_waves(D, Q, sizeof(R)) * 64), 0, st, (const R *)S, v,
+                           pd.perm, pd.slot, pd.pn, pd.ptab, z, ncomp, (const R *)tab);
     }
-    static void mass(const double *mq, const double *x, const PatchDev &pd, double *y,
-                     long long ncomp, const double *tab, double *part_dot, const int *skip,
+    static void mass(const void *mq, const double *x, const PatchDev &pd, double *y,
+                     long long ncomp, const void *tab, double *part_dot, const int *skip,
                      hipStream_t st)
     {
-        const dim3 grid(pd.n_patch), block(mass_waves(D, Q) * 64);
+        const dim3 grid(pd.n_patch), block(mass_waves(D, Q, sizeof(R)) * 64);
         if (part_dot)
-            hipLaunchKernelGGL((k_mass<D, Q, true>), grid, block, 0, st, mq, x, pd.map, pd.slot,
-                               pd.pn, pd.ptab, y, pd.part, ncomp, tab, part_dot, skip);
+            hipLaunchKernelGGL((k_mass<D, Q, true, R>), grid, block, 0, st, (const R *)mq, x,
+                               pd.map, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab,
+                               part_dot, skip);
         else
-            hipLaunchKernelGGL((k_mass<D, Q, false>), grid, block, 0, st, mq, x, pd.map, pd.slot,
-                               pd.pn, pd.ptab, y, pd.part, ncomp, tab, part_dot, skip);
+            hipLaunchKernelGGL((k_mass<D, Q, false, R>), grid, block, 0, st, (const R *)mq, x,
+                               pd.map, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab,
+                               part_dot, skip);
     }
+    // tab: the FP64 table (the algebra is FP64); S receives R values
     static void qdata(const double *x, const double *v, const double *e, const PatchDev &pd, int E,
-                      long long ncomp, int node_off, double *mq, double *S, const double *tab,
+                      long long ncomp, int node_off, double *mq, void *S, const double *tab,
                       QParams prm, long long *min_key, int *nonfinite, bool init, hipStream_t st)
     {
         const dim3 grid((E + NEp - 1) / NEp), block(NEp * Q * Q * Q);
         if (init)
-            hipLaunchKernelGGL((k_qdata<D, Q, true>), grid, block, 0, st, x, v, e, pd.map, pd.perm,
-                               ncomp, node_off, mq, S, E, tab, prm, min_key, nonfinite);
+            hipLaunchKernelGGL((k_qdata<D, Q, true, R>), grid, block, 0, st, x, v, e, pd.map,
+                               pd.perm, ncomp, node_off, mq, (R *)S, E, tab, prm, min_key,
+                               nonfinite);
         else
-            hipLaunchKernelGGL((k_qdata<D, Q, false>), grid, block, 0, st, x, v, e, pd.map,
-                               pd.perm, ncomp, node_off, mq, S, E, tab, prm, min_key, nonfinite);
+            hipLaunchKernelGGL((k_qdata<D, Q, false, R>), grid, block, 0, st, x, v, e, pd.map,
+                               pd.perm, ncomp, node_off, mq, (R *)S, E, tab, prm, min_key,
+                               nonfinite);
     }
 };
 
 #define FEPA_PQ_LIST(X) \
     X(1, 2) X(1, 3) X(1, 4) X(2, 3) X(2, 4) X(2, 5) X(3, 4) X(3, 5) X(3, 6) X(4, 5) X(4, 6) X(4, 7)
 
-const KernelSet *fp64_kernels(int p, int Q)
+template <typename R>
+static const KernelSet *kernels_for(int p, int Q)
 {
-#define FEPA_ENTRY(P, QQ)                                                                    \
-    static const KernelSet ks_##P##_##QQ = {Launch<P + 1, QQ>::force, Launch<P + 1, QQ>::force_t, \
-                                            Launch<P + 1, QQ>::mass, Launch<P + 1, QQ>::qdata,   \
-                                            patch_umax(P + 1)};                                  \
+#define FEPA_ENTRY(P, QQ)                                                                        \
+    static const KernelSet ks_##P##_##QQ = {                                                     \
+        Launch<P + 1, QQ, R>::force, Launch<P + 1, QQ, R>::force_t, Launch<P + 1, QQ, R>::mass, \
+        Launch<P + 1, QQ, R>::qdata, patch_umax(P + 1)};                                         \
     if (p == P && Q == QQ) return &ks_##P##_##QQ;
     FEPA_PQ_LIST(FEPA_ENTRY)
 #undef FEPA_ENTRY
     return nullptr;
+}
+
+const KernelSet *fp64_kernels(int p, int Q) { return kernels_for<double>(p, Q); }
+const KernelSet *fp32_kernels(int p, int Q) { return kernels_for<float>(p, Q); }
+
+__global__ void k_f64_to_f32(const double *__restrict__ in, float *__restrict__ out, long long n)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = (float)in[i];
+}
+
+void launch_f64_to_f32(const double *in, float *out, long long n, hipStream_t st)
+{
+    long long blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) return;
+    hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)blocks), dim3(256), 0, st, in, out, n);
 }
 
 void launch_gather_shared(const PatchDev &pd, double *y, long long ncomp, const int *skip,
@@ -832,14 +861,18 @@ void launch_zero_nodes(const int32_t *nodes, int n, double *y, long long ncomp, 
                        skip);
 }
 
-void launch_unpermute_rows(const double *in, const int32_t *perm, long long rows, int len,
-                           double *out, hipStream_t st)
+void launch_unpermute_rows(const void *in, bool in_f32, const int32_t *perm, long long rows,
+                           int len, double *out, hipStream_t st)
 {
     long long blocks = (rows * len + 255) / 256;
     if (blocks > 65535) blocks = 65535;
     if (blocks < 1) return;
-    hipLaunchKernelGGL(k_unpermute_rows, dim3((unsigned)blocks), dim3(256), 0, st, in, perm, rows,
-                       len, out);
+    if (in_f32)
+        hipLaunchKernelGGL(k_unpermute_rows<float>, dim3((unsigned)blocks), dim3(256), 0, st,
+                           (const float *)in, perm, rows, len, out);
+    else
+        hipLaunchKernelGGL(k_unpermute_rows<double>, dim3((unsigned)blocks), dim3(256), 0, st,
+                           (const double *)in, perm, rows, len, out);
 }
 
 __global__ void k_reset_diag(long long *__restrict__ key, int *__restrict__ flag)

@@ -29,22 +29,27 @@ struct PatchDev {
 };
 
 // Launchers of one (p, Q) instance; ncomp is the component stride of H1 vectors.
+// S, m_q and tab of force/force_t/mass are of the set's real type (double for
+// fp64_kernels, float for fp32_kernels); qdata always takes the FP64 table and
+// writes S in the set's real type.
 struct KernelSet {
-    void (*force)(const double *S, const double *e, const PatchDev &pd, double *y,
-                  long long ncomp, const double *tab, hipStream_t st);
-    void (*force_t)(const double *S, const double *v, const PatchDev &pd, int E, double *z,
-                    long long ncomp, const double *tab, hipStream_t st);
-    void (*mass)(const double *mq, const double *x, const PatchDev &pd, double *y,
-                 long long ncomp, const double *tab, double *part_dot, const int *skip,
+    void (*force)(const void *S, const double *e, const PatchDev &pd, double *y,
+                  long long ncomp, const void *tab, hipStream_t st);
+    void (*force_t)(const void *S, const double *v, const PatchDev &pd, int E, double *z,
+                    long long ncomp, const void *tab, hipStream_t st);
+    void (*mass)(const void *mq, const double *x, const PatchDev &pd, double *y,
+                 long long ncomp, const void *tab, double *part_dot, const int *skip,
                  hipStream_t st);
     void (*qdata)(const double *x, const double *v, const double *e, const PatchDev &pd, int E,
-                  long long ncomp, int node_off, double *mq, double *S, const double *tab,
+                  long long ncomp, int node_off, double *mq, void *S, const double *tab,
                   QParams prm, long long *min_key, int *nonfinite, bool init, hipStream_t st);
     int umax;  // distinct-node capacity of a patch for this order
 };
 
 // nullptr when (p, Q) is not instantiated.
 const KernelSet *fp64_kernels(int p, int Q);
+const KernelSet *fp32_kernels(int p, int Q);
+void launch_f64_to_f32(const double *in, float *out, long long n, hipStream_t st);
 
 // y[c][g] for the shared nodes of a patch plan (after force or mass patches).
 void launch_gather_shared(const PatchDev &pd, double *y, long long ncomp, const int *skip,
@@ -52,9 +57,9 @@ void launch_gather_shared(const PatchDev &pd, double *y, long long ncomp, const 
 // y[c][g] = 0 for the listed nodes
 void launch_zero_nodes(const int32_t *nodes, int n, double *y, long long ncomp, const int *skip,
                        hipStream_t st);
-// out[perm[k]][:] = in[k][:]
-void launch_unpermute_rows(const double *in, const int32_t *perm, long long rows, int len,
-                           double *out, hipStream_t st);
+// out[perm[k]][:] = in[k][:] (in is float when in_f32, else double)
+void launch_unpermute_rows(const void *in, bool in_f32, const int32_t *perm, long long rows,
+                           int len, double *out, hipStream_t st);
 void launch_fill(double *y, long long n, double val, hipStream_t st);
 // *key = INT64_MAX (empty min of ordered detJ keys), *flag = 0; either may be NULL.
 void launch_reset_diag(long long *key, int *flag, hipStream_t st);
