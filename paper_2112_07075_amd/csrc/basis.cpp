@@ -11,7 +11,11 @@
 #include "basis.hpp"
 
 #include <cmath>
+#include <cstdint>
+#include <cstring>
 #include <vector>
+
+#include "kern_common.hpp"
 
 namespace fepa {
 
@@ -120,6 +124,44 @@ std::vector<double> build_table(int p, int Q)
         tab[2 * Q * D + Q * DL + q] = wq[q];
     }
     return tab;
+}
+
+static uint16_t bf16_bits(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // NaN stays NaN
+    u += 0x7fffu + ((u >> 16) & 1u);                                           // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+std::vector<unsigned char> build_mfma_table(int p, int Q, const std::vector<double> &tab)
+{
+    const int D = p + 1, DL = p;
+    const MfmaLayout M = mfma_layout(D, Q);
+    std::vector<unsigned char> out((size_t)M.bytes, 0);
+    float *ft = (float *)out.data();
+    for (size_t k = 0; k < tab.size() && (int)k < M.tabf; ++k) ft[k] = (float)tab[k];
+    (void)DL;
+    uint16_t *fr = (uint16_t *)(out.data() + (size_t)M.tabf * 4);
+    const double *B = tab.data(), *G = tab.data() + Q * D;
+    for (int ct = 0; ct < M.nt; ++ct)
+        for (int d = 0; d < 3; ++d)
+            for (int s = 0; s < M.ns; ++s)
+                for (int l = 0; l < 64; ++l)
+                    for (int j = 0; j < 8; ++j) {
+                        const int q = s * 32 + (l / 16) * 8 + j, i = ct * 16 + l % 16;
+                        double v = 0.0;
+                        if (q < M.q3 && i < M.d3) {
+                            const int qx = q % Q, qy = (q / Q) % Q, qz = q / (Q * Q);
+                            const int ix = i % D, iy = (i / D) % D, iz = i / (D * D);
+                            const double bx = B[qx * D + ix], by = B[qy * D + iy], bz = B[qz * D + iz];
+                            const double gx = G[qx * D + ix], gy = G[qy * D + iy], gz = G[qz * D + iz];
+                            v = d == 0 ? gx * by * bz : (d == 1 ? bx * gy * bz : bx * by * gz);
+                        }
+                        fr[((((size_t)ct * 3 + d) * M.ns + s) * 64 + l) * 8 + j] = bf16_bits((float)v);
+                    }
+    return out;
 }
 
 }  // namespace fepa

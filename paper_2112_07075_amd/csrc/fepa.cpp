@@ -31,7 +31,9 @@ struct MeshRec {
     long long part_off = 0;  // into the CG dot-partial array (one per patch)
     int tab_slot = 0;        // into the table buffer (doubles)
     const KernelSet *ks = nullptr;   // FP64 kernels
-    const KernelSet *ksl = nullptr;  // kernels of the context's precision (== ks for FP64)
+    KernelSet kl{};                  // kernels of the context's precision
+    long long Sb_off = 0;            // offset of the mesh's S in the stored type
+    long long tabb_off = 0;          // BF16 form: byte offset of its operand buffer
     double rho0 = 1.0;
     PatchDev pd;             // device patch plan
     const int32_t *orphans = nullptr;
@@ -55,10 +57,13 @@ struct fe_ctx {
     hipStream_t st = nullptr;
     int device = 0;
     long long E_tot = 0, N_tot = 0, L2_tot = 0, S_len = 0, mq_len = 0;
+    long long Sb_len = 0;  // S entries in the stored layout
     bool uniform_pq = true;
     // device memory owned by the context
     bool lo = false;                  // FP32 storage and contractions (precision form)
-    void *S = nullptr;                // [E][9][Q^3], double or float
+    bool bf = false;                  // BF16 S, MFMA force contractions (precision form)
+    void *S = nullptr;                // [E][9][Q^3] double / float, or [E][9][Q3P] BF16
+    unsigned char *tabsb = nullptr;   // BF16 form operand buffers
     double *mq = nullptr, *tabs = nullptr;
     float *mq32 = nullptr, *tabs32 = nullptr;
     double *ref_r = nullptr, *ref_d = nullptr;  // refinement vectors
@@ -120,7 +125,7 @@ void free_all(fe_ctx *c)
 {
     if (!c) return;
     if (c->st) (void)hipStreamSynchronize(c->st);
-    void *dptrs[] = {c->S, c->mq, c->tabs, c->mq32, c->tabs32, c->ref_r, c->ref_d, c->min_key,
+    void *dptrs[] = {c->S, c->mq, c->tabs, c->mq32, c->tabs32, c->tabsb, c->ref_r, c->ref_d, c->min_key,
                      c->nonfinite, c->r, c->p, c->Ap, c->part, c->part2, c->scal, c->fr, c->cg,
                      c->bad};
     for (void *d : dptrs)
@@ -181,10 +186,12 @@ bool supported_pq(int p, int Q) { return fp64_kernels(p, Q) != nullptr; }
 // typed views of the context's stored data for one mesh
 static void *S_of(fe_ctx *c, const MeshRec &r)
 {
-    return c->lo ? (void *)((float *)c->S + r.S_off) : (void *)((double *)c->S + r.S_off);
+    if (c->bf) return (void *)((uint16_t *)c->S + r.Sb_off);
+    return c->lo ? (void *)((float *)c->S + r.Sb_off) : (void *)((double *)c->S + r.Sb_off);
 }
 static const void *tab_of(fe_ctx *c, const MeshRec &r)
 {
+    if (c->bf) return (const void *)(c->tabsb + r.tabb_off);
     return c->lo ? (const void *)(c->tabs32 + r.tab_slot) : (const void *)(c->tabs + r.tab_slot);
 }
 
@@ -233,7 +240,7 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
     }
     if (!(o.gamma > 1.0) || !(o.q1 >= 0.0) || !(o.q2 >= 0.0))
         return fail(nullptr, FE_EINVAL, "gamma must be > 1 and q1, q2 >= 0%s");
-    if (o.precision != FE_PREC_FP64 && o.precision != FE_PREC_FP32)
+    if (o.precision != FE_PREC_FP64 && o.precision != FE_PREC_FP32 && o.precision != FE_PREC_BF16)
         return fail(nullptr, FE_EUNSUPPORTED, "precision not provided by this build%s");
     if (o.flags & ~(FE_OPT_TIMERS | FE_OPT_BATCHED | FE_OPT_GRAPH))
         return fail(nullptr, FE_EINVAL, "unknown option flags%s");
@@ -246,6 +253,8 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
             return fail(nullptr, FE_EUNSUPPORTED, "q1d must be in [order+1, order+3]%s");
         if (!supported_pq(d.order, d.q1d))
             return fail(nullptr, FE_EUNSUPPORTED, "(order, q1d) not built%s");
+        if (o.precision == FE_PREC_BF16 && !bf16_force(d.order, d.q1d))
+            return fail(nullptr, FE_EUNSUPPORTED, "(order, q1d) has no BF16 MFMA instance%s");
         if (!d.elem_nodes || !d.x0) return fail(nullptr, FE_EINVAL, "NULL mesh array%s");
         if (!(d.rho0 > 0.0)) return fail(nullptr, FE_EINVAL, "rho0 must be > 0%s");
         const long long D3 = (long long)(d.order + 1) * (d.order + 1) * (d.order + 1);
@@ -259,6 +268,7 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
     if (!ctx) return fail(nullptr, FE_ENOMEM, "host allocation failed%s");
     ctx->opts = o;
     ctx->lo = o.precision != FE_PREC_FP64;
+    ctx->bf = o.precision == FE_PREC_BF16;
     ctx->st = (hipStream_t)hip_stream;
     auto bail = [&](int code) {
         g_setup_error = ctx->err;
@@ -283,12 +293,17 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         r.N = d.n_nodes;
         r.rho0 = d.rho0;
         r.ks = fp64_kernels(r.p, r.Q);
-        r.ksl = ctx->lo ? fp32_kernels(r.p, r.Q) : r.ks;
+        r.kl = ctx->lo ? *fp32_kernels(r.p, r.Q) : *r.ks;
+        if (ctx->bf) {
+            r.kl.force = bf16_force(r.p, r.Q);
+            bf16_parts(r.p, r.Q, &r.kl);
+        }
         const long long Q3 = (long long)r.Q * r.Q * r.Q;
         r.node_off = ctx->N_tot;
         r.elem_off = ctx->E_tot;
         r.l2_off = ctx->L2_tot;
         r.S_off = ctx->S_len;
+        r.Sb_off = ctx->Sb_len;
         r.mq_off = ctx->mq_len;
         auto key = std::make_pair(r.p, r.Q);
         if (!slot_of.count(key)) {
@@ -302,6 +317,7 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         ctx->E_tot += r.E;
         ctx->L2_tot += (long long)r.E * r.p * r.p * r.p;
         ctx->S_len += 9 * Q3 * r.E;
+        ctx->Sb_len += 9 * (ctx->bf ? (Q3 + 31) / 32 * 32 : Q3) * r.E;
         ctx->mq_len += Q3 * r.E;
         if (m > 0 && (r.p != ctx->mesh[0].p || r.Q != ctx->mesh[0].Q)) ctx->uniform_pq = false;
         ctx->mesh.push_back(r);
@@ -314,8 +330,10 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
     long long qb = 0, wb = 0;
     int rc = FE_OK;
     if (ctx->lo) {
-        float *S32 = nullptr;
-        if ((rc = dev_alloc(ctx, &S32, ctx->S_len, &qb)) || (rc = dev_alloc(ctx, &ctx->mq32, ctx->mq_len, &qb)) ||
+        void *S32 = nullptr;
+        if ((rc = ctx->bf ? dev_alloc(ctx, (uint16_t **)&S32, ctx->Sb_len, &qb)
+                          : dev_alloc(ctx, (float **)&S32, ctx->Sb_len, &qb)) ||
+            (rc = dev_alloc(ctx, &ctx->mq32, ctx->mq_len, &qb)) ||
             (rc = dev_alloc(ctx, &ctx->tabs32, (long long)tab_host.size(), &wb)) ||
             (rc = dev_alloc(ctx, &ctx->ref_r, 3 * ctx->N_tot, &wb)) ||
             (rc = dev_alloc(ctx, &ctx->ref_d, 3 * ctx->N_tot, &wb))) {
@@ -360,6 +378,27 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         return bail(FE_EDEVICE);
     }
     if (ctx->lo) launch_f64_to_f32(ctx->tabs, ctx->tabs32, (long long)tab_host.size(), ctx->st);
+    if (ctx->bf) {
+        std::vector<unsigned char> tb;
+        std::map<std::pair<int, int>, long long> boff;
+        for (MeshRec &r : ctx->mesh) {
+            auto key = std::make_pair(r.p, r.Q);
+            if (!boff.count(key)) {
+                boff[key] = (long long)tb.size();
+                std::vector<double> t = build_table(r.p, r.Q);
+                std::vector<unsigned char> m = build_mfma_table(r.p, r.Q, t);
+                tb.insert(tb.end(), m.begin(), m.end());
+                while (tb.size() % 256) tb.push_back(0);
+            }
+            r.tabb_off = boff[key];
+        }
+        if ((rc = dev_alloc(ctx, &ctx->tabsb, (long long)tb.size(), &wb))) return bail(rc);
+        if (hipMemcpy(ctx->tabsb, tb.data(), tb.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemsetAsync(ctx->S, 0, 2 * (size_t)ctx->Sb_len, ctx->st) != hipSuccess) {
+            ctx->err = "upload failed";
+            return bail(FE_EDEVICE);
+        }
+    }
 
     // patch plans (element order, distinct nodes, shared-node gather) per mesh
     auto upload = [&](const void *src, size_t bytes, void **dst) -> int {
@@ -501,7 +540,7 @@ int fe_qdata_update(fe_ctx_t *ctx, const double *x, const double *v, const doubl
         for (const MeshRec &r : ctx->mesh) {
             QParams prm{r.rho0, ctx->opts.gamma, ctx->opts.gamma - 1.0, ctx->opts.q1, ctx->opts.q2,
                         1.0 / r.p};
-            r.ksl->qdata(x, v, e + r.l2_off, r.pd, r.E, ctx->N_tot, 0, ctx->mq + r.mq_off,
+            r.kl.qdata(x, v, e + r.l2_off, r.pd, r.E, ctx->N_tot, 0, ctx->mq + r.mq_off,
                         S_of(ctx, r), ctx->tabs + r.tab_slot, prm, ctx->min_key,
                         ctx->nonfinite, false, ctx->st);
         }
@@ -518,7 +557,7 @@ int fe_force_mult(fe_ctx_t *ctx, const double *e, double *y)
     {
         ScopedTimer tm(ctx, FE_TIMER_FORCE);
         for (const MeshRec &r : ctx->mesh) {
-            r.ksl->force(S_of(ctx, r), e ? e + r.l2_off : nullptr, r.pd, y, ctx->N_tot,
+            r.kl.force(S_of(ctx, r), e ? e + r.l2_off : nullptr, r.pd, y, ctx->N_tot,
                          tab_of(ctx, r), ctx->st);
             launch_gather_shared(r.pd, y, ctx->N_tot, nullptr, ctx->st);
             launch_zero_nodes(r.orphans, r.n_orphans, y, ctx->N_tot, nullptr, ctx->st);
@@ -536,7 +575,7 @@ int fe_force_mult_T(fe_ctx_t *ctx, const double *v, double *z)
     {
         ScopedTimer tm(ctx, FE_TIMER_FORCE_T);
         for (const MeshRec &r : ctx->mesh)
-            r.ksl->force_t(S_of(ctx, r), v, r.pd, r.E, z + r.l2_off, ctx->N_tot, tab_of(ctx, r),
+            r.kl.force_t(S_of(ctx, r), v, r.pd, r.E, z + r.l2_off, ctx->N_tot, tab_of(ctx, r),
                            ctx->st);
     }
     HIP_OK(hipGetLastError());
@@ -549,7 +588,7 @@ static void mass_launch(fe_ctx *ctx, const double *x, double *y, bool dot, const
 {
     for (const MeshRec &r : ctx->mesh) {
         if (lo)
-            r.ksl->mass(ctx->mq32 + r.mq_off, x, r.pd, y, ctx->N_tot, ctx->tabs32 + r.tab_slot,
+            r.kl.mass(ctx->mq32 + r.mq_off, x, r.pd, y, ctx->N_tot, ctx->tabs32 + r.tab_slot,
                         dot ? ctx->part + r.part_off : nullptr, skip, ctx->st);
         else
             r.ks->mass(ctx->mq + r.mq_off, x, r.pd, y, ctx->N_tot, ctx->tabs + r.tab_slot,
@@ -701,7 +740,10 @@ int fe_export_qdata(fe_ctx_t *ctx, double *S_out, double *mq_out)
     if (!ctx->uniform_pq) return fail(ctx, FE_EINVAL, "export needs one (order, q1d) for all meshes%s");
     for (const MeshRec &r : ctx->mesh) {
         const int Q3 = r.Q * r.Q * r.Q;
-        if (S_out)
+        if (S_out && ctx->bf)
+            launch_unpermute_s_bf16(S_of(ctx, r), r.pd.perm, r.E, Q3, (Q3 + 31) / 32 * 32,
+                                    S_out + r.S_off, ctx->st);
+        else if (S_out)
             launch_unpermute_rows(S_of(ctx, r), ctx->lo, r.pd.perm, r.E, 9 * Q3, S_out + r.S_off,
                                   ctx->st);
         if (mq_out)

@@ -36,11 +36,126 @@ __host__ __device__ constexpr int col_ne(int Q) { return 256 / (Q * Q) > 0 ? 256
 // Elements per workgroup of the point-layout kernels (Q^3 threads each).
 __host__ __device__ constexpr int pt_ne(int Q) { return 256 / (Q * Q * Q) > 0 ? 256 / (Q * Q * Q) : 1; }
 
+// Stored quadrature data of the BF16 form pads Q^3 to a multiple of 32 (the K
+// step of one MFMA); other forms store Q^3 points.
+template <typename RS>
+__host__ __device__ constexpr int s_stride(int Q)
+{
+    return sizeof(RS) == 2 ? (Q * Q * Q + 31) / 32 * 32 : Q * Q * Q;
+}
+
+// BF16 form operand table of one (p, Q): the FP32 1-D table (Tab layout,
+// padded to 16 bytes) followed by the MFMA B-operand fragments of the dense
+// reference-gradient matrix G3[(d, q)][i] = d w_i / d xi_d at point q, for
+// v_mfma_f32_16x16x32_bf16: fragment ((ct*3 + d)*NS + s)*64 + lane holds the 8
+// values k = s*32 + (lane/16)*8 + j, column i = ct*16 + lane%16.
+struct MfmaLayout {
+    int q3, q3p, ns, d3, nt, tabf, nfrag, bytes;
+};
+__host__ __device__ constexpr MfmaLayout mfma_layout(int D, int Q)
+{
+    const int q3 = Q * Q * Q, q3p = (q3 + 31) / 32 * 32, d3 = D * D * D;
+    const int tsize = 2 * Q * D + Q * (D - 1) + Q;
+    const int tabf = (tsize + 3) / 4 * 4;
+    const int nt = (d3 + 15) / 16, ns = q3p / 32;
+    const int nfrag = nt * 3 * ns * 64;
+    return MfmaLayout{q3, q3p, ns, d3, nt, tabf, nfrag, tabf * 4 + nfrag * 16};
+}
+
 // Order-preserving map of a double onto int64 (for atomicMin of detJ).
 __device__ __forceinline__ long long ordered_key(double d)
 {
     long long b = __double_as_longlong(d);
     return b >= 0 ? b : (b ^ 0x7fffffffffffffffLL);
+}
+
+// ---------------------------------------------------------------- patches
+// Distinct-node slots per patch (UMAX) and the elements a workgroup handles
+// per pass (NE) are chosen so that the static LDS of a workgroup stays below
+// 60 KiB: at most two workgroups' worth of LDS fit a 160 KiB CU at once.
+__host__ __device__ constexpr int patch_umax(int D) { return D == 4 ? 512 : 768; }
+
+
+// Elements whose threads sit in one wave exchange data through LDS with only a
+// wave-level fence: DS instructions of a wave execute in order, so a wave never
+// waits for the other waves of its workgroup inside a patch.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Wave-local element layout: 64/Q^2 elements per wave, 4 waves per workgroup.
+__host__ __device__ constexpr int wave_ne(int Q) { return 64 / (Q * Q); }
+struct Lane {
+    int le;      // element slot in the workgroup (valid lanes only)
+    int t;       // point column qx + Q*qy
+    bool valid;  // lane carries an element column
+};
+// Idle lanes (64 not a multiple of Q^2) point at a spare slot NE whose LDS
+// scratch nobody reads.
+template <int Q, int NE>
+__device__ __forceinline__ Lane lane_map()
+{
+    constexpr int NW = wave_ne(Q), QQ = Q * Q;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    Lane L;
+    L.valid = lane < NW * QQ;
+    L.le = L.valid ? w * NW + lane / QQ : NE;
+    L.t = L.valid ? lane % QQ : 0;
+    return L;
+}
+__host__ __device__ constexpr int fit_waves(int Q, int per_elem, int fixed)
+{
+    int w = 4;
+    while (w > 1 && fixed + (w * wave_ne(Q) + 1) * per_elem > 60 * 1024) --w;
+    return w;
+}
+
+// rs = bytes of the real type of the stored data and the contractions
+__host__ __device__ constexpr int force_waves(int D, int Q, int rs)
+{
+    return fit_waves(Q, rs * (3 * D * Q * Q + 2 * D * D * Q), 3 * rs * patch_umax(D));
+}
+
+// One row of the patch table: first element, element count, offset of the
+// distinct-node list, distinct nodes U, private nodes P, shared-partial offset.
+struct PatchRow {
+    int eb, cnt, pno, U, P, sho;
+};
+__device__ __forceinline__ PatchRow load_patch(const int32_t *__restrict__ ptab, int k)
+{
+    const int32_t *r = ptab + 6 * (long long)k;
+    return PatchRow{r[0], r[1], r[2], r[3], r[4], r[5]};
+}
+
+// R^T of one patch: private nodes are stored, shared nodes leave a partial.
+// Threads first, first + stride, ... of the caller share the work.
+template <int UMAX, typename R>
+__device__ __forceinline__ void patch_write(const R *acc, const PatchRow &pr,
+                                            const int32_t *__restrict__ pn,
+                                            double *__restrict__ y, double *__restrict__ part,
+                                            long long ncomp, int first = -1, int stride = 0)
+{
+    if (first < 0) {
+        first = threadIdx.x;
+        stride = blockDim.x;
+    }
+    for (int u = first; u < pr.U; u += stride) {
+        const double a0 = (double)acc[3 * u], a1 = (double)acc[3 * u + 1], a2 = (double)acc[3 * u + 2];
+        if (u < pr.P) {
+            const long long g = pn[pr.pno + u];
+            y[g] = a0;
+            y[ncomp + g] = a1;
+            y[2 * ncomp + g] = a2;
+        } else {
+            double *dst = part + 3 * (long long)(pr.sho + u - pr.P);
+            dst[0] = a0;
+            dst[1] = a1;
+            dst[2] = a2;
+        }
+    }
 }
 
 }  // namespace fepa

@@ -17,96 +17,17 @@
 
 namespace fepa {
 
+template <typename RS>
+__device__ __forceinline__ RS cvt(double v) { return (RS)v; }
+template <>
+__device__ __forceinline__ __bf16 cvt<__bf16>(double v) { return (__bf16)(float)v; }
+
 // ---------------------------------------------------------------- helpers
 __global__ void k_fill(double *__restrict__ y, long long n, double val)
 {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (; i < n; i += stride) y[i] = val;
-}
-
-// ---------------------------------------------------------------- patches
-// Distinct-node slots per patch (UMAX) and the elements a workgroup handles
-// per pass (NE) are chosen so that the static LDS of a workgroup stays below
-// 60 KiB: at most two workgroups' worth of LDS fit a 160 KiB CU at once.
-__host__ __device__ constexpr int patch_umax(int D) { return D == 4 ? 512 : 768; }
-
-
-// Elements whose threads sit in one wave exchange data through LDS with only a
-// wave-level fence: DS instructions of a wave execute in order, so a wave never
-// waits for the other waves of its workgroup inside a patch.
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Wave-local element layout: 64/Q^2 elements per wave, 4 waves per workgroup.
-__host__ __device__ constexpr int wave_ne(int Q) { return 64 / (Q * Q); }
-struct Lane {
-    int le;      // element slot in the workgroup (valid lanes only)
-    int t;       // point column qx + Q*qy
-    bool valid;  // lane carries an element column
-};
-// Idle lanes (64 not a multiple of Q^2) point at a spare slot NE whose LDS
-// scratch nobody reads.
-template <int Q, int NE>
-__device__ __forceinline__ Lane lane_map()
-{
-    constexpr int NW = wave_ne(Q), QQ = Q * Q;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    Lane L;
-    L.valid = lane < NW * QQ;
-    L.le = L.valid ? w * NW + lane / QQ : NE;
-    L.t = L.valid ? lane % QQ : 0;
-    return L;
-}
-__host__ __device__ constexpr int fit_waves(int Q, int per_elem, int fixed)
-{
-    int w = 4;
-    while (w > 1 && fixed + (w * wave_ne(Q) + 1) * per_elem > 60 * 1024) --w;
-    return w;
-}
-
-// rs = bytes of the real type of the stored data and the contractions
-__host__ __device__ constexpr int force_waves(int D, int Q, int rs)
-{
-    return fit_waves(Q, rs * (3 * D * Q * Q + 2 * D * D * Q), 3 * rs * patch_umax(D));
-}
-
-// One row of the patch table: first element, element count, offset of the
-// distinct-node list, distinct nodes U, private nodes P, shared-partial offset.
-struct PatchRow {
-    int eb, cnt, pno, U, P, sho;
-};
-__device__ __forceinline__ PatchRow load_patch(const int32_t *__restrict__ ptab, int k)
-{
-    const int32_t *r = ptab + 6 * (long long)k;
-    return PatchRow{r[0], r[1], r[2], r[3], r[4], r[5]};
-}
-
-// R^T of one patch: private nodes are stored, shared nodes leave a partial.
-template <int UMAX, typename R>
-__device__ __forceinline__ void patch_write(const R *acc, const PatchRow &pr,
-                                            const int32_t *__restrict__ pn,
-                                            double *__restrict__ y, double *__restrict__ part,
-                                            long long ncomp)
-{
-    for (int u = threadIdx.x; u < pr.U; u += blockDim.x) {
-        const double a0 = (double)acc[3 * u], a1 = (double)acc[3 * u + 1], a2 = (double)acc[3 * u + 2];
-        if (u < pr.P) {
-            const long long g = pn[pr.pno + u];
-            y[g] = a0;
-            y[ncomp + g] = a1;
-            y[2 * ncomp + g] = a2;
-        } else {
-            double *dst = part + 3 * (long long)(pr.sho + u - pr.P);
-            dst[0] = a0;
-            dst[1] = a1;
-            dst[2] = a2;
-        }
-    }
 }
 
 // ------------------------------------------------------------------ force F e
@@ -254,9 +175,9 @@ __host__ __device__ constexpr int force_t_waves(int D, int Q, int rs)
                      3 * rs * patch_umax(D));
 }
 
-template <int D, int Q, typename R>
+template <int D, int Q, typename R, typename RS = R>
 __global__ void __launch_bounds__(force_t_waves(D, Q, sizeof(R)) * 64)
-k_force_t(const R *__restrict__ S, const double *__restrict__ v,
+k_force_t(const RS *__restrict__ S, const double *__restrict__ v,
           const int32_t *__restrict__ perm, const uint16_t *__restrict__ slot,
           const int32_t *__restrict__ pn, const int32_t *__restrict__ ptab,
           double *__restrict__ z, long long ncomp, const R *__restrict__ tab)
@@ -295,13 +216,14 @@ k_force_t(const R *__restrict__ S, const double *__restrict__ v,
         const int idx = base + le;
         const bool act = L.valid && idx < pr.cnt;
         const long long el = pr.eb + (act ? idx : 0);
-        const R *__restrict__ Se = S + el * 9 * Q3 + t;
+        constexpr int SQ = s_stride<RS>(Q);
+        const RS *__restrict__ Se = S + el * 9 * SQ + t;
         R sv[9][Q];
 #pragma unroll
         for (int cd = 0; cd < 9; ++cd)
 #pragma unroll
             for (int qz = 0; qz < Q; ++qz)
-                sv[cd][qz] = act ? __builtin_nontemporal_load(Se + cd * Q3 + qz * QQ) : (R)0;
+                sv[cd][qz] = act ? (R)__builtin_nontemporal_load(Se + cd * SQ + qz * QQ) : (R)0;
         for (int i = t; i < D3; i += QQ) sSl[le][i] = act ? slot[el * D3 + i] : 0;
         wave_sync();
         R s[Q];
@@ -727,7 +649,8 @@ k_qdata(const double *__restrict__ x, const double *__restrict__ v,
         const double ell = cbrt(detJ) * prm.inv_order;
         const double mu = rho * ell * (prm.q1 * cs + prm.q2 * ell * fmax(-tr, 0.0));
         const double wd = w * detJ;
-        RS *__restrict__ Se = S + el * 9 * Q3;
+        constexpr int SQ = s_stride<RS>(Q);
+        RS *__restrict__ Se = S + el * 9 * SQ;
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -740,7 +663,7 @@ k_qdata(const double *__restrict__ x, const double *__restrict__ v,
                 }
                 sv *= wd;
                 if (!isfinite(sv)) nf = true;
-                Se[(c * 3 + d) * Q3 + q] = (RS)sv;
+                Se[(c * 3 + d) * SQ + q] = cvt<RS>(sv);
             }
     }
     if (act) {
@@ -828,6 +751,44 @@ static const KernelSet *kernels_for(int p, int Q)
 }
 
 const KernelSet *fp64_kernels(int p, int Q) { return kernels_for<double>(p, Q); }
+
+// BF16 form: F^T v reads BF16 S with FP32 contractions; qdata writes BF16 S.
+template <int D, int Q>
+struct LaunchBf16 {
+    static void force_t(const void *S, const double *v, const PatchDev &pd, int E, double *z,
+                        long long ncomp, const void *tab, hipStream_t st)
+    {
+        (void)E;
+        hipLaunchKernelGGL((k_force_t<D, Q, float, __bf16>), dim3(pd.n_patch),
+                           dim3(force_t_waves(D, Q, sizeof(float)) * 64), 0, st,
+                           (const __bf16 *)S, v, pd.perm, pd.slot, pd.pn, pd.ptab, z, ncomp,
+                           (const float *)tab);
+    }
+    static void qdata(const double *x, const double *v, const double *e, const PatchDev &pd, int E,
+                      long long ncomp, int node_off, double *mq, void *S, const double *tab,
+                      QParams prm, long long *min_key, int *nonfinite, bool init, hipStream_t st)
+    {
+        constexpr int NEp = pt_ne(Q);
+        const dim3 grid((E + NEp - 1) / NEp), block(NEp * Q * Q * Q);
+        (void)init;
+        hipLaunchKernelGGL((k_qdata<D, Q, false, __bf16>), grid, block, 0, st, x, v, e, pd.map,
+                           pd.perm, ncomp, node_off, mq, (__bf16 *)S, E, tab, prm, min_key,
+                           nonfinite);
+    }
+};
+
+bool bf16_parts(int p, int Q, KernelSet *ks)
+{
+#define FEPA_ENTRY(P, QQ)                                   \
+    if (p == P && Q == QQ) {                                \
+        ks->force_t = LaunchBf16<P + 1, QQ>::force_t;       \
+        ks->qdata = LaunchBf16<P + 1, QQ>::qdata;           \
+        return true;                                        \
+    }
+    FEPA_PQ_LIST(FEPA_ENTRY)
+#undef FEPA_ENTRY
+    return false;
+}
 const KernelSet *fp32_kernels(int p, int Q) { return kernels_for<float>(p, Q); }
 
 __global__ void k_f64_to_f32(const double *__restrict__ in, float *__restrict__ out, long long n)

@@ -49,6 +49,17 @@ struct KernelSet {
 // nullptr when (p, Q) is not instantiated.
 const KernelSet *fp64_kernels(int p, int Q);
 const KernelSet *fp32_kernels(int p, int Q);
+// BF16 form: fills force_t (BF16 S, FP32 contractions) and qdata (writes BF16 S).
+bool bf16_parts(int p, int Q, KernelSet *ks);
+// BF16 form: MFMA force launcher (nullptr when (p, Q) has no MFMA instance).
+using ForceFn = void (*)(const void *S, const double *e, const PatchDev &pd, double *y,
+                         long long ncomp, const void *tab, hipStream_t st);
+ForceFn bf16_force(int p, int Q);
+// Size in bytes of the MFMA operand table of (p, Q) (0 when unsupported).
+int mfma_btab_bytes(int p, int Q);
+// BF16 S (rows of 9 x Q3P) -> caller-ordered FP64 [rows][9][Q^3]
+void launch_unpermute_s_bf16(const void *in, const int32_t *perm, long long rows, int q3, int q3p,
+                             double *out, hipStream_t st);
 void launch_f64_to_f32(const double *in, float *out, long long n, hipStream_t st);
 
 // y[c][g] for the shared nodes of a patch plan (after force or mass patches).

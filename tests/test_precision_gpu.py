@@ -15,6 +15,9 @@ pytestmark = pytest.mark.gpu
 
 # FP32 unit roundoff is 6e-8; the actions sum 100-1000 terms per output.
 FP32_BOUND = 2e-6
+# BF16 keeps 8 significant bits (unit roundoff 2^-9): S and the gradient table
+# are each rounded once, products accumulate in FP32.
+BF16_BOUND = 2e-2
 
 
 @pytest.fixture(scope="module")
@@ -78,11 +81,44 @@ def test_fp32_outputs_against_oracle(torch_cuda, p, Q):
     assert max(errs["F1"], errs["FTv"]) > 1e-10
 
 
+@pytest.mark.parametrize("p,Q", [(1, 3), (2, 4), (3, 5)])
+def test_bf16_outputs_against_oracle(torch_cuda, p, Q):
+    c = make_case(3, p, Q, seed=32, permute=3, compress=0.3)
+    ctx, g = run_actions(torch_cuda, c, fe.FE_PREC_BF16)
+    qd = oracle_qdata(c)
+    M, S = c.mesh.elem_nodes, qd["S"]
+    errs = {
+        "S": rel_elem(g["S"], S.reshape(c.E, -1)),
+        "F1": rel_cw(g["F1"], O.force_mult(M, p, Q, c.N, S), O.force_mult(M, p, Q, c.N, S, absmode=True)),
+        "Fe": rel_cw(g["Fe"], O.force_mult(M, p, Q, c.N, S, c.e),
+                     O.force_mult(M, p, Q, c.N, S, c.e, absmode=True)),
+        "FTv": rel_cw(g["FTv"], O.force_mult_T(M, p, Q, c.N, S, c.v),
+                      O.force_mult_T(M, p, Q, c.N, S, c.v, absmode=True)),
+        "Mx": rel_cw(g["Mx"], O.mass_mult(M, p, Q, c.N, qd["mq"], g["xr"]),
+                     O.mass_mult(M, p, Q, c.N, qd["mq"], g["xr"], absmode=True)),
+    }
+    print(f"BF16 p={p} Q={Q}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    assert errs["S"] < 4e-3            # one BF16 rounding (2^-9 relative) per entry
+    for k in ("F1", "Fe", "FTv"):
+        assert errs[k] < BF16_BOUND, (k, errs[k])
+    assert errs["Mx"] < FP32_BOUND      # the mass operator of this form is FP32
+
+
+def test_bf16_unsupported_pairs_are_rejected(torch_cuda):
+    c = make_case(1, 4, 6)
+    with pytest.raises(fe.FepaError) as ei:
+        fe.fe_pa_setup(fe.MeshDesc(c.mesh.elem_nodes, dev(torch_cuda, c.mesh.x0), 4, 6),
+                       fe.Opts(precision=fe.FE_PREC_BF16))
+    assert ei.value.status == fe.FE_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("ess", [False, True])
-def test_fp32_refinement_reaches_fp64_accuracy(torch_cuda, ess):
+def test_refinement_reaches_fp64_accuracy(torch_cuda, ess, prec):
     c = make_case(4, 2, 4, seed=6)
     x0 = dev(torch_cuda, c.mesh.x0)
-    ctx = fe.fe_pa_setup(fe.MeshDesc(c.mesh.elem_nodes, x0, 2, 4), fe.Opts(precision=fe.FE_PREC_FP32))
+    precision = fe.FE_PREC_FP32 if prec == "fp32" else fe.FE_PREC_BF16
+    ctx = fe.fe_pa_setup(fe.MeshDesc(c.mesh.elem_nodes, x0, 2, 4), fe.Opts(precision=precision))
     mq = oracle_qdata(c)["mq"]
     rng = np.random.default_rng(3)
     xs = rng.standard_normal((3, c.N))
@@ -94,7 +130,7 @@ def test_fp32_refinement_reaches_fp64_accuracy(torch_cuda, ess):
     rc, it, rr = fe.fe_mass_cg(ctx, dev(torch_cuda, b), xg,
                                None if ess_idx is None else dev(torch_cuda, ess_idx), rel_tol=1e-12)
     xg = xg.cpu().numpy()
-    print(f"FP32 refinement: {it} inner iterations, residual {rr:.2e}", flush=True)
+    print(f"{prec} refinement: {it} inner iterations, residual {rr:.2e}", flush=True)
     assert rc == fe.FE_OK and rr <= 1e-12
     assert np.linalg.norm(xg - xs) < 1e-9 * np.linalg.norm(xs)
 
@@ -115,7 +151,8 @@ def test_fp32_full_size_c4_sampled(torch_cuda):
     zo = O.force_mult_T(M, 3, 5, c.N, qd["S"], c.v, elems=el)
     za = O.force_mult_T(M, 3, 5, c.N, qd["S"], c.v, elems=el, absmode=True)
     res = {}
-    for name, prec in (("fp64", fe.FE_PREC_FP64), ("fp32", fe.FE_PREC_FP32)):
+    for name, prec in (("fp64", fe.FE_PREC_FP64), ("fp32", fe.FE_PREC_FP32),
+                       ("bf16", fe.FE_PREC_BF16)):
         ctx, g = run_actions(torch_cuda, c, prec)
         res[name] = (rel_cw(g["F1"][:, nodes], y1o[:, nodes], y1a[:, nodes]),
                      rel_cw(g["FTv"][el], zo[el], za[el]))
@@ -123,3 +160,4 @@ def test_fp32_full_size_c4_sampled(torch_cuda):
     print(f"C4 sampled errors (F.1, F^T.v): {res}", flush=True)
     assert max(res["fp64"]) < 1e-12
     assert max(res["fp32"]) < FP32_BOUND
+    assert max(res["bf16"]) < BF16_BOUND
