@@ -310,14 +310,14 @@ k_force_t(const RS *__restrict__ S, const double *__restrict__ v,
 }
 
 // -------------------------------------------------------------- mass M_v x
-// y_c = R^T B^T diag(m_q) B R x_c for c = 0..2, one patch per workgroup; each
-// wave works through its own elements (per-element node gather, one component
-// at a time) and sums into the patch's LDS slots. With DOT, the workgroup also
-// writes sum_E x_E^T (M_E x_E) (= x^T M x over its elements) to part_dot.
+// y_c = R^T B^T diag(m_q) B R x_c, one patch per workgroup, one component at a
+// time: the patch's distinct-node values of x_c are read once into LDS, each
+// wave works through its own elements and sums into the patch's LDS slots,
+// and the component is written out before the next one starts. With DOT, the
+// workgroup also writes sum_E x_E^T (M_E x_E) (= x^T M x over its elements).
 __host__ __device__ constexpr int mass_waves(int D, int Q, int rs)
 {
-    return fit_waves(Q, rs * (3 * D * D * D + 2 * D * D * Q + D * Q * Q) + 4 * D * D * D,
-                     3 * rs * patch_umax(D) + 256);
+    return fit_waves(Q, rs * (2 * D * D * Q + D * Q * Q) + 4 * D * D * D, 2 * rs * patch_umax(D) + 256);
 }
 
 template <int D, int Q, bool DOT, typename R>
@@ -333,17 +333,17 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
     constexpr int QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D;
     using T = Tab<D, Q>;
     if (skip && *skip) return;  // a finished CG solve
-    __shared__ R acc[3 * UMAX];
-    __shared__ R sU[NE + 1][3][D3];
+    __shared__ R acc[UMAX];
+    __shared__ R xs[UMAX];
     __shared__ int sSl[NE + 1][D3];
     __shared__ R sX[NE + 1][D][D * Q];  // x-stage out, then y^T out
     __shared__ R sZ[NE + 1][D][QQ];
     __shared__ double sred[8];
+    (void)map;
 
     const Lane L = lane_map<Q, NE>();
     const int tid = threadIdx.x, le = L.le, t = L.t, qx = t % Q, qy = t / Q;
     const PatchRow pr = load_patch(ptab, xcd_block(blockIdx.x, gridDim.x));
-    for (int k = tid; k < 3 * pr.U; k += blockDim.x) acc[k] = 0.0;
     R rBx[D], rBy[D], cBy[Q], cBx[Q];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -352,38 +352,35 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
     }
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-        cBy[k] = qy < D ? tab[T::B + k * D + qy] : 0.0;
-        cBx[k] = qx < D ? tab[T::B + k * D + qx] : 0.0;
+        cBy[k] = qy < D ? tab[T::B + k * D + qy] : (R)0;
+        cBx[k] = qx < D ? tab[T::B + k * D + qx] : (R)0;
     }
     double dot = 0.0;
-    __syncthreads();
 
 #pragma unroll 1
-    for (int base = 0; base < pr.cnt; base += NE) {
-        const int idx = base + le;
-        const bool act = L.valid && idx < pr.cnt;
-        const long long el = pr.eb + (act ? idx : 0);
-        R m[Q];
-#pragma unroll
-        for (int k = 0; k < Q; ++k)
-            m[k] = act ? __builtin_nontemporal_load(mq + el * Q3 + k * QQ + t) : (R)0;
-        for (int i = t; i < D3; i += QQ) {
-            const long long g = act ? map[el * D3 + i] : 0;
-            sSl[le][i] = act ? slot[el * D3 + i] : 0;
-            sU[le][0][i] = act ? (R)x[g] : (R)0;
-            sU[le][1][i] = act ? (R)x[ncomp + g] : (R)0;
-            sU[le][2][i] = act ? (R)x[2 * ncomp + g] : (R)0;
+    for (int c = 0; c < 3; ++c) {
+        for (int u = tid; u < pr.U; u += blockDim.x) {
+            xs[u] = (R)x[c * ncomp + pn[pr.pno + u]];
+            acc[u] = (R)0;
         }
-        wave_sync();
+        __syncthreads();
 #pragma unroll 1
-        for (int c = 0; c < 3; ++c) {
+        for (int base = 0; base < pr.cnt; base += NE) {
+            const int idx = base + le;
+            const bool act = L.valid && idx < pr.cnt;
+            const long long el = pr.eb + (act ? idx : 0);
+            R m[Q];
+#pragma unroll
+            for (int k = 0; k < Q; ++k) m[k] = act ? mq[el * Q3 + k * QQ + t] : (R)0;
+            for (int i = t; i < D3; i += QQ) sSl[le][i] = act ? slot[el * D3 + i] : 0;
+            wave_sync();
             // x-stage: thread (qx, iy = qy)
             if (qy < D) {
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
-                    R a = 0.0;
+                    R a = 0;
 #pragma unroll
-                    for (int ix = 0; ix < D; ++ix) a += rBx[ix] * sU[le][c][(iz * D + qy) * D + ix];
+                    for (int ix = 0; ix < D; ++ix) a += rBx[ix] * xs[sSl[le][(iz * D + qy) * D + ix]];
                     sX[le][iz][qy * Q + qx] = a;
                 }
             }
@@ -392,17 +389,17 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
             R w[D];
 #pragma unroll
             for (int iz = 0; iz < D; ++iz) {
-                R a = 0.0;
+                R a = 0;
 #pragma unroll
                 for (int iy = 0; iy < D; ++iy) a += rBy[iy] * sX[le][iz][iy * Q + qx];
                 w[iz] = a;
             }
             R a[D];
 #pragma unroll
-            for (int iz = 0; iz < D; ++iz) a[iz] = 0.0;
+            for (int iz = 0; iz < D; ++iz) a[iz] = 0;
 #pragma unroll
             for (int qz = 0; qz < Q; ++qz) {
-                R u = 0.0;
+                R u = 0;
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) u += tab[T::B + qz * D + iz] * w[iz];
                 u *= m[qz];
@@ -416,7 +413,7 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
             if (qy < D) {
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
-                    R b = 0.0;
+                    R b = 0;
 #pragma unroll
                     for (int k = 0; k < Q; ++k) b += cBy[k] * sZ[le][iz][k * Q + qx];
                     sX[le][iz][qy * Q + qx] = b;
@@ -427,19 +424,26 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
             if (act && qx < D && qy < D) {
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
-                    const int li = (iz * D + qy) * D + qx;
-                    R r = 0.0;
+                    const int s = sSl[le][(iz * D + qy) * D + qx];
+                    R r = 0;
 #pragma unroll
                     for (int k = 0; k < Q; ++k) r += cBx[k] * sX[le][iz][qy * Q + k];
-                    atomicAdd(&acc[3 * sSl[le][li] + c], r);
-                    if (DOT) dot += (double)r * (double)sU[le][c][li];
+                    atomicAdd(&acc[s], r);
+                    if (DOT) dot += (double)r * (double)xs[s];
                 }
             }
-            wave_sync();  // sX is rewritten by the next component
+            wave_sync();  // sSl and sX are rewritten by the next pass
         }
+        __syncthreads();
+        for (int u = tid; u < pr.U; u += blockDim.x) {
+            const double a = (double)acc[u];
+            if (u < pr.P)
+                y[c * ncomp + pn[pr.pno + u]] = a;
+            else
+                part[3 * (long long)(pr.sho + u - pr.P) + c] = a;
+        }
+        __syncthreads();  // xs and acc are rewritten by the next component
     }
-    __syncthreads();
-    patch_write<UMAX>(acc, pr, pn, y, part, ncomp);
     if (DOT) {
         for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off);
         const int lane = tid & 63, wv = tid >> 6;
