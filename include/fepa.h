@@ -106,15 +106,25 @@ typedef struct fe_mesh_desc {
     double rho0;               /* initial density (> 0), uniform            */
 } fe_mesh_desc_t;
 
+/* Tile shapes of the patch kernels. 0 selects, in order, the entry of the
+ * tuning table named by the environment variable FEPA_TUNE_TABLE (text lines
+ * "order q1d precision nw_force nw_force_t nw_mass patch", as written by the
+ * package's autotuner), else the library default. */
 typedef struct fe_opts {
     int32_t precision;         /* FE_PREC_*                                 */
     int32_t flags;             /* FE_OPT_* bit set                          */
     double gamma;              /* ideal-gas ratio of specific heats (> 1)   */
     double q1, q2;             /* linear / quadratic viscosity coefficients */
+    int32_t tune_nw_force;     /* waves per workgroup of F e (2, 4 or 8)    */
+    int32_t tune_nw_force_t;   /* waves per workgroup of F^T v              */
+    int32_t tune_nw_mass;      /* waves per workgroup of M x                */
+    int32_t tune_patch;        /* elements per patch (8, 64 or 512)         */
 } fe_opts_t;
 
 typedef struct fe_info {
     int32_t n_mesh;
+    int32_t nw_force, nw_force_t, nw_mass;  /* tile shapes in use for mesh 0 */
+    int32_t patch;                          /* its elements per patch (cap)  */
     int64_t n_elem_total;      /* E_tot                                     */
     int64_t n_nodes_total;     /* N_tot (scalar); H1 vectors hold 3*N_tot    */
     int64_t l2_size_total;     /* sum over meshes of E*p^3                  */

@@ -44,11 +44,15 @@ class _MeshDesc(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("flags", C.c_int32), ("gamma", C.c_double),
-                ("q1", C.c_double), ("q2", C.c_double)]
+                ("q1", C.c_double), ("q2", C.c_double), ("tune_nw_force", C.c_int32),
+                ("tune_nw_force_t", C.c_int32), ("tune_nw_mass", C.c_int32),
+                ("tune_patch", C.c_int32)]
 
 
 class _Info(C.Structure):
-    _fields_ = [("n_mesh", C.c_int32), ("n_elem_total", C.c_int64), ("n_nodes_total", C.c_int64),
+    _fields_ = [("n_mesh", C.c_int32), ("nw_force", C.c_int32), ("nw_force_t", C.c_int32),
+                ("nw_mass", C.c_int32), ("patch", C.c_int32),
+                ("n_elem_total", C.c_int64), ("n_nodes_total", C.c_int64),
                 ("l2_size_total", C.c_int64), ("qdata_bytes", C.c_int64),
                 ("workspace_bytes", C.c_int64), ("precision", C.c_int32), ("flags", C.c_int32)]
 
@@ -135,6 +139,10 @@ class Opts:
     gamma: float = 5.0 / 3.0
     q1: float = 0.5
     q2: float = 2.0
+    tune_nw_force: int = 0      # 0: tuning table / library default
+    tune_nw_force_t: int = 0
+    tune_nw_mass: int = 0
+    tune_patch: int = 0
 
 
 class Ctx:
@@ -169,7 +177,8 @@ def fe_pa_setup(meshes, opts: Opts | None = None, stream=None) -> Ctx:
         descs[k] = _MeshDesc(E, m.order, m.q1d, m.x0.shape[-1], en.ctypes.data,
                              _ptr(m.x0).value, float(m.rho0))
     o = opts or Opts()
-    co = _Opts(o.precision, o.flags, o.gamma, o.q1, o.q2)
+    co = _Opts(o.precision, o.flags, o.gamma, o.q1, o.q2, o.tune_nw_force, o.tune_nw_force_t,
+               o.tune_nw_mass, o.tune_patch)
     h = C.c_void_p()
     _check(L.fe_pa_setup(descs, len(meshes), C.byref(co), _stream(stream), C.byref(h)))
     return Ctx(h, keep)

@@ -32,7 +32,7 @@ DEVICE = [f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
 def _compile(src: str) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(BUILD, src + ".o")
-    cmd = [HIPCC] + COMMON + (DEVICE if src.endswith(".hip") else []) + ["-c", path, "-o", obj]
+    cmd = [HIPCC] + COMMON + DEVICE + ["-c", path, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     noise = ("packed-fp32-ops", "warning generated", "warnings generated")
     msgs = "\n".join(l for l in (res.stdout + res.stderr).splitlines()

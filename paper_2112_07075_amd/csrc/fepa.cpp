@@ -8,6 +8,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -16,6 +17,7 @@
 
 #include "basis.hpp"
 #include "kern_cg.hpp"
+#include "kern_common.hpp"
 #include "kern_fp64.hpp"
 #include "patch.hpp"
 
@@ -33,6 +35,8 @@ struct MeshRec {
     const KernelSet *ks = nullptr;   // FP64 kernels
     KernelSet kl{};                  // kernels of the context's precision
     long long Sb_off = 0;            // offset of the mesh's S in the stored type
+    int nw_force = 4, nw_force_t = 4, nw_mass = 4;  // waves per workgroup
+    int patch = 0;                                   // elements per patch (0: default)
     long long tabb_off = 0;          // BF16 form: byte offset of its operand buffer
     double rho0 = 1.0;
     PatchDev pd;             // device patch plan
@@ -181,6 +185,38 @@ struct ScopedTimer {
 
 bool supported_pq(int p, int Q) { return fp64_kernels(p, Q) != nullptr; }
 
+struct TuneEntry {
+    int p, Q, prec, nwf, nwt, nwm, patch;
+};
+
+// the tuning table named by FEPA_TUNE_TABLE (missing or unreadable: empty)
+std::vector<TuneEntry> read_tune_table()
+{
+    std::vector<TuneEntry> t;
+    const char *path = std::getenv("FEPA_TUNE_TABLE");
+    if (!path || !*path) return t;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return t;
+    char line[256];
+    while (std::fgets(line, sizeof(line), f)) {
+        TuneEntry e{};
+        if (line[0] == '#') continue;
+        if (std::sscanf(line, "%d %d %d %d %d %d %d", &e.p, &e.Q, &e.prec, &e.nwf, &e.nwt, &e.nwm,
+                        &e.patch) == 7)
+            t.push_back(e);
+    }
+    std::fclose(f);
+    return t;
+}
+
+// largest waves per workgroup (8, 4, 2) whose LDS leaves room for two workgroups per CU
+int default_nw(int lds8, int lds4)
+{
+    if (lds8 <= 80 * 1024) return 8;
+    if (lds4 <= 80 * 1024) return 4;
+    return 2;
+}
+
 }  // namespace
 
 // typed views of the context's stored data for one mesh
@@ -244,6 +280,11 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         return fail(nullptr, FE_EUNSUPPORTED, "precision not provided by this build%s");
     if (o.flags & ~(FE_OPT_TIMERS | FE_OPT_BATCHED | FE_OPT_GRAPH))
         return fail(nullptr, FE_EINVAL, "unknown option flags%s");
+    for (int v : {o.tune_nw_force, o.tune_nw_force_t, o.tune_nw_mass})
+        if (v != 0 && v != 2 && v != 4 && v != 8)
+            return fail(nullptr, FE_EINVAL, "waves per workgroup must be 2, 4 or 8%s");
+    if (o.tune_patch != 0 && o.tune_patch != 8 && o.tune_patch != 64 && o.tune_patch != 512)
+        return fail(nullptr, FE_EINVAL, "patch size must be 8, 64 or 512%s");
     // host-side validation of every mesh before any device work
     for (int m = 0; m < n_mesh; ++m) {
         const fe_mesh_desc_t &d = meshes[m];
@@ -282,6 +323,7 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
     }
 
     // layout of the concatenated vectors and context arrays
+    const std::vector<TuneEntry> tune = read_tune_table();
     std::map<std::pair<int, int>, int> slot_of;
     std::vector<double> tab_host;
     for (int m = 0; m < n_mesh; ++m) {
@@ -294,6 +336,24 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         r.rho0 = d.rho0;
         r.ks = fp64_kernels(r.p, r.Q);
         r.kl = ctx->lo ? *fp32_kernels(r.p, r.Q) : *r.ks;
+        {
+            const int D = r.p + 1, rs = ctx->lo ? 4 : 8;
+            r.nw_force = default_nw(force_lds(D, r.Q, rs, 8), force_lds(D, r.Q, rs, 4));
+            r.nw_force_t = default_nw(force_t_lds(D, r.Q, rs, 8), force_t_lds(D, r.Q, rs, 4));
+            r.nw_mass = default_nw(mass_lds(D, r.Q, rs, 8), mass_lds(D, r.Q, rs, 4));
+            r.patch = 0;
+            for (const TuneEntry &te : tune)
+                if (te.p == r.p && te.Q == r.Q && te.prec == o.precision) {
+                    if (te.nwf) r.nw_force = te.nwf;
+                    if (te.nwt) r.nw_force_t = te.nwt;
+                    if (te.nwm) r.nw_mass = te.nwm;
+                    if (te.patch) r.patch = te.patch;
+                }
+            if (o.tune_nw_force) r.nw_force = o.tune_nw_force;
+            if (o.tune_nw_force_t) r.nw_force_t = o.tune_nw_force_t;
+            if (o.tune_nw_mass) r.nw_mass = o.tune_nw_mass;
+            if (o.tune_patch) r.patch = o.tune_patch;
+        }
         if (ctx->bf) {
             r.kl.force = bf16_force(r.p, r.Q);
             bf16_parts(r.p, r.Q, &r.kl);
@@ -429,6 +489,8 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         int B = 8;
         for (int cand : {512, 64, 8})
             if (cand <= bmax && (long long)r.E / cand >= 1024) { B = cand; break; }
+        if (r.patch) B = r.patch;
+        r.patch = B;
         PatchPlan pl = build_patch_plan(r.E, r.p, r.N, meshes[m].elem_nodes, x0h.data(), B, r.ks->umax);
         for (auto &g : pl.map_int) g += (int32_t)r.node_off;
         for (auto &g : pl.pn) g += (int32_t)r.node_off;
@@ -508,6 +570,10 @@ int fe_query(const fe_ctx_t *ctx, fe_info_t *info)
 {
     if (!ctx || !info) return FE_EINVAL;
     info->n_mesh = (int32_t)ctx->mesh.size();
+    info->nw_force = ctx->mesh[0].nw_force;
+    info->nw_force_t = ctx->mesh[0].nw_force_t;
+    info->nw_mass = ctx->mesh[0].nw_mass;
+    info->patch = ctx->mesh[0].patch;
     info->n_elem_total = ctx->E_tot;
     info->n_nodes_total = ctx->N_tot;
     info->l2_size_total = ctx->L2_tot;
@@ -558,7 +624,7 @@ int fe_force_mult(fe_ctx_t *ctx, const double *e, double *y)
         ScopedTimer tm(ctx, FE_TIMER_FORCE);
         for (const MeshRec &r : ctx->mesh) {
             r.kl.force(S_of(ctx, r), e ? e + r.l2_off : nullptr, r.pd, y, ctx->N_tot,
-                         tab_of(ctx, r), ctx->st);
+                       tab_of(ctx, r), r.nw_force, ctx->st);
             launch_gather_shared(r.pd, y, ctx->N_tot, nullptr, ctx->st);
             launch_zero_nodes(r.orphans, r.n_orphans, y, ctx->N_tot, nullptr, ctx->st);
         }
@@ -576,7 +642,7 @@ int fe_force_mult_T(fe_ctx_t *ctx, const double *v, double *z)
         ScopedTimer tm(ctx, FE_TIMER_FORCE_T);
         for (const MeshRec &r : ctx->mesh)
             r.kl.force_t(S_of(ctx, r), v, r.pd, r.E, z + r.l2_off, ctx->N_tot, tab_of(ctx, r),
-                           ctx->st);
+                         r.nw_force_t, ctx->st);
     }
     HIP_OK(hipGetLastError());
     return FE_OK;
@@ -589,10 +655,10 @@ static void mass_launch(fe_ctx *ctx, const double *x, double *y, bool dot, const
     for (const MeshRec &r : ctx->mesh) {
         if (lo)
             r.kl.mass(ctx->mq32 + r.mq_off, x, r.pd, y, ctx->N_tot, ctx->tabs32 + r.tab_slot,
-                        dot ? ctx->part + r.part_off : nullptr, skip, ctx->st);
+                      dot ? ctx->part + r.part_off : nullptr, skip, r.nw_mass, ctx->st);
         else
             r.ks->mass(ctx->mq + r.mq_off, x, r.pd, y, ctx->N_tot, ctx->tabs + r.tab_slot,
-                       dot ? ctx->part + r.part_off : nullptr, skip, ctx->st);
+                       dot ? ctx->part + r.part_off : nullptr, skip, r.nw_mass, ctx->st);
         launch_gather_shared(r.pd, y, ctx->N_tot, skip, ctx->st);
         launch_zero_nodes(r.orphans, r.n_orphans, y, ctx->N_tot, skip, ctx->st);
     }

@@ -131,8 +131,9 @@ k_force_mfma(const __bf16 *__restrict__ S, const double *__restrict__ e,
 template <int D, int Q>
 struct LaunchMfma {
     static void force(const void *S, const double *e, const PatchDev &pd, double *y,
-                      long long ncomp, const void *tab, hipStream_t st)
+                      long long ncomp, const void *tab, int nw, hipStream_t st)
     {
+        (void)nw;  // one wave per patch, four per workgroup
         const dim3 grid((pd.n_patch + 3) / 4), block(256);
         if (e)
             hipLaunchKernelGGL((k_force_mfma<D, Q, false>), grid, block, 0, st, (const __bf16 *)S,

@@ -113,10 +113,22 @@ __host__ __device__ constexpr int fit_waves(int Q, int per_elem, int fixed)
     return w;
 }
 
-// rs = bytes of the real type of the stored data and the contractions
-__host__ __device__ constexpr int force_waves(int D, int Q, int rs)
+// Static LDS bytes of the patch kernels with NW waves per workgroup; rs =
+// bytes of the real type of the stored data and the contractions. Instances
+// above kLdsMax are not launched (gfx950: 160 KiB per workgroup).
+constexpr int kLdsMax = 160 * 1024;
+__host__ __device__ constexpr int force_lds(int D, int Q, int rs, int NW)
 {
-    return fit_waves(Q, rs * (3 * D * Q * Q + 2 * D * D * Q), 3 * rs * patch_umax(D));
+    return 3 * rs * patch_umax(D) + (NW * wave_ne(Q) + 1) * rs * (3 * D * Q * Q + 2 * D * D * Q);
+}
+__host__ __device__ constexpr int force_t_lds(int D, int Q, int rs, int NW)
+{
+    return 3 * rs * patch_umax(D) +
+           (NW * wave_ne(Q) + 1) * (4 * D * D * D + rs * (2 * D * D * Q + (D - 1) * Q * Q + (D - 1) * (D - 1) * Q));
+}
+__host__ __device__ constexpr int mass_lds(int D, int Q, int rs, int NW)
+{
+    return 2 * rs * patch_umax(D) + (NW * wave_ne(Q) + 1) * (4 * D * D * D + rs * (D * D * Q + D * Q * Q)) + 64;
 }
 
 // One row of the patch table: first element, element count, offset of the

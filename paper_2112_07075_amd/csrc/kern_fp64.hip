@@ -35,15 +35,15 @@ __global__ void k_fill(double *__restrict__ y, long long n, double val)
 // per workgroup. Three H1 contraction stages per component with the three
 // derivative terms fused: z-stage -> (B, B, G), y-stage -> (B | G + B),
 // x-stage -> (G + B); element results are summed into the patch's LDS slots.
-template <int D, int Q, bool ONE, typename R>
-__global__ void __launch_bounds__(force_waves(D, Q, sizeof(R)) * 64)
+template <int D, int Q, bool ONE, typename R, int NW>
+__global__ void __launch_bounds__(NW * 64)
 k_force(const R *__restrict__ S, const double *__restrict__ e,
         const int32_t *__restrict__ perm, const uint16_t *__restrict__ slot,
         const int32_t *__restrict__ pn, const int32_t *__restrict__ ptab,
         double *__restrict__ y, double *__restrict__ part, long long ncomp,
         const R *__restrict__ tab)
 {
-    constexpr int NE = force_waves(D, Q, sizeof(R)) * wave_ne(Q), UMAX = patch_umax(D);
+    constexpr int NE = NW * wave_ne(Q), UMAX = patch_umax(D);
     constexpr int DL = D - 1, QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D, DL3 = DL * DL * DL;
     using T = Tab<D, Q>;
     __shared__ R acc[3 * UMAX];
@@ -169,20 +169,15 @@ k_force(const R *__restrict__ S, const double *__restrict__ e,
 // z[E][j] = sum_q phi_j(q) sum_{c,d} S[c][d](q) (grad_xi v_c)_d(q), one patch per
 // workgroup: the patch's distinct nodes of v are read once into LDS; rows of z
 // are written in caller element order.
-__host__ __device__ constexpr int force_t_waves(int D, int Q, int rs)
-{
-    return fit_waves(Q, rs * (2 * D * D * Q + (D - 1) * Q * Q + (D - 1) * (D - 1) * Q) + 4 * D * D * D,
-                     3 * rs * patch_umax(D));
-}
 
-template <int D, int Q, typename R, typename RS = R>
-__global__ void __launch_bounds__(force_t_waves(D, Q, sizeof(R)) * 64)
+template <int D, int Q, typename R, typename RS, int NW>
+__global__ void __launch_bounds__(NW * 64)
 k_force_t(const RS *__restrict__ S, const double *__restrict__ v,
           const int32_t *__restrict__ perm, const uint16_t *__restrict__ slot,
           const int32_t *__restrict__ pn, const int32_t *__restrict__ ptab,
           double *__restrict__ z, long long ncomp, const R *__restrict__ tab)
 {
-    constexpr int NE = force_t_waves(D, Q, sizeof(R)) * wave_ne(Q), UMAX = patch_umax(D);
+    constexpr int NE = NW * wave_ne(Q), UMAX = patch_umax(D);
     constexpr int DL = D - 1, QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D, DL3 = DL * DL * DL;
     using T = Tab<D, Q>;
     __shared__ R vs[3 * UMAX];
@@ -315,13 +310,9 @@ k_force_t(const RS *__restrict__ S, const double *__restrict__ v,
 // wave works through its own elements and sums into the patch's LDS slots,
 // and the component is written out before the next one starts. With DOT, the
 // workgroup also writes sum_E x_E^T (M_E x_E) (= x^T M x over its elements).
-__host__ __device__ constexpr int mass_waves(int D, int Q, int rs)
-{
-    return fit_waves(Q, rs * (2 * D * D * Q + D * Q * Q) + 4 * D * D * D, 2 * rs * patch_umax(D) + 256);
-}
 
-template <int D, int Q, bool DOT, typename R>
-__global__ void __launch_bounds__(mass_waves(D, Q, sizeof(R)) * 64)
+template <int D, int Q, bool DOT, typename R, int NW>
+__global__ void __launch_bounds__(NW * 64)
 k_mass(const R *__restrict__ mq, const double *__restrict__ x,
        const int32_t *__restrict__ map, const uint16_t *__restrict__ slot,
        const int32_t *__restrict__ pn, const int32_t *__restrict__ ptab,
@@ -329,7 +320,7 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
        const R *__restrict__ tab, double *__restrict__ part_dot,
        const int *__restrict__ skip)
 {
-    constexpr int NE = mass_waves(D, Q, sizeof(R)) * wave_ne(Q), UMAX = patch_umax(D);
+    constexpr int NE = NW * wave_ne(Q), UMAX = patch_umax(D);
     constexpr int QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D;
     using T = Tab<D, Q>;
     if (skip && *skip) return;  // a finished CG solve
@@ -688,38 +679,68 @@ template <int D, int Q, typename R>
 struct Launch {
     static constexpr int NEp = pt_ne(Q);
 
-    static void force(const void *S, const double *e, const PatchDev &pd, double *y,
-                      long long ncomp, const void *tab, hipStream_t st)
+    template <int NW>
+    static void force_nw(const void *S, const double *e, const PatchDev &pd, double *y,
+                         long long ncomp, const void *tab, hipStream_t st)
     {
-        const dim3 grid(pd.n_patch), block(force_waves(D, Q, sizeof(R)) * 64);
+        const dim3 grid(pd.n_patch), block(NW * 64);
         if (e)
-            hipLaunchKernelGGL((k_force<D, Q, false, R>), grid, block, 0, st, (const R *)S, e,
+            hipLaunchKernelGGL((k_force<D, Q, false, R, NW>), grid, block, 0, st, (const R *)S, e,
                                pd.perm, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab);
         else
-            hipLaunchKernelGGL((k_force<D, Q, true, R>), grid, block, 0, st, (const R *)S, e,
+            hipLaunchKernelGGL((k_force<D, Q, true, R, NW>), grid, block, 0, st, (const R *)S, e,
                                pd.perm, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab);
+    }
+    static void force(const void *S, const double *e, const PatchDev &pd, double *y,
+                      long long ncomp, const void *tab, int nw, hipStream_t st)
+    {
+        constexpr int rs = sizeof(R);
+        if (nw >= 8 && force_lds(D, Q, rs, 8) <= kLdsMax) return force_nw<8>(S, e, pd, y, ncomp, tab, st);
+        if (nw >= 4 && force_lds(D, Q, rs, 4) <= kLdsMax) return force_nw<4>(S, e, pd, y, ncomp, tab, st);
+        return force_nw<2>(S, e, pd, y, ncomp, tab, st);
+    }
+    template <int NW>
+    static void force_t_nw(const void *S, const double *v, const PatchDev &pd, double *z,
+                           long long ncomp, const void *tab, hipStream_t st)
+    {
+        hipLaunchKernelGGL((k_force_t<D, Q, R, R, NW>), dim3(pd.n_patch), dim3(NW * 64), 0, st,
+                           (const R *)S, v, pd.perm, pd.slot, pd.pn, pd.ptab, z, ncomp,
+                           (const R *)tab);
     }
     static void force_t(const void *S, const double *v, const PatchDev &pd, int E, double *z,
-                        long long ncomp, const void *tab, hipStream_t st)
+                        long long ncomp, const void *tab, int nw, hipStream_t st)
     {
         (void)E;
-        hipLaunchKernelGGL((k_force_t<D, Q, R>), dim3(pd.n_patch),
-                           dim3(force_t_waves(D, Q, sizeof(R)) * 64), 0, st, (const R *)S, v,
-                           pd.perm, pd.slot, pd.pn, pd.ptab, z, ncomp, (const R *)tab);
+        constexpr int rs = sizeof(R);
+        if (nw >= 8 && force_t_lds(D, Q, rs, 8) <= kLdsMax) return force_t_nw<8>(S, v, pd, z, ncomp, tab, st);
+        if (nw >= 4 && force_t_lds(D, Q, rs, 4) <= kLdsMax) return force_t_nw<4>(S, v, pd, z, ncomp, tab, st);
+        return force_t_nw<2>(S, v, pd, z, ncomp, tab, st);
     }
-    static void mass(const void *mq, const double *x, const PatchDev &pd, double *y,
-                     long long ncomp, const void *tab, double *part_dot, const int *skip,
-                     hipStream_t st)
+    template <int NW>
+    static void mass_nw(const void *mq, const double *x, const PatchDev &pd, double *y,
+                        long long ncomp, const void *tab, double *part_dot, const int *skip,
+                        hipStream_t st)
     {
-        const dim3 grid(pd.n_patch), block(mass_waves(D, Q, sizeof(R)) * 64);
+        const dim3 grid(pd.n_patch), block(NW * 64);
         if (part_dot)
-            hipLaunchKernelGGL((k_mass<D, Q, true, R>), grid, block, 0, st, (const R *)mq, x,
+            hipLaunchKernelGGL((k_mass<D, Q, true, R, NW>), grid, block, 0, st, (const R *)mq, x,
                                pd.map, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab,
                                part_dot, skip);
         else
-            hipLaunchKernelGGL((k_mass<D, Q, false, R>), grid, block, 0, st, (const R *)mq, x,
+            hipLaunchKernelGGL((k_mass<D, Q, false, R, NW>), grid, block, 0, st, (const R *)mq, x,
                                pd.map, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab,
                                part_dot, skip);
+    }
+    static void mass(const void *mq, const double *x, const PatchDev &pd, double *y,
+                     long long ncomp, const void *tab, double *part_dot, const int *skip, int nw,
+                     hipStream_t st)
+    {
+        constexpr int rs = sizeof(R);
+        if (nw >= 8 && mass_lds(D, Q, rs, 8) <= kLdsMax)
+            return mass_nw<8>(mq, x, pd, y, ncomp, tab, part_dot, skip, st);
+        if (nw >= 4 && mass_lds(D, Q, rs, 4) <= kLdsMax)
+            return mass_nw<4>(mq, x, pd, y, ncomp, tab, part_dot, skip, st);
+        return mass_nw<2>(mq, x, pd, y, ncomp, tab, part_dot, skip, st);
     }
     // tab: the FP64 table (the algebra is FP64); S receives R values
     static void qdata(const double *x, const double *v, const double *e, const PatchDev &pd, int E,
@@ -759,14 +780,21 @@ const KernelSet *fp64_kernels(int p, int Q) { return kernels_for<double>(p, Q); 
 // BF16 form: F^T v reads BF16 S with FP32 contractions; qdata writes BF16 S.
 template <int D, int Q>
 struct LaunchBf16 {
+    template <int NW>
+    static void force_t_nw(const void *S, const double *v, const PatchDev &pd, double *z,
+                           long long ncomp, const void *tab, hipStream_t st)
+    {
+        hipLaunchKernelGGL((k_force_t<D, Q, float, __bf16, NW>), dim3(pd.n_patch), dim3(NW * 64),
+                           0, st, (const __bf16 *)S, v, pd.perm, pd.slot, pd.pn, pd.ptab, z, ncomp,
+                           (const float *)tab);
+    }
     static void force_t(const void *S, const double *v, const PatchDev &pd, int E, double *z,
-                        long long ncomp, const void *tab, hipStream_t st)
+                        long long ncomp, const void *tab, int nw, hipStream_t st)
     {
         (void)E;
-        hipLaunchKernelGGL((k_force_t<D, Q, float, __bf16>), dim3(pd.n_patch),
-                           dim3(force_t_waves(D, Q, sizeof(float)) * 64), 0, st,
-                           (const __bf16 *)S, v, pd.perm, pd.slot, pd.pn, pd.ptab, z, ncomp,
-                           (const float *)tab);
+        if (nw >= 8 && force_t_lds(D, Q, 4, 8) <= kLdsMax) return force_t_nw<8>(S, v, pd, z, ncomp, tab, st);
+        if (nw >= 4 && force_t_lds(D, Q, 4, 4) <= kLdsMax) return force_t_nw<4>(S, v, pd, z, ncomp, tab, st);
+        return force_t_nw<2>(S, v, pd, z, ncomp, tab, st);
     }
     static void qdata(const double *x, const double *v, const double *e, const PatchDev &pd, int E,
                       long long ncomp, int node_off, double *mq, void *S, const double *tab,

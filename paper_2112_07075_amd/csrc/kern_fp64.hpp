@@ -32,13 +32,15 @@ struct PatchDev {
 // S, m_q and tab of force/force_t/mass are of the set's real type (double for
 // fp64_kernels, float for fp32_kernels); qdata always takes the FP64 table and
 // writes S in the set's real type.
+// nw: waves per workgroup of the patch kernels (2, 4 or 8; the largest
+// instance that fits the LDS limit is used when nw is too large).
 struct KernelSet {
     void (*force)(const void *S, const double *e, const PatchDev &pd, double *y,
-                  long long ncomp, const void *tab, hipStream_t st);
+                  long long ncomp, const void *tab, int nw, hipStream_t st);
     void (*force_t)(const void *S, const double *v, const PatchDev &pd, int E, double *z,
-                    long long ncomp, const void *tab, hipStream_t st);
+                    long long ncomp, const void *tab, int nw, hipStream_t st);
     void (*mass)(const void *mq, const double *x, const PatchDev &pd, double *y,
-                 long long ncomp, const void *tab, double *part_dot, const int *skip,
+                 long long ncomp, const void *tab, double *part_dot, const int *skip, int nw,
                  hipStream_t st);
     void (*qdata)(const double *x, const double *v, const double *e, const PatchDev &pd, int E,
                   long long ncomp, int node_off, double *mq, void *S, const double *tab,
@@ -53,7 +55,7 @@ const KernelSet *fp32_kernels(int p, int Q);
 bool bf16_parts(int p, int Q, KernelSet *ks);
 // BF16 form: MFMA force launcher (nullptr when (p, Q) has no MFMA instance).
 using ForceFn = void (*)(const void *S, const double *e, const PatchDev &pd, double *y,
-                         long long ncomp, const void *tab, hipStream_t st);
+                         long long ncomp, const void *tab, int nw, hipStream_t st);
 ForceFn bf16_force(int p, int Q);
 // Size in bytes of the MFMA operand table of (p, Q) (0 when unsupported).
 int mfma_btab_bytes(int p, int Q);

@@ -59,6 +59,8 @@ def _setup(descs, n, opts=None):
     ("null_x0", fe.FE_EINVAL),
     ("bad_gamma", fe.FE_EINVAL),
     ("bad_precision", fe.FE_EUNSUPPORTED),
+    ("bad_waves", fe.FE_EINVAL),
+    ("bad_patch", fe.FE_EINVAL),
 ])
 def test_setup_rejects_invalid_arguments_without_device(case, expect):
     d, keep = _desc()
@@ -75,9 +77,13 @@ def test_setup_rejects_invalid_arguments_without_device(case, expect):
     elif case == "null_x0":
         d.x0 = None
     elif case == "bad_gamma":
-        opts = fe._Opts(0, 0, 0.5, 0.5, 2.0)
+        opts = fe._Opts(0, 0, 0.5, 0.5, 2.0, 0, 0, 0, 0)
     elif case == "bad_precision":
-        opts = fe._Opts(7, 0, 5.0 / 3.0, 0.5, 2.0)
+        opts = fe._Opts(7, 0, 5.0 / 3.0, 0.5, 2.0, 0, 0, 0, 0)
+    elif case == "bad_waves":
+        opts = fe._Opts(0, 0, 5.0 / 3.0, 0.5, 2.0, 3, 0, 0, 0)
+    elif case == "bad_patch":
+        opts = fe._Opts(0, 0, 5.0 / 3.0, 0.5, 2.0, 0, 0, 0, 100)
     rc, h = _setup([d], n, opts)
     assert rc == expect
     assert not h.value
