@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <string>
 #include <utility>
@@ -353,6 +354,11 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
             if (o.tune_nw_force_t) r.nw_force_t = o.tune_nw_force_t;
             if (o.tune_nw_mass) r.nw_mass = o.tune_nw_mass;
             if (o.tune_patch) r.patch = o.tune_patch;
+            // never a tile shape whose kernels spill registers or overflow LDS
+            const KernelSet &kc = ctx->lo ? *fp32_kernels(r.p, r.Q) : *r.ks;
+            r.nw_force = std::min(r.nw_force, kc.max_nw(0));
+            r.nw_force_t = std::min(r.nw_force_t, kc.max_nw(1));
+            r.nw_mass = std::min(r.nw_mass, kc.max_nw(2));
         }
         if (ctx->bf) {
             r.kl.force = bf16_force(r.p, r.Q);

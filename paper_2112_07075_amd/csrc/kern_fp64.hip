@@ -742,6 +742,33 @@ struct Launch {
             return mass_nw<4>(mq, x, pd, y, ncomp, tab, part_dot, skip, st);
         return mass_nw<2>(mq, x, pd, y, ncomp, tab, part_dot, skip, st);
     }
+    // Largest waves per workgroup (8, 4, 2) of kernel kind (0 force, 1 force^T,
+    // 2 mass) whose instances fit the LDS limit and keep every value in
+    // registers (no private-segment spills).
+    template <typename K>
+    static bool no_spill(K kern)
+    {
+        hipFuncAttributes a{};
+        return hipFuncGetAttributes(&a, (const void *)kern) == hipSuccess && a.localSizeBytes == 0;
+    }
+    template <int NW>
+    static bool fits(int kind)
+    {
+        constexpr int rs = sizeof(R);
+        if (kind == 0)
+            return force_lds(D, Q, rs, NW) <= kLdsMax && no_spill(k_force<D, Q, true, R, NW>) &&
+                   no_spill(k_force<D, Q, false, R, NW>);
+        if (kind == 1)
+            return force_t_lds(D, Q, rs, NW) <= kLdsMax && no_spill(k_force_t<D, Q, R, R, NW>);
+        return mass_lds(D, Q, rs, NW) <= kLdsMax && no_spill(k_mass<D, Q, true, R, NW>) &&
+               no_spill(k_mass<D, Q, false, R, NW>);
+    }
+    static int max_nw(int kind)
+    {
+        if (fits<8>(kind)) return 8;
+        if (fits<4>(kind)) return 4;
+        return 2;
+    }
     // tab: the FP64 table (the algebra is FP64); S receives R values
     static void qdata(const double *x, const double *v, const double *e, const PatchDev &pd, int E,
                       long long ncomp, int node_off, double *mq, void *S, const double *tab,
@@ -768,7 +795,7 @@ static const KernelSet *kernels_for(int p, int Q)
 #define FEPA_ENTRY(P, QQ)                                                                        \
     static const KernelSet ks_##P##_##QQ = {                                                     \
         Launch<P + 1, QQ, R>::force, Launch<P + 1, QQ, R>::force_t, Launch<P + 1, QQ, R>::mass, \
-        Launch<P + 1, QQ, R>::qdata, patch_umax(P + 1)};                                         \
+        Launch<P + 1, QQ, R>::qdata, patch_umax(P + 1), Launch<P + 1, QQ, R>::max_nw};           \
     if (p == P && Q == QQ) return &ks_##P##_##QQ;
     FEPA_PQ_LIST(FEPA_ENTRY)
 #undef FEPA_ENTRY

@@ -46,6 +46,9 @@ struct KernelSet {
                   long long ncomp, int node_off, double *mq, void *S, const double *tab,
                   QParams prm, long long *min_key, int *nonfinite, bool init, hipStream_t st);
     int umax;  // distinct-node capacity of a patch for this order
+    // largest waves per workgroup of kind 0 (force), 1 (force^T), 2 (mass)
+    // that fits the LDS limit without register spills
+    int (*max_nw)(int kind);
 };
 
 // nullptr when (p, Q) is not instantiated.
