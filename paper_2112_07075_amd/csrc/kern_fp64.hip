@@ -308,8 +308,12 @@ k_force_t(const RS *__restrict__ S, const double *__restrict__ v,
 // y_c = R^T B^T diag(m_q) B R x_c, one patch per workgroup, one component at a
 // time: the patch's distinct-node values of x_c are read once into LDS, each
 // wave works through its own elements and sums into the patch's LDS slots,
-// and the component is written out before the next one starts. With DOT, the
-// workgroup also writes sum_E x_E^T (M_E x_E) (= x^T M x over its elements).
+// and the component is written out before the next one starts. Elements are
+// taken in groups of MAXP passes whose m_q (registers) and slots (LDS) are
+// loaded together, so a patch waits for memory once per group, not per pass.
+// With DOT, the workgroup also writes sum_E x_E^T (M_E x_E) (= x^T M x over
+// its elements).
+constexpr int kMassGroup = 4;  // passes per load group
 
 template <int D, int Q, bool DOT, typename R, int NW>
 __global__ void __launch_bounds__(NW * 64)
@@ -320,16 +324,16 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
        const R *__restrict__ tab, double *__restrict__ part_dot,
        const int *__restrict__ skip)
 {
-    constexpr int NE = NW * wave_ne(Q), UMAX = patch_umax(D);
+    constexpr int NE = NW * wave_ne(Q), UMAX = patch_umax(D), MAXP = kMassGroup;
     constexpr int QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D;
     using T = Tab<D, Q>;
     if (skip && *skip) return;  // a finished CG solve
     __shared__ R acc[UMAX];
     __shared__ R xs[UMAX];
-    __shared__ int sSl[NE + 1][D3];
+    __shared__ int sSl[MAXP * NE + 1][D3];
     __shared__ R sX[NE + 1][D][D * Q];  // x-stage out, then y^T out
     __shared__ R sZ[NE + 1][D][QQ];
-    __shared__ double sred[8];
+    __shared__ double sred[16];
     (void)map;
 
     const Lane L = lane_map<Q, NE>();
@@ -347,6 +351,7 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
         cBx[k] = qx < D ? tab[T::B + k * D + qx] : (R)0;
     }
     double dot = 0.0;
+    for (int i = tid; i < D3; i += blockDim.x) sSl[MAXP * NE][i] = 0;  // spare row of idle lanes
 
 #pragma unroll 1
     for (int c = 0; c < 3; ++c) {
@@ -354,78 +359,90 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
             xs[u] = (R)x[c * ncomp + pn[pr.pno + u]];
             acc[u] = (R)0;
         }
-        __syncthreads();
 #pragma unroll 1
-        for (int base = 0; base < pr.cnt; base += NE) {
-            const int idx = base + le;
-            const bool act = L.valid && idx < pr.cnt;
-            const long long el = pr.eb + (act ? idx : 0);
-            R m[Q];
+        for (int g0 = 0; g0 < pr.cnt; g0 += MAXP * NE) {
+            const int gcnt = min(MAXP * NE, pr.cnt - g0);
+            // the group's m_q into registers and its slots into LDS, all loads in flight
+            R m[MAXP][Q];
 #pragma unroll
-            for (int k = 0; k < Q; ++k) m[k] = act ? mq[el * Q3 + k * QQ + t] : (R)0;
-            for (int i = t; i < D3; i += QQ) sSl[le][i] = act ? slot[el * D3 + i] : 0;
-            wave_sync();
-            // x-stage: thread (qx, iy = qy)
-            if (qy < D) {
+            for (int k = 0; k < MAXP; ++k) {
+                const int idx = k * NE + le;
+                const bool act = L.valid && idx < gcnt;
+                const long long el = pr.eb + g0 + (act ? idx : 0);
+#pragma unroll
+                for (int qz = 0; qz < Q; ++qz) m[k][qz] = act ? mq[el * Q3 + qz * QQ + t] : (R)0;
+            }
+            for (int i = tid; i < gcnt * D3; i += blockDim.x)
+                sSl[i / D3][i % D3] = slot[(long long)(pr.eb + g0) * D3 + i];
+            __syncthreads();  // xs, acc (first group) and the group's slots are ready
+#pragma unroll
+            for (int k = 0; k < MAXP; ++k) {
+                const int idx = k * NE + le;
+                const bool act = L.valid && idx < gcnt;
+                const int sl = act ? idx : MAXP * NE;  // spare row for idle lanes
+                if (k * NE >= gcnt) break;             // uniform: no element of the pass left
+                // x-stage: thread (qx, iy = qy)
+                if (qy < D) {
+#pragma unroll
+                    for (int iz = 0; iz < D; ++iz) {
+                        R a = 0;
+#pragma unroll
+                        for (int ix = 0; ix < D; ++ix) a += rBx[ix] * xs[sSl[sl][(iz * D + qy) * D + ix]];
+                        sX[le][iz][qy * Q + qx] = a;
+                    }
+                }
+                wave_sync();
+                // y-stage, z-stage, weights, z^T in registers of thread (qx, qy)
+                R w[D];
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
                     R a = 0;
 #pragma unroll
-                    for (int ix = 0; ix < D; ++ix) a += rBx[ix] * xs[sSl[le][(iz * D + qy) * D + ix]];
-                    sX[le][iz][qy * Q + qx] = a;
+                    for (int iy = 0; iy < D; ++iy) a += rBy[iy] * sX[le][iz][iy * Q + qx];
+                    w[iz] = a;
                 }
-            }
-            wave_sync();
-            // y-stage, z-stage, weights, z^T in registers of thread (qx, qy)
-            R w[D];
+                R a[D];
 #pragma unroll
-            for (int iz = 0; iz < D; ++iz) {
-                R a = 0;
+                for (int iz = 0; iz < D; ++iz) a[iz] = 0;
 #pragma unroll
-                for (int iy = 0; iy < D; ++iy) a += rBy[iy] * sX[le][iz][iy * Q + qx];
-                w[iz] = a;
-            }
-            R a[D];
+                for (int qz = 0; qz < Q; ++qz) {
+                    R u = 0;
 #pragma unroll
-            for (int iz = 0; iz < D; ++iz) a[iz] = 0;
+                    for (int iz = 0; iz < D; ++iz) u += tab[T::B + qz * D + iz] * w[iz];
+                    u *= m[k][qz];
 #pragma unroll
-            for (int qz = 0; qz < Q; ++qz) {
-                R u = 0;
-#pragma unroll
-                for (int iz = 0; iz < D; ++iz) u += tab[T::B + qz * D + iz] * w[iz];
-                u *= m[qz];
-#pragma unroll
-                for (int iz = 0; iz < D; ++iz) a[iz] += tab[T::B + qz * D + iz] * u;
-            }
-#pragma unroll
-            for (int iz = 0; iz < D; ++iz) sZ[le][iz][t] = a[iz];
-            wave_sync();
-            // y^T: thread (qx, iy = qy), into sX
-            if (qy < D) {
-#pragma unroll
-                for (int iz = 0; iz < D; ++iz) {
-                    R b = 0;
-#pragma unroll
-                    for (int k = 0; k < Q; ++k) b += cBy[k] * sZ[le][iz][k * Q + qx];
-                    sX[le][iz][qy * Q + qx] = b;
+                    for (int iz = 0; iz < D; ++iz) a[iz] += tab[T::B + qz * D + iz] * u;
                 }
-            }
-            wave_sync();
-            // x^T: thread (ix = qx, iy = qy), summed into the patch slots
-            if (act && qx < D && qy < D) {
 #pragma unroll
-                for (int iz = 0; iz < D; ++iz) {
-                    const int s = sSl[le][(iz * D + qy) * D + qx];
-                    R r = 0;
+                for (int iz = 0; iz < D; ++iz) sZ[le][iz][t] = a[iz];
+                wave_sync();
+                // y^T: thread (qx, iy = qy), into sX
+                if (qy < D) {
 #pragma unroll
-                    for (int k = 0; k < Q; ++k) r += cBx[k] * sX[le][iz][qy * Q + k];
-                    atomicAdd(&acc[s], r);
-                    if (DOT) dot += (double)r * (double)xs[s];
+                    for (int iz = 0; iz < D; ++iz) {
+                        R b = 0;
+#pragma unroll
+                        for (int kk = 0; kk < Q; ++kk) b += cBy[kk] * sZ[le][iz][kk * Q + qx];
+                        sX[le][iz][qy * Q + qx] = b;
+                    }
                 }
+                wave_sync();
+                // x^T: thread (ix = qx, iy = qy), summed into the patch slots
+                if (act && qx < D && qy < D) {
+#pragma unroll
+                    for (int iz = 0; iz < D; ++iz) {
+                        const int s = sSl[sl][(iz * D + qy) * D + qx];
+                        R r = 0;
+#pragma unroll
+                        for (int kk = 0; kk < Q; ++kk) r += cBx[kk] * sX[le][iz][qy * Q + kk];
+                        atomicAdd(&acc[s], r);
+                        if (DOT) dot += (double)r * (double)xs[s];
+                    }
+                }
+                wave_sync();  // sX is rewritten by the next pass
             }
-            wave_sync();  // sSl and sX are rewritten by the next pass
+            __syncthreads();  // sSl is rewritten by the next group
         }
-        __syncthreads();
         for (int u = tid; u < pr.U; u += blockDim.x) {
             const double a = (double)acc[u];
             if (u < pr.P)
