@@ -1,8 +1,8 @@
 """Benchmark of the PA Lagrange-phase hot path on one MI355X.
 
-One step = the whole hot path over the 48^3 Q2-Q1 Taylor-Green workload with
-inputs resident in HBM: one quadrature-data update, 50 x (F.1 + F^T.v), and
-one mass CG solve to a 1e-12 relative residual (v.n = 0 on the boundary).
+One step = the whole hot path over a Taylor-Green workload with inputs resident
+in HBM: one quadrature-data update, 50 x (F.1 + F^T.v), and one mass CG solve
+to a 1e-12 relative residual (v.n = 0 on the boundary).
 
 value = kinematic DOFs processed by force actions per second of the whole
 step, 3N x 100 / t_step / 1e9 (GDOF/s; the CG and qdata time count against
@@ -10,7 +10,13 @@ it). The roofline object rates the dominant kernel (the force action with the
 larger total time) by algorithmic bytes per launch over its mean duration,
 measured with HIP events recorded by the library on its own stream.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2|c3|c4]
+Workloads: c2 (default) 48^3 Q2-Q1; c3 24^3 Q4-Q3; c4 64^3 Q3-Q2 (with
+--precision fp64|fp32|bf16, the precision form); c5 the 256-mesh uneven batch
+(4^3..24^3 elements, p 1..4, Q = p+2) run as one batched, graph-replayed
+context and, for comparison, as per-mesh launches of the plain path.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2|c3|c4|c5]
+                       [--precision fp64|fp32|bf16]
 """
 from __future__ import annotations
 
@@ -29,8 +35,11 @@ CONFIGS = {
     # name: (n, p, Q, label)
     "c2": (48, 2, 4, "48^3 hex, H1 Q2 / L2 Q1, 4^3 Gauss points, Taylor-Green, seed 0"),
     "c3": (24, 4, 6, "24^3 hex, H1 Q4 / L2 Q3, 6^3 Gauss points, Taylor-Green, seed 0"),
-    "c4": (64, 3, 5, "64^3 hex, H1 Q3 / L2 Q2, 5^3 Gauss points, Taylor-Green, seed 0, FP64 path"),
+    "c4": (64, 3, 5, "64^3 hex, H1 Q3 / L2 Q2, 5^3 Gauss points, Taylor-Green, seed 0"),
+    "c5": (None, None, None, "256 perturbed cubes, 4^3..24^3 elements, H1 Q1..Q4, Q = p+2, "
+                             "Taylor-Green, seeds 1000..1255"),
 }
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 N_PAIRS = 50
 HBM_PEAK_GBS = 8000.0
 
@@ -48,29 +57,113 @@ def algorithmic_bytes(E, N, p, Q):
     }
 
 
-def cpu_baseline(mesh, v, e, p, Q, budget_s=12.0):
-    """The plain oracle (single thread) on a bounded element sample: qdata, F.1 and
-    F^T.v over the first k elements, scaled to GDOF/s of the full mesh."""
+def cpu_baseline(meshes, qs, fields, budget_s=12.0):
+    """The plain oracle (single thread) on a bounded element sample: F.1 and F^T.v
+    over the first k elements of the first mesh of every (p, Q) class, scaled to
+    GDOF/s of the whole workload (qdata on the sample is timed but excluded)."""
     import oracle as O
-    E, N = mesh.n_elem, mesh.n_nodes
-    k = 256
-    while True:
-        el = np.arange(k, dtype=np.int32)
+    classes = {}
+    for m, Q, f in zip(meshes, qs, fields):
+        classes.setdefault((m.p, Q), (m, f))
+    per_elem, notes, t_q = {}, [], 0.0
+    for (p, Q), (mesh, (v, e)) in classes.items():
+        E, N = mesh.n_elem, mesh.n_nodes
+        k = min(64, E)
+        while True:
+            el = np.arange(k, dtype=np.int32)
+            t0 = time.perf_counter()
+            S = O.qdata(mesh.elem_nodes, p, Q, N, mesh.x0, mesh.x0, v, e, elems=el,
+                        want=("S",))["S"]
+            t1 = time.perf_counter()
+            O.force_mult(mesh.elem_nodes, p, Q, N, S, None, elems=el)
+            O.force_mult_T(mesh.elem_nodes, p, Q, N, S, v, elems=el)
+            t2 = time.perf_counter()
+            if (t2 - t0) > budget_s / (4 * len(classes)) or k * 2 > E:
+                break
+            k *= 2
+        per_elem[(p, Q)] = (t2 - t1) / k
+        t_q += t1 - t0
+        notes.append(f"p={p},Q={Q}: first {k} of {E} elements, {t2 - t1:.2f} s")
+    pair_s = sum(per_elem[(m.p, Q)] * m.n_elem for m, Q in zip(meshes, qs))
+    dofs = sum(3 * m.n_nodes for m in meshes)
+    return {"value": dofs * 2 / pair_s / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+            "sample": "F.1 + F^T.v on " + "; ".join(notes) +
+                      f" (qdata on the samples {t_q:.2f} s, excluded), scaled per element to "
+                      "the whole workload"}
+
+
+def build_workload(config, W):
+    """(meshes, q1d per mesh, (v, e) per mesh, label)"""
+    if config == "c5":
+        items = W.batch_meshes(256)
+        meshes = [b.mesh for b in items]
+        qs = [b.q1d for b in items]
+    else:
+        n, p, Q, _ = CONFIGS[config]
+        meshes, qs = [W.cube_mesh(n, p, W.default_amp(p), seed=0)], [Q]
+    fields = [W.taylor_green_fields(m) for m in meshes]
+    return meshes, qs, fields, CONFIGS[config][3]
+
+
+class Runner:
+    """One context over the workload's meshes and the vectors of one step."""
+
+    def __init__(self, torch, fe, W, meshes, qs, fields, opts):
+        dev = torch.device("cuda:0")
+        self.torch, self.fe = torch, fe
+        noff = np.concatenate([[0], np.cumsum([m.n_nodes for m in meshes])]).astype(np.int64)
+        self.Ntot = int(noff[-1])
+        self.x0 = torch.from_numpy(np.concatenate([m.x0 for m in meshes], axis=1)).to(dev)
+        descs = [fe.MeshDesc(m.elem_nodes, self.x0[:, noff[k]:noff[k + 1]].contiguous(), m.p, qs[k])
+                 for k, m in enumerate(meshes)]
+        self.ctx = fe.fe_pa_setup(descs, opts)
+        del descs
+        _, _, loff = fe.fe_mesh_offsets(self.ctx)
+        self.L2 = fe.fe_query(self.ctx)["l2_size_total"]
+        self.v = torch.from_numpy(np.concatenate([f[0] for f in fields], axis=1)).to(dev)
+        eh = np.zeros(self.L2)
+        ess = []
+        for k, (m, f) in enumerate(zip(meshes, fields)):
+            eh[loff[k]:loff[k] + f[1].size] = f[1].ravel()
+            idx = W.boundary_normal_dofs(m)
+            ess.append((idx // m.n_nodes) * self.Ntot + noff[k] + idx % m.n_nodes)
+        self.e = torch.from_numpy(eh).to(dev)
+        self.ess = torch.from_numpy(np.concatenate(ess).astype(np.int32)).to(dev)
+        self.y = torch.empty((3, self.Ntot), dtype=torch.float64, device=dev)
+        self.z = torch.empty(self.L2, dtype=torch.float64, device=dev)
+        self.a = torch.zeros((3, self.Ntot), dtype=torch.float64, device=dev)
+        self.cg = {}
+
+    def step(self):
+        fe, t = self.fe, self.torch
+        fe.fe_qdata_update(self.ctx, self.x0, self.v, self.e)
+        for _ in range(N_PAIRS):
+            fe.fe_force_mult(self.ctx, None, self.y)
+            fe.fe_force_mult_T(self.ctx, self.v, self.z)
+        # momentum equation M_v a = -F.1, a = 0 on v.n = 0 DOFs
+        t.neg(self.y, out=self.y)
+        self.a.zero_()
+        rc, it, rr = fe.fe_mass_cg(self.ctx, self.y, self.a, self.ess, rel_tol=1e-12, max_iter=5000)
+        self.cg.update(iters=it, rel_res=rr)
+
+    def time(self, steps, warmup):
+        t, fe = self.torch, self.fe
+        for _ in range(warmup):
+            self.step()
+        t.cuda.synchronize()
+        fe.fe_timer_reset(self.ctx)
+        t.cuda.synchronize()
         t0 = time.perf_counter()
-        S = O.qdata(mesh.elem_nodes, p, Q, N, mesh.x0, mesh.x0, v, e, elems=el, want=("S",))["S"]
-        t1 = time.perf_counter()
-        O.force_mult(mesh.elem_nodes, p, Q, N, S, None, elems=el)
-        O.force_mult_T(mesh.elem_nodes, p, Q, N, S, v, elems=el)
-        t2 = time.perf_counter()
-        if (t2 - t0) > budget_s / 4 or k * 2 > E:
-            break
-        k *= 2
-    frac = k / E
-    pair_s = (t2 - t1) / frac                 # one F.1 + F^T.v over the whole mesh
-    gdofs = 3 * N * 2 / pair_s / 1e9
-    return {"value": gdofs, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
-            "sample": f"F.1 + F^T.v on the first {k} of {E} elements "
-                      f"({t2 - t1:.2f} s; qdata on them {t1 - t0:.2f} s, excluded), scaled by E/{k}"}
+        for _ in range(steps):
+            self.step()
+        t.cuda.synchronize()
+        step_s = (time.perf_counter() - t0) / steps
+        per = {}
+        for name, which in (("qdata", fe.FE_TIMER_QDATA), ("force_1", fe.FE_TIMER_FORCE),
+                            ("force_T", fe.FE_TIMER_FORCE_T), ("mass", fe.FE_TIMER_MASS)):
+            ms, cnt = fe.fe_timer_read(self.ctx, which)
+            per[name] = (ms / cnt if cnt else float("nan"), ms)
+        return step_s, per
 
 
 def main():
@@ -79,6 +172,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--precision", default="fp64", choices=sorted(PRECISIONS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
@@ -120,57 +214,35 @@ def main():
                           "read_GBps": src.numel() * 8 / (ms_r * 1e-3) / 1e9}))
         return
 
-    n, p, Q, label = CONFIGS[args.config]
-    mesh = W.cube_mesh(n, p, W.default_amp(p), seed=0)
-    v_np, e_np = W.taylor_green_fields(mesh)
-    E, N = mesh.n_elem, mesh.n_nodes
-    dev = torch.device("cuda:0")
-    x0 = torch.from_numpy(mesh.x0).to(dev)
-    v = torch.from_numpy(v_np).to(dev)
-    e = torch.from_numpy(e_np).to(dev)
-    ess = torch.from_numpy(W.boundary_normal_dofs(mesh)).to(dev)
-    ctx = fe.fe_pa_setup(fe.MeshDesc(mesh.elem_nodes, x0, p, Q), fe.Opts(flags=fe.FE_OPT_TIMERS))
-    y = torch.empty((3, N), dtype=torch.float64, device=dev)
-    z = torch.empty((E, p ** 3), dtype=torch.float64, device=dev)
-    a = torch.zeros((3, N), dtype=torch.float64, device=dev)
-    cg_info = {}
-
-    def step():
-        fe.fe_qdata_update(ctx, x0, v, e)
-        for _ in range(N_PAIRS):
-            fe.fe_force_mult(ctx, None, y)
-            fe.fe_force_mult_T(ctx, v, z)
-        # momentum equation M_v a = -F.1, a = 0 on v.n = 0 DOFs
-        torch.neg(y, out=y)
-        a.zero_()
-        rc, it, rr = fe.fe_mass_cg(ctx, y, a, ess, rel_tol=1e-12, max_iter=5000)
-        cg_info.update(iters=it, rel_res=rr)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    fe.fe_timer_reset(ctx)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    step_s = (t1 - t0) / args.steps
-
-    timers = {}
-    for name, which in (("qdata", fe.FE_TIMER_QDATA), ("force_1", fe.FE_TIMER_FORCE),
-                        ("force_T", fe.FE_TIMER_FORCE_T), ("mass", fe.FE_TIMER_MASS)):
-        ms, cnt = fe.fe_timer_read(ctx, which)
-        timers[name] = (ms, cnt)
-    ab = algorithmic_bytes(E, N, p, Q)
-    per = {k: (ms / cnt if cnt else float("nan")) for k, (ms, cnt) in timers.items()}
-    dom = max(("force_1", "force_T"), key=lambda k: timers[k][0])
-    achieved = ab[dom] / (per[dom] * 1e-3) / 1e9
-    diag = fe.fe_get_diag(ctx)
-
+    if args.precision != "fp64" and args.config == "c5":
+        print("the batch workload runs the plain FP64 path", file=sys.stderr)
+        sys.exit(2)
+    meshes, qs, fields, label = build_workload(args.config, W)
+    E = sum(m.n_elem for m in meshes)
+    N = sum(m.n_nodes for m in meshes)
+    base = fe.FE_OPT_TIMERS
+    flags = base | (fe.FE_OPT_BATCHED | fe.FE_OPT_GRAPH if args.config == "c5" else 0)
+    run = Runner(torch, fe, W, meshes, qs, fields,
+                 fe.Opts(precision=PRECISIONS[args.precision], flags=flags))
+    step_s, per = run.time(args.steps, args.warmup)
+    ab = {}
+    for m, Q in zip(meshes, qs):
+        for k, b in algorithmic_bytes(m.n_elem, m.n_nodes, m.p, Q).items():
+            ab[k] = ab.get(k, 0) + b
+    if args.precision != "fp64":
+        # S and m_q are stored in 4 (FP32) or 2 (BF16) bytes instead of 8
+        rs = 4 if args.precision == "fp32" else 2
+        for m, Q in zip(meshes, qs):
+            S = 9 * Q ** 3 * m.n_elem
+            for k in ("force_1", "force_e", "force_T", "qdata"):
+                ab[k] -= S * (8 - rs)
+            ab["mass"] -= Q ** 3 * m.n_elem * 4  # m_q in FP32 (both forms)
+    dom = max(("force_1", "force_T"), key=lambda k: per[k][1])
+    achieved = ab[dom] / (per[dom][0] * 1e-3) / 1e9
+    diag = fe.fe_get_diag(run.ctx)
+    order = meshes[0].p if len(meshes) == 1 else "1..4"
     out = {
-        "metric": "F.1 + F^T.v action GDOF/s (FP64) and % HBM roofline",
+        "metric": "F.1 + F^T.v action GDOF/s and % HBM roofline",
         "value": 3 * N * 2 * N_PAIRS / step_s / 1e9,
         "unit": "GDOF/s",
         "n_gpus": 1,
@@ -180,26 +252,38 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic (seeded perturbed unit cube, Taylor-Green fields)",
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[args.precision],
+        "data": "synthetic (seeded perturbed unit cubes, Taylor-Green fields)",
         "config": {
             "workload": f"{args.config.upper()}: {label}; step = qdata + {N_PAIRS} x (F.1 + F^T.v)"
                         f" + mass CG to 1e-12",
-            "elements": E, "h1_dofs": 3 * N, "l2_dofs": E * p ** 3, "order": p, "q1d": Q,
-            "parallelism": "single GPU",
+            "meshes": len(meshes), "elements": E, "h1_dofs": 3 * N, "order": order,
+            "precision": args.precision, "parallelism": "single GPU",
+            "launch": "batched + hipGraph" if args.config == "c5" else "plain",
         },
-        "kernels_us": {k: round(vv * 1e3, 2) for k, vv in per.items()},
-        "kernels_gbs": {k: round(ab[k] / (per[k] * 1e-3) / 1e9, 1) for k in per},
-        "force_pair_gdof_s": 3 * N * 2 / ((per["force_1"] + per["force_T"]) * 1e-3) / 1e9,
-        "cg": {"iters": cg_info.get("iters"), "true_rel_res": cg_info.get("rel_res"),
-               "mass_us": round(per["mass"] * 1e3, 2)},
+        "kernels_us": {k: round(vv[0] * 1e3, 2) for k, vv in per.items()},
+        "kernels_gbs": {k: round(ab[k] / (per[k][0] * 1e-3) / 1e9, 1) for k in per},
+        "force_pair_gdof_s": 3 * N * 2 / ((per["force_1"][0] + per["force_T"][0]) * 1e-3) / 1e9,
+        "cg": {"iters": run.cg.get("iters"), "true_rel_res": run.cg.get("rel_res"),
+               "mass_us": round(per["mass"][0] * 1e3, 2)},
         "min_detj": diag["min_detj"],
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None},
     }
+    if args.config == "c5":
+        # the same step as per-mesh launches of the plain path (one context, no batching)
+        del run
+        torch.cuda.empty_cache()
+        plain = Runner(torch, fe, W, meshes, qs, fields, fe.Opts(flags=base))
+        p_step, p_per = plain.time(max(1, args.steps // 2), 1)
+        out["per_mesh_plain"] = {"value": 3 * N * 2 * N_PAIRS / p_step / 1e9,
+                                 "ms_per_step": p_step * 1e3,
+                                 "kernels_us": {k: round(vv[0] * 1e3, 2) for k, vv in p_per.items()}}
+        out["batched_speedup"] = round(p_step / step_s, 3)
+        del plain
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(mesh, v_np, e_np, p, Q)
+        out["cpu_baseline"] = cpu_baseline(meshes, qs, fields)
     print(json.dumps(out))
 
 

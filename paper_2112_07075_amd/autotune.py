@@ -7,11 +7,19 @@ choice as one line "p Q precision nw_force nw_force_t nw_mass patch" of a
 tuning table. fe_pa_setup reads that table when the environment variable
 FEPA_TUNE_TABLE names it (explicit fe_opts_t tune fields take precedence).
 
+The --builtin mode tunes every (p, Q) pair in FP64 and the Q = p+2 pairs in
+FP32 and BF16, each on a Taylor-Green cube of about 2.7M velocity DOFs (the
+benchmark workloads' own sizes where they exist), and writes the rows as the
+C++ initialiser file that the library compiles in as its default table
+(paper_2112_07075_amd/csrc/tune_table.inc).
+
 Usage: python -m paper_2112_07075_amd.autotune --n 48 --p 2 --q 4 --out tune.txt
+       python -m paper_2112_07075_amd.autotune --builtin path/to/tune_table.inc
 """
 from __future__ import annotations
 
 import argparse
+import functools
 import json
 import os
 import sys
@@ -55,13 +63,19 @@ def time_actions(fe, torch, mesh, p, Q, precision, nw, patch, reps=20):
     return out
 
 
+@functools.lru_cache(maxsize=1)
+def _mesh(n: int, p: int):
+    from . import workload as W
+    return W.cube_mesh(n, p, W.default_amp(p), seed=0)
+
+
 def tune(n: int, p: int, Q: int, precision: int = 0, verbose: bool = True):
     import torch
 
     import paper_2112_07075_amd as fe
     from . import workload as W
 
-    mesh = W.cube_mesh(n, p, W.default_amp(p), seed=0)
+    mesh = _mesh(n, p)
     best = {}
     trials = []
     for patch in patch_choices(p):
@@ -89,6 +103,44 @@ def tune(n: int, p: int, Q: int, precision: int = 0, verbose: bool = True):
     return best
 
 
+def builtin_cases():
+    """(p, Q, precision, n) of the built-in table."""
+    size = {1: 96, 2: 48, 3: 32, 4: 24}
+    cases = []
+    for p in range(1, 5):
+        for Q in (p + 1, p + 2, p + 3):
+            n = 64 if (p, Q) == (3, 5) else size[p]
+            cases.append((p, Q, 0, n))
+    for prec in (1, 2):
+        for p in range(1, 5):
+            cases.append((p, p + 2, prec, 64 if p == 3 else size[p]))
+    return cases
+
+
+def write_builtin(path: str):
+    import paper_2112_07075_amd as fe
+    rows = []
+    for p, Q, prec, n in builtin_cases():
+        print(f"== p={p} Q={Q} precision={prec} n={n}", flush=True)
+        try:
+            b = tune(n, p, Q, prec)
+        except fe.FepaError as err:
+            if err.status != fe.FE_EUNSUPPORTED:
+                raise
+            print("   unsupported, skipped", flush=True)
+            continue
+        rows.append(b)
+        print("   best:", table_line(b), json.dumps(b["us"]), flush=True)
+    with open(path, "w") as f:
+        f.write("// Generated by paper_2112_07075_amd/autotune.py --builtin: {p, Q, precision,\n"
+                "// waves F, waves F^T, waves M, elements per patch}, fastest measured on MI355X.\n")
+        for b in rows:
+            us = b["us"]
+            f.write(f"{{{b['p']}, {b['Q']}, {b['precision']}, {b['nw_force']}, {b['nw_force_t']}, "
+                    f"{b['nw_mass']}, {b['patch']}}},  // F.1 {us['force']:.1f} us, "
+                    f"F^T.v {us['force_t']:.1f} us, M x {us['mass']:.1f} us\n")
+
+
 def table_line(b) -> str:
     return (f"{b['p']} {b['Q']} {b['precision']} {b['nw_force']} {b['nw_force_t']} "
             f"{b['nw_mass']} {b['patch']}")
@@ -102,7 +154,11 @@ def main():
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--out", default="")
     ap.add_argument("--json", default="")
+    ap.add_argument("--builtin", default="", help="tune the built-in set, write this .inc file")
     args = ap.parse_args()
+    if args.builtin:
+        write_builtin(args.builtin)
+        return 0
     b = tune(args.n, args.p, args.q, args.precision)
     line = table_line(b)
     print("best:", line, json.dumps(b["us"]))

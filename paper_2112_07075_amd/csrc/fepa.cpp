@@ -43,6 +43,10 @@ struct MeshRec {
     PatchDev pd;             // device patch plan
     const int32_t *orphans = nullptr;
     int n_orphans = 0;
+    // batched form: the class (launch unit) holding the mesh and the mesh's
+    // first element in it; the mesh's pd then only views the class's perm/map
+    int unit = -1;
+    long long el_in_unit = 0;
 };
 
 struct TimerPool {
@@ -54,10 +58,35 @@ struct TimerPool {
 
 constexpr size_t kTimerPairs = 4096;
 
+// A captured graph and what it was captured for: the action and the caller's
+// pointers (a graph bakes its kernel arguments in).
+struct GraphKey {
+    int action = 0;
+    const void *a = nullptr, *b = nullptr, *c = nullptr;
+    int extra = 0;
+    bool operator==(const GraphKey &o) const
+    {
+        return action == o.action && a == o.a && b == o.b && c == o.c && extra == o.extra;
+    }
+};
+struct GraphRec {
+    GraphKey key;
+    hipGraphExec_t exec = nullptr;
+};
+constexpr int kAuxStreams = 3;     // side streams of the unit branches in a graph
+constexpr size_t kMaxGraphs = 32;  // cached graphs per context (oldest dropped)
+constexpr int kGraphCgIters = 8;   // CG iterations per captured graph
+enum { kActQdata = 1, kActForce, kActForceT, kActMass, kActCg };
+
 }  // namespace
 
 struct fe_ctx {
     std::vector<MeshRec> mesh;
+    // batched form: one launch unit per (order, Q) class, covering all of the
+    // class's meshes; otherwise every mesh is its own unit
+    bool batched = false;
+    std::vector<MeshRec> unit;
+    const std::vector<MeshRec> &units() const { return batched ? unit : mesh; }
     fe_opts_t opts{};
     hipStream_t st = nullptr;
     int device = 0;
@@ -92,6 +121,12 @@ struct fe_ctx {
     double last_res = 0.0;
     std::string err;
     TimerPool timers[FE_TIMER_COUNT];
+    // FE_OPT_GRAPH: captured action graphs, the private capture stream and the
+    // side streams / events of the parallel unit branches
+    std::vector<GraphRec> graphs;
+    hipStream_t gst = nullptr;
+    hipStream_t aux[kAuxStreams] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[kAuxStreams] = {};
 };
 
 namespace {
@@ -145,6 +180,14 @@ void free_all(fe_ctx *c)
             (void)hipEventDestroy(pr.first);
             (void)hipEventDestroy(pr.second);
         }
+    for (GraphRec &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+    for (hipStream_t s : c->aux)
+        if (s) (void)hipStreamDestroy(s);
+    if (c->gst) (void)hipStreamDestroy(c->gst);
+    for (hipEvent_t e : c->ev_join)
+        if (e) (void)hipEventDestroy(e);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
 }
 
 double key_to_double(long long k)
@@ -190,10 +233,19 @@ struct TuneEntry {
     int p, Q, prec, nwf, nwt, nwm, patch;
 };
 
-// the tuning table named by FEPA_TUNE_TABLE (missing or unreadable: empty)
+// Tile shapes measured by the autotuner (paper_2112_07075_amd/autotune.py,
+// --builtin) on MI355X, one row per (p, Q, precision); ends with a zero row.
+const TuneEntry kBuiltinTune[] = {
+#include "tune_table.inc"
+    {0, 0, 0, 0, 0, 0, 0}};
+
+// the built-in table followed by the one named by FEPA_TUNE_TABLE (missing or
+// unreadable: none); later rows take precedence
 std::vector<TuneEntry> read_tune_table()
 {
     std::vector<TuneEntry> t;
+    for (const TuneEntry &e : kBuiltinTune)
+        if (e.p) t.push_back(e);
     const char *path = std::getenv("FEPA_TUNE_TABLE");
     if (!path || !*path) return t;
     FILE *f = std::fopen(path, "r");
@@ -210,11 +262,13 @@ std::vector<TuneEntry> read_tune_table()
     return t;
 }
 
-// largest waves per workgroup (8, 4, 2) whose LDS leaves room for two workgroups per CU
-int default_nw(int lds8, int lds4)
+// Waves per workgroup when no table row applies: the largest of `pref` or
+// fewer whose LDS leaves room for two workgroups per CU (the force kernels run
+// best at 4 waves, the mass kernel at 8, at the 48^3 Q2 workload).
+int default_nw(int pref, int lds8, int lds4)
 {
-    if (lds8 <= 80 * 1024) return 8;
-    if (lds4 <= 80 * 1024) return 4;
+    if (pref >= 8 && lds8 <= 80 * 1024) return 8;
+    if (pref >= 4 && lds4 <= 80 * 1024) return 4;
     return 2;
 }
 
@@ -232,9 +286,68 @@ static const void *tab_of(fe_ctx *c, const MeshRec &r)
     return c->lo ? (const void *)(c->tabs32 + r.tab_slot) : (const void *)(c->tabs + r.tab_slot);
 }
 
-namespace {
+// Enqueues per_unit(r, stream) for every launch unit after the work already on
+// s. With branch set (graph capture) the units become independent branches,
+// spread over the side streams and joined back on s: units own disjoint nodes
+// and elements, so their outputs never overlap.
+template <typename F>
+static void enqueue_units(fe_ctx *ctx, hipStream_t s, bool branch, F &&per_unit)
+{
+    const std::vector<MeshRec> &U = ctx->units();
+    if (!branch || U.size() < 2) {
+        for (const MeshRec &r : U) per_unit(r, s);
+        return;
+    }
+    const int naux = std::min<int>(kAuxStreams, (int)U.size() - 1);
+    (void)hipEventRecord(ctx->ev_fork, s);
+    for (int i = 0; i < naux; ++i) (void)hipStreamWaitEvent(ctx->aux[i], ctx->ev_fork, 0);
+    for (size_t k = 0; k < U.size(); ++k) per_unit(U[k], k == 0 ? s : ctx->aux[(k - 1) % naux]);
+    for (int i = 0; i < naux; ++i) {
+        (void)hipEventRecord(ctx->ev_join[i], ctx->aux[i]);
+        (void)hipStreamWaitEvent(s, ctx->ev_join[i], 0);
+    }
+}
 
-}  // namespace
+// Runs enqueue(stream, branch) on the caller's stream; with FE_OPT_GRAPH it
+// replays the graph captured from enqueue for the same key instead (captured
+// on the context's private stream at first use, then launched on the caller's).
+template <typename F>
+static int run_graph(fe_ctx *ctx, const GraphKey &key, F &&enqueue)
+{
+    if (!(ctx->opts.flags & FE_OPT_GRAPH)) {
+        enqueue(ctx->st, false);
+        HIP_OK(hipGetLastError());
+        return FE_OK;
+    }
+    for (const GraphRec &g : ctx->graphs)
+        if (g.key == key) {
+            HIP_OK(hipGraphLaunch(g.exec, ctx->st));
+            return FE_OK;
+        }
+    HIP_OK(hipStreamBeginCapture(ctx->gst, hipStreamCaptureModeThreadLocal));
+    enqueue(ctx->gst, true);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(ctx->gst, &graph);
+    if (ec != hipSuccess || !graph) {
+        (void)hipGetLastError();
+        return fail(ctx, FE_EDEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, FE_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
+    }
+    if (ctx->graphs.size() >= kMaxGraphs) {
+        HIP_OK(hipStreamSynchronize(ctx->st));  // the oldest graph may still run
+        (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+        ctx->graphs.erase(ctx->graphs.begin());
+    }
+    ctx->graphs.push_back(GraphRec{key, exec});
+    HIP_OK(hipGraphLaunch(exec, ctx->st));
+    return FE_OK;
+}
 
 // ======================================================================= ABI
 extern "C" {
@@ -339,9 +452,9 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         r.kl = ctx->lo ? *fp32_kernels(r.p, r.Q) : *r.ks;
         {
             const int D = r.p + 1, rs = ctx->lo ? 4 : 8;
-            r.nw_force = default_nw(force_lds(D, r.Q, rs, 8), force_lds(D, r.Q, rs, 4));
-            r.nw_force_t = default_nw(force_t_lds(D, r.Q, rs, 8), force_t_lds(D, r.Q, rs, 4));
-            r.nw_mass = default_nw(mass_lds(D, r.Q, rs, 8), mass_lds(D, r.Q, rs, 4));
+            r.nw_force = default_nw(4, force_lds(D, r.Q, rs, 8), force_lds(D, r.Q, rs, 4));
+            r.nw_force_t = default_nw(4, force_t_lds(D, r.Q, rs, 8), force_t_lds(D, r.Q, rs, 4));
+            r.nw_mass = default_nw(8, mass_lds(D, r.Q, rs, 8), mass_lds(D, r.Q, rs, 4));
             r.patch = 0;
             for (const TuneEntry &te : tune)
                 if (te.p == r.p && te.Q == r.Q && te.prec == o.precision) {
@@ -364,13 +477,13 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
             r.kl.force = bf16_force(r.p, r.Q);
             bf16_parts(r.p, r.Q, &r.kl);
         }
-        const long long Q3 = (long long)r.Q * r.Q * r.Q;
+        // each mesh's L2 block starts at a multiple of p^3, so that an L2 element
+        // index (offset / p^3) addresses it in every mesh of the same order
+        const long long DL3 = (long long)r.p * r.p * r.p;
+        ctx->L2_tot = (ctx->L2_tot + DL3 - 1) / DL3 * DL3;
         r.node_off = ctx->N_tot;
         r.elem_off = ctx->E_tot;
         r.l2_off = ctx->L2_tot;
-        r.S_off = ctx->S_len;
-        r.Sb_off = ctx->Sb_len;
-        r.mq_off = ctx->mq_len;
         auto key = std::make_pair(r.p, r.Q);
         if (!slot_of.count(key)) {
             slot_of[key] = (int)tab_host.size();
@@ -381,12 +494,47 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         r.tab_slot = slot_of[key];
         ctx->N_tot += r.N;
         ctx->E_tot += r.E;
-        ctx->L2_tot += (long long)r.E * r.p * r.p * r.p;
+        ctx->L2_tot += (long long)r.E * DL3;
+        if (m > 0 && (r.p != ctx->mesh[0].p || r.Q != ctx->mesh[0].Q)) ctx->uniform_pq = false;
+        ctx->mesh.push_back(r);
+    }
+    // storage of S and m_q: grouped by (order, Q) class in the batched form, so
+    // that every class is one contiguous range; in caller order otherwise
+    ctx->batched = (o.flags & FE_OPT_BATCHED) != 0;
+    std::vector<int> order(n_mesh);
+    for (int m = 0; m < n_mesh; ++m) order[m] = m;
+    if (ctx->batched)
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return std::make_pair(ctx->mesh[a].p, ctx->mesh[a].Q) <
+                   std::make_pair(ctx->mesh[b].p, ctx->mesh[b].Q);
+        });
+    for (int m : order) {
+        MeshRec &r = ctx->mesh[m];
+        const long long Q3 = (long long)r.Q * r.Q * r.Q;
+        r.S_off = ctx->S_len;
+        r.Sb_off = ctx->Sb_len;
+        r.mq_off = ctx->mq_len;
         ctx->S_len += 9 * Q3 * r.E;
         ctx->Sb_len += 9 * (ctx->bf ? (Q3 + 31) / 32 * 32 : Q3) * r.E;
         ctx->mq_len += Q3 * r.E;
-        if (m > 0 && (r.p != ctx->mesh[0].p || r.Q != ctx->mesh[0].Q)) ctx->uniform_pq = false;
-        ctx->mesh.push_back(r);
+        if (ctx->batched) {
+            if (ctx->unit.empty() || ctx->unit.back().p != r.p || ctx->unit.back().Q != r.Q) {
+                MeshRec u = r;  // kernels, tables, tile shapes and storage start of the class
+                u.E = 0;
+                u.N = 0;
+                u.node_off = u.elem_off = u.l2_off = 0;
+                ctx->unit.push_back(u);
+            }
+            MeshRec &u = ctx->unit.back();
+            r.unit = (int)ctx->unit.size() - 1;
+            r.el_in_unit = u.E;
+            u.E += r.E;
+            u.N += r.N;
+        }
+    }
+    if (ctx->E_tot > (1LL << 31) - 1 || ctx->L2_tot > (1LL << 31) - 1) {
+        ctx->err = "too many elements for int32 element indices";
+        return bail(FE_EINVAL);
     }
     if (ctx->N_tot * 3 > (1LL << 31) - 1) {
         ctx->err = "too many nodes for int32 DOF indices";
@@ -422,6 +570,21 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         (rc = dev_alloc(ctx, &ctx->fr, 3 * ctx->N_tot, &wb)) || (rc = dev_alloc(ctx, &ctx->cg, 1, &wb)) ||
         (rc = dev_alloc(ctx, &ctx->bad, 1, &wb)))
         return bail(rc);
+    if (hipMemsetAsync(ctx->cg, 0, sizeof(CgState), ctx->st) != hipSuccess) {
+        ctx->err = "device memset failed";
+        return bail(FE_EDEVICE);
+    }
+    if (o.flags & FE_OPT_GRAPH) {
+        bool ok = hipStreamCreateWithFlags(&ctx->gst, hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) == hipSuccess;
+        for (int i = 0; ok && i < kAuxStreams; ++i)
+            ok = hipStreamCreateWithFlags(&ctx->aux[i], hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&ctx->ev_join[i], hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            ctx->err = "stream or event creation failed";
+            return bail(FE_EDEVICE);
+        }
+    }
     if (hipHostMalloc((void **)&ctx->h_cg, sizeof(CgState)) != hipSuccess ||
         hipHostMalloc((void **)&ctx->h_scal, 8 * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&ctx->h_key, sizeof(long long)) != hipSuccess ||
@@ -458,6 +621,7 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
             }
             r.tabb_off = boff[key];
         }
+        for (MeshRec &u : ctx->unit) u.tabb_off = boff[std::make_pair(u.p, u.Q)];
         if ((rc = dev_alloc(ctx, &ctx->tabsb, (long long)tb.size(), &wb))) return bail(rc);
         if (hipMemcpy(ctx->tabsb, tb.data(), tb.size(), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemsetAsync(ctx->S, 0, 2 * (size_t)ctx->Sb_len, ctx->st) != hipSuccess) {
@@ -480,28 +644,7 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
             return FE_EDEVICE;
         return FE_OK;
     };
-    for (int m = 0; m < n_mesh; ++m) {
-        MeshRec &r = ctx->mesh[m];
-        std::vector<double> x0h(3 * (size_t)r.N);
-        if (hipStreamSynchronize(ctx->st) != hipSuccess ||
-            hipMemcpy(x0h.data(), meshes[m].x0, x0h.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
-            ctx->err = "cannot read x0";
-            return bail(FE_EDEVICE);
-        }
-        const int D3 = (r.p + 1) * (r.p + 1) * (r.p + 1);
-        // patch size: the largest Morton block (512, 64, 8 elements) allowed for this
-        // order that still leaves >= 1024 workgroups
-        const int bmax = r.p == 1 ? 512 : (r.p == 2 ? 64 : 8);
-        int B = 8;
-        for (int cand : {512, 64, 8})
-            if (cand <= bmax && (long long)r.E / cand >= 1024) { B = cand; break; }
-        if (r.patch) B = r.patch;
-        r.patch = B;
-        PatchPlan pl = build_patch_plan(r.E, r.p, r.N, meshes[m].elem_nodes, x0h.data(), B, r.ks->umax);
-        for (auto &g : pl.map_int) g += (int32_t)r.node_off;
-        for (auto &g : pl.pn) g += (int32_t)r.node_off;
-        for (auto &g : pl.sh_node) g += (int32_t)r.node_off;
-        for (auto &g : pl.orphans) g += (int32_t)r.node_off;
+    auto upload_plan = [&](const PatchPlan &pl, MeshRec &r) -> int {
         void *dp = nullptr;
         int urc = FE_OK;
         if ((urc = upload(pl.perm.data(), pl.perm.size() * 4, &dp)) == FE_OK) r.pd.perm = (const int32_t *)dp;
@@ -514,17 +657,67 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         if (!urc && (urc = upload(pl.sh_idx.data(), pl.sh_idx.size() * 4, &dp)) == FE_OK) r.pd.sh_idx = (const int32_t *)dp;
         if (!urc && (urc = upload(nullptr, (size_t)pl.n_entries * 3 * sizeof(double), &dp)) == FE_OK) r.pd.part = (double *)dp;
         if (!urc && (urc = upload(pl.orphans.data(), pl.orphans.size() * 4, &dp)) == FE_OK) r.orphans = (const int32_t *)dp;
-        if (urc) {
-            ctx->err = "patch plan upload failed";
-            return bail(urc);
-        }
         static_assert(sizeof(PatchRec) == 6 * sizeof(int32_t), "patch table rows are 6 int32");
         r.pd.n_patch = (int)pl.patch.size();
         r.pd.n_shared = (int)pl.sh_node.size();
         r.n_orphans = (int)pl.orphans.size();
+        return urc;
+    };
+    // patch size: the largest Morton block (512, 64, 8 elements) allowed for the
+    // order that still leaves >= 1024 workgroups per launch (of the mesh, or of
+    // its class in the batched form), unless the tuning sets it
+    auto pick_patch = [](const MeshRec &r, long long E) {
+        const int bmax = r.p == 1 ? 512 : (r.p == 2 ? 64 : 8);
+        int B = 8;
+        for (int cand : {512, 64, 8})
+            if (cand <= bmax && E / cand >= 1024) { B = cand; break; }
+        return r.patch ? r.patch : B;
+    };
+    for (MeshRec &u : ctx->unit) u.patch = pick_patch(u, u.E);
+    std::vector<PatchPlan> cplan(ctx->unit.size());
+    for (int m = 0; m < n_mesh; ++m) {
+        MeshRec &r = ctx->mesh[m];
+        std::vector<double> x0h(3 * (size_t)r.N);
+        if (hipStreamSynchronize(ctx->st) != hipSuccess ||
+            hipMemcpy(x0h.data(), meshes[m].x0, x0h.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+            ctx->err = "cannot read x0";
+            return bail(FE_EDEVICE);
+        }
+        r.patch = ctx->batched ? ctx->unit[r.unit].patch : pick_patch(r, r.E);
+        PatchPlan pl = build_patch_plan(r.E, r.p, r.N, meshes[m].elem_nodes, x0h.data(), r.patch,
+                                        r.ks->umax);
+        for (auto &g : pl.map_int) g += (int32_t)r.node_off;
+        for (auto &g : pl.pn) g += (int32_t)r.node_off;
+        for (auto &g : pl.sh_node) g += (int32_t)r.node_off;
+        for (auto &g : pl.orphans) g += (int32_t)r.node_off;
+        if (ctx->batched) {
+            // element ids of the class plan are L2 element indices of the whole vector
+            const long long DL3 = (long long)r.p * r.p * r.p;
+            append_plan(cplan[r.unit], pl, (int32_t)(r.l2_off / DL3));
+            continue;
+        }
+        if (upload_plan(pl, r)) {
+            ctx->err = "patch plan upload failed";
+            return bail(FE_ENOMEM);
+        }
+    }
+    for (size_t k = 0; k < ctx->unit.size(); ++k)
+        if (upload_plan(cplan[k], ctx->unit[k])) {
+            ctx->err = "patch plan upload failed";
+            return bail(FE_ENOMEM);
+        }
+    cplan.clear();
+    for (MeshRec &r : ctx->mesh)
+        if (ctx->batched) {  // the mesh's rows of its class plan (set-up and export kernels)
+            const MeshRec &u = ctx->unit[r.unit];
+            const long long D3 = (long long)(r.p + 1) * (r.p + 1) * (r.p + 1);
+            r.pd = PatchDev{};
+            r.pd.perm = u.pd.perm + r.el_in_unit;
+            r.pd.map = u.pd.map + r.el_in_unit * D3;
+        }
+    for (MeshRec &r : ctx->batched ? ctx->unit : ctx->mesh) {
         r.part_off = ctx->n_parts;
         ctx->n_parts += r.pd.n_patch;
-        (void)D3;
     }
     if ((rc = dev_alloc(ctx, &ctx->part, std::max<long long>(ctx->n_parts, kVecBlocks), &wb)))
         return bail(rc);
@@ -606,19 +799,17 @@ int fe_qdata_update(fe_ctx_t *ctx, const double *x, const double *v, const doubl
 {
     if (!ctx) return FE_EINVAL;
     if (!x || !v || !e) return fail(ctx, FE_EINVAL, "NULL input%s");
-    launch_reset_diag(ctx->min_key, ctx->nonfinite, ctx->st);
-    {
-        ScopedTimer tm(ctx, FE_TIMER_QDATA);
-        for (const MeshRec &r : ctx->mesh) {
+    ScopedTimer tm(ctx, FE_TIMER_QDATA);
+    return run_graph(ctx, GraphKey{kActQdata, x, v, e}, [&](hipStream_t s, bool branch) {
+        launch_reset_diag(ctx->min_key, ctx->nonfinite, s);
+        enqueue_units(ctx, s, branch, [&](const MeshRec &r, hipStream_t su) {
             QParams prm{r.rho0, ctx->opts.gamma, ctx->opts.gamma - 1.0, ctx->opts.q1, ctx->opts.q2,
                         1.0 / r.p};
             r.kl.qdata(x, v, e + r.l2_off, r.pd, r.E, ctx->N_tot, 0, ctx->mq + r.mq_off,
-                        S_of(ctx, r), ctx->tabs + r.tab_slot, prm, ctx->min_key,
-                        ctx->nonfinite, false, ctx->st);
-        }
-    }
-    HIP_OK(hipGetLastError());
-    return FE_OK;
+                       S_of(ctx, r), ctx->tabs + r.tab_slot, prm, ctx->min_key, ctx->nonfinite,
+                       false, su);
+        });
+    });
 }
 
 int fe_force_mult(fe_ctx_t *ctx, const double *e, double *y)
@@ -626,17 +817,15 @@ int fe_force_mult(fe_ctx_t *ctx, const double *e, double *y)
     if (!ctx) return FE_EINVAL;
     if (!y) return fail(ctx, FE_EINVAL, "NULL output%s");
     if ((const void *)e == (const void *)y) return fail(ctx, FE_EINVAL, "input aliases output%s");
-    {
-        ScopedTimer tm(ctx, FE_TIMER_FORCE);
-        for (const MeshRec &r : ctx->mesh) {
+    ScopedTimer tm(ctx, FE_TIMER_FORCE);
+    return run_graph(ctx, GraphKey{kActForce, e, y}, [&](hipStream_t s, bool branch) {
+        enqueue_units(ctx, s, branch, [&](const MeshRec &r, hipStream_t su) {
             r.kl.force(S_of(ctx, r), e ? e + r.l2_off : nullptr, r.pd, y, ctx->N_tot,
-                       tab_of(ctx, r), r.nw_force, ctx->st);
-            launch_gather_shared(r.pd, y, ctx->N_tot, nullptr, ctx->st);
-            launch_zero_nodes(r.orphans, r.n_orphans, y, ctx->N_tot, nullptr, ctx->st);
-        }
-    }
-    HIP_OK(hipGetLastError());
-    return FE_OK;
+                       tab_of(ctx, r), r.nw_force, su);
+            launch_gather_shared(r.pd, y, ctx->N_tot, nullptr, su);
+            launch_zero_nodes(r.orphans, r.n_orphans, y, ctx->N_tot, nullptr, su);
+        });
+    });
 }
 
 int fe_force_mult_T(fe_ctx_t *ctx, const double *v, double *z)
@@ -644,30 +833,45 @@ int fe_force_mult_T(fe_ctx_t *ctx, const double *v, double *z)
     if (!ctx) return FE_EINVAL;
     if (!v || !z) return fail(ctx, FE_EINVAL, "NULL argument%s");
     if ((const void *)v == (const void *)z) return fail(ctx, FE_EINVAL, "input aliases output%s");
-    {
-        ScopedTimer tm(ctx, FE_TIMER_FORCE_T);
-        for (const MeshRec &r : ctx->mesh)
+    ScopedTimer tm(ctx, FE_TIMER_FORCE_T);
+    return run_graph(ctx, GraphKey{kActForceT, v, z}, [&](hipStream_t s, bool branch) {
+        enqueue_units(ctx, s, branch, [&](const MeshRec &r, hipStream_t su) {
             r.kl.force_t(S_of(ctx, r), v, r.pd, r.E, z + r.l2_off, ctx->N_tot, tab_of(ctx, r),
-                         r.nw_force_t, ctx->st);
-    }
-    HIP_OK(hipGetLastError());
-    return FE_OK;
+                         r.nw_force_t, su);
+        });
+    });
 }
 
-// lo: the FP32 operator (precision form); otherwise the FP64 operator
-static void mass_launch(fe_ctx *ctx, const double *x, double *y, bool dot, const int *skip,
-                        bool lo = false)
+// lo: the FP32 operator (precision form); otherwise the FP64 operator.
+// With x2 set, the launch is a CG iteration's: the operand is x + beta x2
+// (x = r, x2 = p; beta and the done flag from the device CG state) and the
+// kernels leave partials of the operand's M-norm in ctx->part.
+static void mass_enqueue(fe_ctx *ctx, const double *x, double *y, bool lo, const double *x2,
+                         hipStream_t s, bool branch)
 {
-    for (const MeshRec &r : ctx->mesh) {
+    const int *skip = x2 ? &ctx->cg->done : nullptr;
+    enqueue_units(ctx, s, branch, [&](const MeshRec &r, hipStream_t su) {
+        MassCg cg;
+        if (x2) {
+            cg.part_dot = ctx->part + r.part_off;
+            cg.skip = skip;
+            cg.x2 = x2;
+            cg.beta = &ctx->cg->beta;
+        }
         if (lo)
-            r.kl.mass(ctx->mq32 + r.mq_off, x, r.pd, y, ctx->N_tot, ctx->tabs32 + r.tab_slot,
-                      dot ? ctx->part + r.part_off : nullptr, skip, r.nw_mass, ctx->st);
+            r.kl.mass(ctx->mq32 + r.mq_off, x, r.pd, y, ctx->N_tot, ctx->tabs32 + r.tab_slot, cg,
+                      r.nw_mass, su);
         else
-            r.ks->mass(ctx->mq + r.mq_off, x, r.pd, y, ctx->N_tot, ctx->tabs + r.tab_slot,
-                       dot ? ctx->part + r.part_off : nullptr, skip, r.nw_mass, ctx->st);
-        launch_gather_shared(r.pd, y, ctx->N_tot, skip, ctx->st);
-        launch_zero_nodes(r.orphans, r.n_orphans, y, ctx->N_tot, skip, ctx->st);
-    }
+            r.ks->mass(ctx->mq + r.mq_off, x, r.pd, y, ctx->N_tot, ctx->tabs + r.tab_slot, cg,
+                       r.nw_mass, su);
+        launch_gather_shared(r.pd, y, ctx->N_tot, skip, su);
+        launch_zero_nodes(r.orphans, r.n_orphans, y, ctx->N_tot, skip, su);
+    });
+}
+
+static void mass_launch(fe_ctx *ctx, const double *x, double *y, bool lo)
+{
+    mass_enqueue(ctx, x, y, lo, nullptr, ctx->st, false);
 }
 
 int fe_mass_mult(fe_ctx_t *ctx, const double *x, double *y)
@@ -675,12 +879,9 @@ int fe_mass_mult(fe_ctx_t *ctx, const double *x, double *y)
     if (!ctx) return FE_EINVAL;
     if (!x || !y) return fail(ctx, FE_EINVAL, "NULL argument%s");
     if ((const void *)x == (const void *)y) return fail(ctx, FE_EINVAL, "input aliases output%s");
-    {
-        ScopedTimer tm(ctx, FE_TIMER_MASS);
-        mass_launch(ctx, x, y, false, nullptr, ctx->lo);
-    }
-    HIP_OK(hipGetLastError());
-    return FE_OK;
+    ScopedTimer tm(ctx, FE_TIMER_MASS);
+    return run_graph(ctx, GraphKey{kActMass, x, y, nullptr, ctx->lo ? 1 : 0},
+                     [&](hipStream_t s, bool branch) { mass_enqueue(ctx, x, y, ctx->lo, nullptr, s, branch); });
 }
 
 }  // extern "C"
@@ -692,22 +893,37 @@ static int cg_run(fe_ctx *ctx, const double *b, double *x, double rel_tol, int m
                   CgState *out)
 {
     const long long n = 3 * ctx->N_tot;
-    mass_launch(ctx, x, ctx->Ap, false, nullptr, lo);
+    mass_launch(ctx, x, ctx->Ap, lo);
     cg_start(b, ctx->Ap, ctx->r, ctx->p, ctx->fr, n, ctx->part, ctx->part2, ctx->cg, rel_tol,
              max_iter, ctx->st);
     HIP_OK(hipGetLastError());
-    const int *skip = &ctx->cg->done;
-    int batch = 4;
+    // one iteration: Ap = M (r + beta p) with partials of its M-norm, then the step
+    auto iteration = [&](hipStream_t s, bool branch) {
+        mass_enqueue(ctx, ctx->r, ctx->Ap, lo, ctx->p, s, branch);
+        cg_step(x, ctx->r, ctx->p, ctx->Ap, ctx->fr, n, ctx->part, (int)ctx->n_parts, ctx->cg,
+                ctx->part2, s);
+    };
+    const bool graph = (ctx->opts.flags & FE_OPT_GRAPH) != 0;
+    int batch = graph ? kGraphCgIters : 4;
     for (;;) {
-        for (int k = 0; k < batch; ++k) {
-            {
-                ScopedTimer tm(ctx, FE_TIMER_MASS);
-                mass_launch(ctx, ctx->p, ctx->Ap, true, skip, lo);
+        if (graph) {
+            // kGraphCgIters iterations per replay; finished iterations are no-ops
+            for (int k = 0; k < batch; k += kGraphCgIters) {
+                const int rc = run_graph(ctx, GraphKey{kActCg, x, nullptr, nullptr, lo ? 1 : 0},
+                                         [&](hipStream_t s, bool branch) {
+                                             for (int i = 0; i < kGraphCgIters; ++i) iteration(s, branch);
+                                         });
+                if (rc) return rc;
             }
-            cg_alpha(ctx->part, (int)ctx->n_parts, ctx->cg, ctx->st);
-            cg_update(x, ctx->r, ctx->p, ctx->Ap, ctx->fr, n, ctx->cg, ctx->part2, ctx->st);
-            cg_beta(ctx->part2, ctx->cg, ctx->st);
-            cg_direction(ctx->p, ctx->r, n, ctx->cg, ctx->st);
+        } else {
+            for (int k = 0; k < batch; ++k) {
+                {
+                    ScopedTimer tm(ctx, FE_TIMER_MASS);
+                    mass_enqueue(ctx, ctx->r, ctx->Ap, lo, ctx->p, ctx->st, false);
+                }
+                cg_step(x, ctx->r, ctx->p, ctx->Ap, ctx->fr, n, ctx->part, (int)ctx->n_parts,
+                        ctx->cg, ctx->part2, ctx->st);
+            }
         }
         HIP_OK(hipGetLastError());
         HIP_OK(hipMemcpyAsync(ctx->h_cg, ctx->cg, sizeof(CgState), hipMemcpyDeviceToHost, ctx->st));
@@ -725,7 +941,7 @@ static int cg_run(fe_ctx *ctx, const double *b, double *x, double rel_tol, int m
 static int true_resid2(fe_ctx *ctx, const double *b, const double *x, double *res2)
 {
     const long long n = 3 * ctx->N_tot;
-    mass_launch(ctx, x, ctx->Ap, false, nullptr, false);
+    mass_launch(ctx, x, ctx->Ap, false);
     resid_norm2(b, ctx->Ap, ctx->fr, n, ctx->part2, ctx->scal, ctx->st);
     HIP_OK(hipMemcpyAsync(ctx->h_scal, ctx->scal, sizeof(double), hipMemcpyDeviceToHost, ctx->st));
     HIP_OK(hipStreamSynchronize(ctx->st));
@@ -812,14 +1028,17 @@ int fe_export_qdata(fe_ctx_t *ctx, double *S_out, double *mq_out)
     if (!ctx->uniform_pq) return fail(ctx, FE_EINVAL, "export needs one (order, q1d) for all meshes%s");
     for (const MeshRec &r : ctx->mesh) {
         const int Q3 = r.Q * r.Q * r.Q;
+        // batched form: the mesh's element ids are already global (one order, so
+        // L2 element index = caller element index); otherwise mesh-local
+        const long long e0 = ctx->batched ? 0 : r.elem_off;
         if (S_out && ctx->bf)
             launch_unpermute_s_bf16(S_of(ctx, r), r.pd.perm, r.E, Q3, (Q3 + 31) / 32 * 32,
-                                    S_out + r.S_off, ctx->st);
+                                    S_out + e0 * 9 * Q3, ctx->st);
         else if (S_out)
-            launch_unpermute_rows(S_of(ctx, r), ctx->lo, r.pd.perm, r.E, 9 * Q3, S_out + r.S_off,
-                                  ctx->st);
+            launch_unpermute_rows(S_of(ctx, r), ctx->lo, r.pd.perm, r.E, 9 * Q3,
+                                  S_out + e0 * 9 * Q3, ctx->st);
         if (mq_out)
-            launch_unpermute_rows(ctx->mq + r.mq_off, false, r.pd.perm, r.E, Q3, mq_out + r.mq_off,
+            launch_unpermute_rows(ctx->mq + r.mq_off, false, r.pd.perm, r.E, Q3, mq_out + e0 * Q3,
                                   ctx->st);
     }
     HIP_OK(hipGetLastError());

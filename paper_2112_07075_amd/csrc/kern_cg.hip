@@ -1,7 +1,9 @@
 // Vector kernels of the mass conjugate-gradient solve (the CG inversion of the
 // kinematic mass matrix, paper Sec. 3.3 and Sec. 6): masked residual set-up,
-// fused axpy + dot, direction update, and deterministic two-level FP64
-// reductions (per-workgroup partials, then one workgroup). The iteration state
+// one fused step kernel per iteration (direction, axpys and r.r) plus a
+// one-workgroup kernel for beta, and
+// deterministic two-level FP64 reductions (per-workgroup partials, then one
+// workgroup, always summed in the same order). The iteration state
 // lives on the device; every kernel leaves at once when the solve is done, so
 // the host can enqueue batches of iterations and poll rarely.
 #include "kern_cg.hpp"
@@ -99,42 +101,41 @@ __global__ void k_cg_start_final(const double *__restrict__ part_rr,
     }
 }
 
-// alpha = rr / (p . M p) from the mass kernel's per-workgroup partials
-__global__ void k_cg_alpha(const double *__restrict__ part, int nparts, CgState *__restrict__ st)
+// One step of the iteration. Every workgroup sums the mass kernel's partials
+// of p'.Ap in the same order, so all agree on alpha without another launch;
+// the new r.r is left as per-workgroup partials for k_cg_beta. (A last-
+// workgroup reduction here would need a device-scope release fence per
+// workgroup, which writes back the XCD's L2 and costs more than a launch.)
+__global__ void k_cg_step(double *__restrict__ x, double *__restrict__ r, double *__restrict__ p,
+                          const double *__restrict__ Ap, const unsigned char *__restrict__ fr,
+                          long long n, const double *__restrict__ part_pap, int n_pap,
+                          const CgState *__restrict__ st, double *__restrict__ part)
 {
     __shared__ double sred[16];
+    __shared__ double s_alpha;
     if (st->done) return;
     double s = 0.0;
-    for (int k = threadIdx.x; k < nparts; k += blockDim.x) s += part[k];
+    for (int k = threadIdx.x; k < n_pap; k += blockDim.x) s += part_pap[k];
     s = block_sum(s, sred);
-    if (threadIdx.x == 0) {
-        st->pAp = s;
-        st->alpha = st->rr / s;
-    }
-}
-
-// x += alpha p; r -= alpha Ap (free DOFs); partials of the new r.r
-__global__ void k_cg_update(double *__restrict__ x, double *__restrict__ r,
-                            const double *__restrict__ p, const double *__restrict__ Ap,
-                            const unsigned char *__restrict__ fr, long long n,
-                            const CgState *__restrict__ st, double *__restrict__ part)
-{
-    __shared__ double sred[16];
-    if (st->done) return;
-    const double alpha = st->alpha;
+    if (threadIdx.x == 0) s_alpha = st->rr / s;
+    __syncthreads();
+    const double alpha = s_alpha, beta = st->beta;
     double rr = 0.0;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        x[i] += alpha * p[i];
-        const double ri = fr[i] ? r[i] - alpha * Ap[i] : 0.0;
-        r[i] = ri;
-        rr += ri * ri;
+        const double ri = r[i];
+        const double pi = ri + beta * p[i];
+        p[i] = pi;
+        x[i] += alpha * pi;
+        const double rn = fr[i] ? ri - alpha * Ap[i] : 0.0;
+        r[i] = rn;
+        rr += rn * rn;
     }
     rr = block_sum(rr, sred);
     if (threadIdx.x == 0) part[blockIdx.x] = rr;
 }
 
-// beta = rr_new / rr; convergence and iteration-limit checks
+// One workgroup: the new r.r, beta = rr_new / rr, convergence and limit checks.
 __global__ void k_cg_beta(const double *__restrict__ part, int nparts, CgState *__restrict__ st)
 {
     __shared__ double sred[16];
@@ -151,17 +152,6 @@ __global__ void k_cg_beta(const double *__restrict__ part, int nparts, CgState *
         else if (st->iter >= st->max_iter)
             st->done = 2;
     }
-}
-
-// p = r + beta p
-__global__ void k_cg_direction(double *__restrict__ p, const double *__restrict__ r, long long n,
-                               const CgState *__restrict__ st)
-{
-    if (st->done) return;
-    const double beta = st->beta;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        p[i] = r[i] + beta * p[i];
 }
 
 // partials of the free-DOF residual norm ||b - Ax||^2
@@ -242,26 +232,13 @@ void cg_start(const double *b, const double *Ax, double *r, double *p, const uns
                        state, rel_tol, max_iter);
 }
 
-void cg_alpha(const double *part, int nparts, CgState *state, hipStream_t st)
+void cg_step(double *x, double *r, double *p, const double *Ap, const unsigned char *fr,
+             long long n, const double *part_pap, int n_pap, CgState *state, double *part,
+             hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, st, part, nparts, state);
-}
-
-void cg_update(double *x, double *r, const double *p, const double *Ap, const unsigned char *fr,
-               long long n, const CgState *state, double *part, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_cg_update, dim3(kVecBlocks), dim3(256), 0, st, x, r, p, Ap, fr, n, state,
-                       part);
-}
-
-void cg_beta(const double *part, CgState *state, hipStream_t st)
-{
+    hipLaunchKernelGGL(k_cg_step, dim3(kVecBlocks), dim3(256), 0, st, x, r, p, Ap, fr, n, part_pap,
+                       n_pap, state, part);
     hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1024), 0, st, part, kVecBlocks, state);
-}
-
-void cg_direction(double *p, const double *r, long long n, const CgState *state, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_cg_direction, dim3(kVecBlocks), dim3(256), 0, st, p, r, n, state);
 }
 
 void resid_norm2(const double *b, const double *Ax, const unsigned char *fr, long long n,

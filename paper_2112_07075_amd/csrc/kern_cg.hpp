@@ -20,11 +20,13 @@ void cg_mask_apply(double *x, const unsigned char *fr, long long n, hipStream_t 
 void cg_start(const double *b, const double *Ax, double *r, double *p, const unsigned char *fr,
               long long n, double *part_a, double *part_b, CgState *state, double rel_tol,
               int max_iter, hipStream_t st);
-void cg_alpha(const double *part, int nparts, CgState *state, hipStream_t st);
-void cg_update(double *x, double *r, const double *p, const double *Ap, const unsigned char *fr,
-               long long n, const CgState *state, double *part, hipStream_t st);
-void cg_beta(const double *part, CgState *state, hipStream_t st);
-void cg_direction(double *p, const double *r, long long n, const CgState *state, hipStream_t st);
+// One CG step after Ap = M p' with p' = r + beta p (the mass kernel forms p'
+// during its gather and leaves partials of p'.Ap in part_pap): p = p',
+// alpha = rr / (p.Ap), x += alpha p, r -= alpha Ap on free DOFs; then one
+// workgroup finishes r.r and sets beta, the iteration count and done.
+void cg_step(double *x, double *r, double *p, const double *Ap, const unsigned char *fr,
+             long long n, const double *part_pap, int n_pap, CgState *state, double *part,
+             hipStream_t st);
 void vec_sub_masked(const double *b, const double *Ax, const unsigned char *fr, double *out,
                     long long n, hipStream_t st);
 void vec_add(double *x, const double *d, long long n, hipStream_t st);

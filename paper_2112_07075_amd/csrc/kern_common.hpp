@@ -128,8 +128,7 @@ __host__ __device__ constexpr int force_t_lds(int D, int Q, int rs, int NW)
 }
 __host__ __device__ constexpr int mass_lds(int D, int Q, int rs, int NW)
 {
-    return 2 * rs * patch_umax(D) + (4 * NW * wave_ne(Q) + 1) * 4 * D * D * D +
-           (NW * wave_ne(Q) + 1) * rs * (D * D * Q + D * Q * Q) + 128;
+    return 2 * rs * patch_umax(D) + (NW * wave_ne(Q) + 1) * (4 * D * D * D + rs * (D * D * Q + D * Q * Q)) + 64;
 }
 
 // One row of the patch table: first element, element count, offset of the

@@ -308,12 +308,10 @@ k_force_t(const RS *__restrict__ S, const double *__restrict__ v,
 // y_c = R^T B^T diag(m_q) B R x_c, one patch per workgroup, one component at a
 // time: the patch's distinct-node values of x_c are read once into LDS, each
 // wave works through its own elements and sums into the patch's LDS slots,
-// and the component is written out before the next one starts. Elements are
-// taken in groups of MAXP passes whose m_q (registers) and slots (LDS) are
-// loaded together, so a patch waits for memory once per group, not per pass.
-// With DOT, the workgroup also writes sum_E x_E^T (M_E x_E) (= x^T M x over
-// its elements).
-constexpr int kMassGroup = 4;  // passes per load group
+// and the component is written out before the next one starts. With DOT, the
+// workgroup also writes sum_E x_E^T (M_E x_E) (= x^T M x over its elements).
+// With x2 the operand is x + beta x2, formed during the gather (a CG
+// iteration's new direction r + beta p, never stored by this kernel).
 
 template <int D, int Q, bool DOT, typename R, int NW>
 __global__ void __launch_bounds__(NW * 64)
@@ -322,18 +320,19 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
        const int32_t *__restrict__ pn, const int32_t *__restrict__ ptab,
        double *__restrict__ y, double *__restrict__ part, long long ncomp,
        const R *__restrict__ tab, double *__restrict__ part_dot,
-       const int *__restrict__ skip)
+       const int *__restrict__ skip, const double *__restrict__ x2,
+       const double *__restrict__ beta)
 {
-    constexpr int NE = NW * wave_ne(Q), UMAX = patch_umax(D), MAXP = kMassGroup;
+    constexpr int NE = NW * wave_ne(Q), UMAX = patch_umax(D);
     constexpr int QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D;
     using T = Tab<D, Q>;
     if (skip && *skip) return;  // a finished CG solve
     __shared__ R acc[UMAX];
     __shared__ R xs[UMAX];
-    __shared__ int sSl[MAXP * NE + 1][D3];
+    __shared__ int sSl[NE + 1][D3];
     __shared__ R sX[NE + 1][D][D * Q];  // x-stage out, then y^T out
     __shared__ R sZ[NE + 1][D][QQ];
-    __shared__ double sred[16];
+    __shared__ double sred[8];
     (void)map;
 
     const Lane L = lane_map<Q, NE>();
@@ -351,98 +350,87 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
         cBx[k] = qx < D ? tab[T::B + k * D + qx] : (R)0;
     }
     double dot = 0.0;
-    for (int i = tid; i < D3; i += blockDim.x) sSl[MAXP * NE][i] = 0;  // spare row of idle lanes
+    const double bt = x2 ? *beta : 0.0;
 
 #pragma unroll 1
     for (int c = 0; c < 3; ++c) {
         for (int u = tid; u < pr.U; u += blockDim.x) {
-            xs[u] = (R)x[c * ncomp + pn[pr.pno + u]];
+            const long long g = c * ncomp + pn[pr.pno + u];
+            xs[u] = (R)(x2 ? x[g] + bt * x2[g] : x[g]);
             acc[u] = (R)0;
         }
+        __syncthreads();
 #pragma unroll 1
-        for (int g0 = 0; g0 < pr.cnt; g0 += MAXP * NE) {
-            const int gcnt = min(MAXP * NE, pr.cnt - g0);
-            // the group's m_q into registers and its slots into LDS, all loads in flight
-            R m[MAXP][Q];
+        for (int base = 0; base < pr.cnt; base += NE) {
+            const int idx = base + le;
+            const bool act = L.valid && idx < pr.cnt;
+            const long long el = pr.eb + (act ? idx : 0);
+            R m[Q];
 #pragma unroll
-            for (int k = 0; k < MAXP; ++k) {
-                const int idx = k * NE + le;
-                const bool act = L.valid && idx < gcnt;
-                const long long el = pr.eb + g0 + (act ? idx : 0);
-#pragma unroll
-                for (int qz = 0; qz < Q; ++qz) m[k][qz] = act ? mq[el * Q3 + qz * QQ + t] : (R)0;
-            }
-            for (int i = tid; i < gcnt * D3; i += blockDim.x)
-                sSl[i / D3][i % D3] = slot[(long long)(pr.eb + g0) * D3 + i];
-            __syncthreads();  // xs, acc (first group) and the group's slots are ready
-#pragma unroll
-            for (int k = 0; k < MAXP; ++k) {
-                const int idx = k * NE + le;
-                const bool act = L.valid && idx < gcnt;
-                const int sl = act ? idx : MAXP * NE;  // spare row for idle lanes
-                if (k * NE >= gcnt) break;             // uniform: no element of the pass left
-                // x-stage: thread (qx, iy = qy)
-                if (qy < D) {
-#pragma unroll
-                    for (int iz = 0; iz < D; ++iz) {
-                        R a = 0;
-#pragma unroll
-                        for (int ix = 0; ix < D; ++ix) a += rBx[ix] * xs[sSl[sl][(iz * D + qy) * D + ix]];
-                        sX[le][iz][qy * Q + qx] = a;
-                    }
-                }
-                wave_sync();
-                // y-stage, z-stage, weights, z^T in registers of thread (qx, qy)
-                R w[D];
+            for (int k = 0; k < Q; ++k) m[k] = act ? mq[el * Q3 + k * QQ + t] : (R)0;
+            for (int i = t; i < D3; i += QQ) sSl[le][i] = act ? slot[el * D3 + i] : 0;
+            wave_sync();
+            // x-stage: thread (qx, iy = qy)
+            if (qy < D) {
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
                     R a = 0;
 #pragma unroll
-                    for (int iy = 0; iy < D; ++iy) a += rBy[iy] * sX[le][iz][iy * Q + qx];
-                    w[iz] = a;
+                    for (int ix = 0; ix < D; ++ix) a += rBx[ix] * xs[sSl[le][(iz * D + qy) * D + ix]];
+                    sX[le][iz][qy * Q + qx] = a;
                 }
-                R a[D];
-#pragma unroll
-                for (int iz = 0; iz < D; ++iz) a[iz] = 0;
-#pragma unroll
-                for (int qz = 0; qz < Q; ++qz) {
-                    R u = 0;
-#pragma unroll
-                    for (int iz = 0; iz < D; ++iz) u += tab[T::B + qz * D + iz] * w[iz];
-                    u *= m[k][qz];
-#pragma unroll
-                    for (int iz = 0; iz < D; ++iz) a[iz] += tab[T::B + qz * D + iz] * u;
-                }
-#pragma unroll
-                for (int iz = 0; iz < D; ++iz) sZ[le][iz][t] = a[iz];
-                wave_sync();
-                // y^T: thread (qx, iy = qy), into sX
-                if (qy < D) {
-#pragma unroll
-                    for (int iz = 0; iz < D; ++iz) {
-                        R b = 0;
-#pragma unroll
-                        for (int kk = 0; kk < Q; ++kk) b += cBy[kk] * sZ[le][iz][kk * Q + qx];
-                        sX[le][iz][qy * Q + qx] = b;
-                    }
-                }
-                wave_sync();
-                // x^T: thread (ix = qx, iy = qy), summed into the patch slots
-                if (act && qx < D && qy < D) {
-#pragma unroll
-                    for (int iz = 0; iz < D; ++iz) {
-                        const int s = sSl[sl][(iz * D + qy) * D + qx];
-                        R r = 0;
-#pragma unroll
-                        for (int kk = 0; kk < Q; ++kk) r += cBx[kk] * sX[le][iz][qy * Q + kk];
-                        atomicAdd(&acc[s], r);
-                        if (DOT) dot += (double)r * (double)xs[s];
-                    }
-                }
-                wave_sync();  // sX is rewritten by the next pass
             }
-            __syncthreads();  // sSl is rewritten by the next group
+            wave_sync();
+            // y-stage, z-stage, weights, z^T in registers of thread (qx, qy)
+            R w[D];
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) {
+                R a = 0;
+#pragma unroll
+                for (int iy = 0; iy < D; ++iy) a += rBy[iy] * sX[le][iz][iy * Q + qx];
+                w[iz] = a;
+            }
+            R a[D];
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) a[iz] = 0;
+#pragma unroll
+            for (int qz = 0; qz < Q; ++qz) {
+                R u = 0;
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) u += tab[T::B + qz * D + iz] * w[iz];
+                u *= m[qz];
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) a[iz] += tab[T::B + qz * D + iz] * u;
+            }
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) sZ[le][iz][t] = a[iz];
+            wave_sync();
+            // y^T: thread (qx, iy = qy), into sX
+            if (qy < D) {
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) {
+                    R b = 0;
+#pragma unroll
+                    for (int k = 0; k < Q; ++k) b += cBy[k] * sZ[le][iz][k * Q + qx];
+                    sX[le][iz][qy * Q + qx] = b;
+                }
+            }
+            wave_sync();
+            // x^T: thread (ix = qx, iy = qy), summed into the patch slots
+            if (act && qx < D && qy < D) {
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) {
+                    const int s = sSl[le][(iz * D + qy) * D + qx];
+                    R r = 0;
+#pragma unroll
+                    for (int k = 0; k < Q; ++k) r += cBx[k] * sX[le][iz][qy * Q + k];
+                    atomicAdd(&acc[s], r);
+                    if (DOT) dot += (double)r * (double)xs[s];
+                }
+            }
+            wave_sync();  // sSl and sX are rewritten by the next pass
         }
+        __syncthreads();
         for (int u = tid; u < pr.U; u += blockDim.x) {
             const double a = (double)acc[u];
             if (u < pr.P)
@@ -735,29 +723,25 @@ struct Launch {
     }
     template <int NW>
     static void mass_nw(const void *mq, const double *x, const PatchDev &pd, double *y,
-                        long long ncomp, const void *tab, double *part_dot, const int *skip,
-                        hipStream_t st)
+                        long long ncomp, const void *tab, const MassCg &cg, hipStream_t st)
     {
         const dim3 grid(pd.n_patch), block(NW * 64);
-        if (part_dot)
+        if (cg.part_dot)
             hipLaunchKernelGGL((k_mass<D, Q, true, R, NW>), grid, block, 0, st, (const R *)mq, x,
                                pd.map, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab,
-                               part_dot, skip);
+                               cg.part_dot, cg.skip, cg.x2, cg.beta);
         else
             hipLaunchKernelGGL((k_mass<D, Q, false, R, NW>), grid, block, 0, st, (const R *)mq, x,
                                pd.map, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab,
-                               part_dot, skip);
+                               cg.part_dot, cg.skip, cg.x2, cg.beta);
     }
     static void mass(const void *mq, const double *x, const PatchDev &pd, double *y,
-                     long long ncomp, const void *tab, double *part_dot, const int *skip, int nw,
-                     hipStream_t st)
+                     long long ncomp, const void *tab, const MassCg &cg, int nw, hipStream_t st)
     {
         constexpr int rs = sizeof(R);
-        if (nw >= 8 && mass_lds(D, Q, rs, 8) <= kLdsMax)
-            return mass_nw<8>(mq, x, pd, y, ncomp, tab, part_dot, skip, st);
-        if (nw >= 4 && mass_lds(D, Q, rs, 4) <= kLdsMax)
-            return mass_nw<4>(mq, x, pd, y, ncomp, tab, part_dot, skip, st);
-        return mass_nw<2>(mq, x, pd, y, ncomp, tab, part_dot, skip, st);
+        if (nw >= 8 && mass_lds(D, Q, rs, 8) <= kLdsMax) return mass_nw<8>(mq, x, pd, y, ncomp, tab, cg, st);
+        if (nw >= 4 && mass_lds(D, Q, rs, 4) <= kLdsMax) return mass_nw<4>(mq, x, pd, y, ncomp, tab, cg, st);
+        return mass_nw<2>(mq, x, pd, y, ncomp, tab, cg, st);
     }
     // Largest waves per workgroup (8, 4, 2) of kernel kind (0 force, 1 force^T,
     // 2 mass) whose instances fit the LDS limit and keep every value in

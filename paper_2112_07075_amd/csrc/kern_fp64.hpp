@@ -28,6 +28,16 @@ struct PatchDev {
     double *part = nullptr;          // [entries][3] shared-node partials
 };
 
+// CG extras of a mass launch: part_dot receives per-workgroup partials of
+// x . M x; with x2 the operand is x + (*beta) x2; skip points at a device flag
+// that makes the launch a no-op when set. All null for a plain action.
+struct MassCg {
+    double *part_dot = nullptr;
+    const int *skip = nullptr;
+    const double *x2 = nullptr;
+    const double *beta = nullptr;
+};
+
 // Launchers of one (p, Q) instance; ncomp is the component stride of H1 vectors.
 // S, m_q and tab of force/force_t/mass are of the set's real type (double for
 // fp64_kernels, float for fp32_kernels); qdata always takes the FP64 table and
@@ -40,8 +50,7 @@ struct KernelSet {
     void (*force_t)(const void *S, const double *v, const PatchDev &pd, int E, double *z,
                     long long ncomp, const void *tab, int nw, hipStream_t st);
     void (*mass)(const void *mq, const double *x, const PatchDev &pd, double *y,
-                 long long ncomp, const void *tab, double *part_dot, const int *skip, int nw,
-                 hipStream_t st);
+                 long long ncomp, const void *tab, const MassCg &cg, int nw, hipStream_t st);
     void (*qdata)(const double *x, const double *v, const double *e, const PatchDev &pd, int E,
                   long long ncomp, int node_off, double *mq, void *S, const double *tab,
                   QParams prm, long long *min_key, int *nonfinite, bool init, hipStream_t st);

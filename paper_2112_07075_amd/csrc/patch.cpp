@@ -165,4 +165,27 @@ PatchPlan build_patch_plan(int E, int p, int N, const int32_t *map, const double
     return pl;
 }
 
+void append_plan(PatchPlan &dst, const PatchPlan &src, int32_t perm_base)
+{
+    const int e0 = (int)dst.perm.size(), pn0 = (int)dst.pn.size(), en0 = dst.n_entries;
+    const int idx0 = (int)dst.sh_idx.size();
+    for (int32_t g : src.perm) dst.perm.push_back(g + perm_base);
+    dst.map_int.insert(dst.map_int.end(), src.map_int.begin(), src.map_int.end());
+    dst.slot.insert(dst.slot.end(), src.slot.begin(), src.slot.end());
+    dst.pn.insert(dst.pn.end(), src.pn.begin(), src.pn.end());
+    for (PatchRec r : src.patch) {
+        r.elem_begin += e0;
+        r.pn_off += pn0;
+        r.sh_off += en0;
+        dst.patch.push_back(r);
+    }
+    if (dst.sh_ptr.empty()) dst.sh_ptr.push_back(0);
+    dst.sh_node.insert(dst.sh_node.end(), src.sh_node.begin(), src.sh_node.end());
+    for (size_t k = 1; k < src.sh_ptr.size(); ++k) dst.sh_ptr.push_back(src.sh_ptr[k] + idx0);
+    for (int32_t j : src.sh_idx) dst.sh_idx.push_back(j + en0);
+    dst.orphans.insert(dst.orphans.end(), src.orphans.begin(), src.orphans.end());
+    dst.n_entries += src.n_entries;
+    dst.umax_used = std::max(dst.umax_used, src.umax_used);
+}
+
 }  // namespace fepa

@@ -32,4 +32,11 @@ struct PatchPlan {
 PatchPlan build_patch_plan(int E, int p, int N, const int32_t *map, const double *x0, int B,
                            int umax);
 
+// Appends the plan of another mesh of the same order behind dst: its elements
+// follow dst's, its element ids (perm) are shifted by perm_base, and its patch
+// rows and shared-node lists are re-based onto dst's arrays. Node ids must
+// already be global (meshes own disjoint node ranges), so no patch spans two
+// meshes and the kernels treat the result as one mesh.
+void append_plan(PatchPlan &dst, const PatchPlan &src, int32_t perm_base);
+
 }  // namespace fepa

@@ -160,7 +160,15 @@ def test_multi_mesh_context(torch_cuda):
     assert list(no) == list(offs[:-1])
     x = dev(torch_cuda, np.concatenate([c.x for c in cases], axis=1))
     v = dev(torch_cuda, np.concatenate([c.v for c in cases], axis=1))
-    e = dev(torch_cuda, np.concatenate([c.e.ravel() for c in cases]))
+    # each mesh's L2 block starts at a multiple of its p^3 (padding in between)
+    L2 = fe.fe_query(ctx)["l2_size_total"]
+    assert all(lo[k] % cases[k].p ** 3 == 0 for k in range(len(cases)))
+    assert all(lo[k] + cases[k].E * cases[k].p ** 3 <= (lo[k + 1] if k + 1 < len(cases) else L2)
+               for k in range(len(cases)))
+    eh = np.zeros(L2)
+    for k, c in enumerate(cases):
+        eh[lo[k]:lo[k] + c.E * c.p ** 3] = c.e.ravel()
+    e = dev(torch_cuda, eh)
     fe.fe_qdata_update(ctx, x, v, e)
     y = torch_cuda.empty_like(x)
     fe.fe_force_mult(ctx, e, y)
