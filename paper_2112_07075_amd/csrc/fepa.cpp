@@ -47,6 +47,7 @@ struct MeshRec {
     // first element in it; the mesh's pd then only views the class's perm/map
     int unit = -1;
     long long el_in_unit = 0;
+    int patch_in_unit = 0, n_patch_mesh = 0;  // the mesh's rows of its unit's patch table
 };
 
 struct TimerPool {
@@ -101,7 +102,7 @@ struct fe_ctx {
     double *mq = nullptr, *tabs = nullptr;
     float *mq32 = nullptr, *tabs32 = nullptr;
     double *ref_r = nullptr, *ref_d = nullptr;  // refinement vectors
-    std::vector<void *> plan_bufs;  // per-mesh patch plan arrays
+    std::vector<void *> plan_bufs;  // patch plan and CG chunk arrays
     long long *min_key = nullptr;
     int *nonfinite = nullptr;
     double *r = nullptr, *p = nullptr, *Ap = nullptr;
@@ -110,6 +111,17 @@ struct fe_ctx {
     CgState *cg = nullptr;
     int *bad = nullptr;
     long long n_parts = 0;
+    // several meshes: one CG per mesh (chunked vectors, per-mesh scalars)
+    bool multi = false;
+    CgMulti cm;
+    CgChunk *chunk = nullptr;
+    int *cbeg = nullptr, *prange = nullptr, *pmesh = nullptr;
+    CgState *cgm = nullptr;
+    CgGlobal *glob = nullptr;
+    double *part3 = nullptr, *mres = nullptr;
+    CgState *h_cgm = nullptr;
+    CgGlobal *h_glob = nullptr;
+    double *h_mres = nullptr;
     // pinned host staging
     CgState *h_cg = nullptr;
     double *h_scal = nullptr;
@@ -167,12 +179,12 @@ void free_all(fe_ctx *c)
     if (c->st) (void)hipStreamSynchronize(c->st);
     void *dptrs[] = {c->S, c->mq, c->tabs, c->mq32, c->tabs32, c->tabsb, c->ref_r, c->ref_d, c->min_key,
                      c->nonfinite, c->r, c->p, c->Ap, c->part, c->part2, c->scal, c->fr, c->cg,
-                     c->bad};
+                     c->bad, c->cgm, c->glob, c->part3, c->mres};
     for (void *d : dptrs)
         if (d) (void)hipFree(d);
     for (void *d : c->plan_bufs)
         if (d) (void)hipFree(d);
-    void *hptrs[] = {c->h_cg, c->h_scal, c->h_key, c->h_flag};
+    void *hptrs[] = {c->h_cg, c->h_scal, c->h_key, c->h_flag, c->h_cgm, c->h_glob, c->h_mres};
     for (void *h : hptrs)
         if (h) (void)hipHostFree(h);
     for (auto &tp : c->timers)
@@ -693,6 +705,8 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         if (ctx->batched) {
             // element ids of the class plan are L2 element indices of the whole vector
             const long long DL3 = (long long)r.p * r.p * r.p;
+            r.patch_in_unit = (int)cplan[r.unit].patch.size();
+            r.n_patch_mesh = (int)pl.patch.size();
             append_plan(cplan[r.unit], pl, (int32_t)(r.l2_off / DL3));
             continue;
         }
@@ -721,6 +735,58 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
     }
     if ((rc = dev_alloc(ctx, &ctx->part, std::max<long long>(ctx->n_parts, kVecBlocks), &wb)))
         return bail(rc);
+    // several meshes: chunks of at most kChunk DOFs inside one mesh and component,
+    // ordered by mesh; each mesh's range of mass partials; the mesh of each partial
+    ctx->multi = n_mesh > 1;
+    if (ctx->multi) {
+        std::vector<CgChunk> ch;
+        std::vector<int> cbeg(n_mesh + 1), prange(2 * (size_t)n_mesh), pmesh((size_t)ctx->n_parts);
+        for (int m = 0; m < n_mesh; ++m) {
+            const MeshRec &r = ctx->mesh[m];
+            cbeg[m] = (int)ch.size();
+            for (int c = 0; c < 3; ++c)
+                for (int off = 0; off < r.N; off += kChunk)
+                    ch.push_back(CgChunk{(int)(c * ctx->N_tot + r.node_off + off),
+                                         std::min(kChunk, r.N - off), m, 0});
+            const long long pb = ctx->batched ? ctx->unit[r.unit].part_off + r.patch_in_unit : r.part_off;
+            const long long pc = ctx->batched ? r.n_patch_mesh : r.pd.n_patch;
+            prange[2 * m] = (int)pb;
+            prange[2 * m + 1] = (int)(pb + pc);
+            for (long long k = pb; k < pb + pc; ++k) pmesh[k] = m;
+        }
+        cbeg[n_mesh] = (int)ch.size();
+        const long long nch = (long long)ch.size();
+        void *dp = nullptr;
+        int urc = upload(ch.data(), ch.size() * sizeof(CgChunk), &dp);
+        ctx->chunk = (CgChunk *)dp;
+        if (!urc && !(urc = upload(cbeg.data(), cbeg.size() * 4, &dp))) ctx->cbeg = (int *)dp;
+        if (!urc && !(urc = upload(prange.data(), prange.size() * 4, &dp))) ctx->prange = (int *)dp;
+        if (!urc && !(urc = upload(pmesh.data(), pmesh.size() * 4, &dp))) ctx->pmesh = (int *)dp;
+        if (urc || (rc = dev_alloc(ctx, &ctx->cgm, n_mesh, &wb)) || (rc = dev_alloc(ctx, &ctx->glob, 1, &wb)) ||
+            (rc = dev_alloc(ctx, &ctx->part3, std::max<long long>(nch, kVecBlocks), &wb)) ||
+            (rc = dev_alloc(ctx, &ctx->mres, n_mesh, &wb))) {
+            ctx->err = "CG workspace allocation failed";
+            return bail(FE_ENOMEM);
+        }
+        if (nch > kVecBlocks) {
+            (void)hipFree(ctx->part2);
+            ctx->part2 = nullptr;
+            if ((rc = dev_alloc(ctx, &ctx->part2, nch, &wb))) return bail(rc);
+        }
+        if (hipHostMalloc((void **)&ctx->h_cgm, n_mesh * sizeof(CgState)) != hipSuccess ||
+            hipHostMalloc((void **)&ctx->h_glob, sizeof(CgGlobal)) != hipSuccess ||
+            hipHostMalloc((void **)&ctx->h_mres, n_mesh * sizeof(double)) != hipSuccess) {
+            ctx->err = "pinned host allocation failed";
+            return bail(FE_ENOMEM);
+        }
+        ctx->cm.chunk = ctx->chunk;
+        ctx->cm.n_chunk = (int)nch;
+        ctx->cm.cbeg = ctx->cbeg;
+        ctx->cm.prange = ctx->prange;
+        ctx->cm.n_mesh = n_mesh;
+        ctx->cm.state = ctx->cgm;
+        ctx->cm.glob = ctx->glob;
+    }
     ctx->qdata_bytes = qb;
     ctx->work_bytes = wb;
 
@@ -849,14 +915,23 @@ int fe_force_mult_T(fe_ctx_t *ctx, const double *v, double *z)
 static void mass_enqueue(fe_ctx *ctx, const double *x, double *y, bool lo, const double *x2,
                          hipStream_t s, bool branch)
 {
-    const int *skip = x2 ? &ctx->cg->done : nullptr;
+    // one CG: its done flag; several meshes: all-done for the gathers, and each
+    // patch's own mesh state in the mass kernel
+    const int *skip = !x2 ? nullptr : (ctx->multi ? &ctx->glob->done : &ctx->cg->done);
     enqueue_units(ctx, s, branch, [&](const MeshRec &r, hipStream_t su) {
         MassCg cg;
         if (x2) {
             cg.part_dot = ctx->part + r.part_off;
-            cg.skip = skip;
             cg.x2 = x2;
-            cg.beta = &ctx->cg->beta;
+            if (ctx->multi) {
+                cg.skip = &ctx->cgm[0].done;
+                cg.beta = &ctx->cgm[0].beta;
+                cg.pmesh = ctx->pmesh + r.part_off;
+                cg.sstride = (int)sizeof(CgState);
+            } else {
+                cg.skip = skip;
+                cg.beta = &ctx->cg->beta;
+            }
         }
         if (lo)
             r.kl.mass(ctx->mq32 + r.mq_off, x, r.pd, y, ctx->N_tot, ctx->tabs32 + r.tab_slot, cg,
@@ -887,21 +962,29 @@ int fe_mass_mult(fe_ctx_t *ctx, const double *x, double *y)
 }  // extern "C"
 
 // CG on the free DOFs (mask already built, x already zero on essential DOFs)
-// with the FP64 operator, or the FP32 one when lo. On return *out holds the
-// final device state (iterations, ||b_free||^2, done flag).
+// with the FP64 operator, or the FP32 one when lo; one solve per mesh when the
+// context holds several. On return out[m] holds mesh m's final device state
+// (iterations, ||b_free||^2, done flag).
 static int cg_run(fe_ctx *ctx, const double *b, double *x, double rel_tol, int max_iter, bool lo,
-                  CgState *out)
+                  std::vector<CgState> &out)
 {
     const long long n = 3 * ctx->N_tot;
     mass_launch(ctx, x, ctx->Ap, lo);
-    cg_start(b, ctx->Ap, ctx->r, ctx->p, ctx->fr, n, ctx->part, ctx->part2, ctx->cg, rel_tol,
-             max_iter, ctx->st);
+    if (ctx->multi)
+        cgm_start(b, ctx->Ap, ctx->r, ctx->p, ctx->fr, ctx->cm, ctx->part2, ctx->part3, rel_tol,
+                  max_iter, ctx->st);
+    else
+        cg_start(b, ctx->Ap, ctx->r, ctx->p, ctx->fr, n, ctx->part, ctx->part2, ctx->cg, rel_tol,
+                 max_iter, ctx->st);
     HIP_OK(hipGetLastError());
-    // one iteration: Ap = M (r + beta p) with partials of its M-norm, then the step
-    auto iteration = [&](hipStream_t s, bool branch) {
-        mass_enqueue(ctx, ctx->r, ctx->Ap, lo, ctx->p, s, branch);
-        cg_step(x, ctx->r, ctx->p, ctx->Ap, ctx->fr, n, ctx->part, (int)ctx->n_parts, ctx->cg,
-                ctx->part2, s);
+    // one iteration: Ap = M (r + beta p) with partials of its M-norm, then the
+    // step kernels (alpha, the axpys and the new r.r, beta)
+    auto step = [&](hipStream_t s) {
+        if (ctx->multi)
+            cgm_iterate(x, ctx->r, ctx->p, ctx->Ap, ctx->fr, ctx->cm, ctx->part, ctx->part2, s);
+        else
+            cg_step(x, ctx->r, ctx->p, ctx->Ap, ctx->fr, n, ctx->part, (int)ctx->n_parts, ctx->cg,
+                    ctx->part2, s);
     };
     const bool graph = (ctx->opts.flags & FE_OPT_GRAPH) != 0;
     int batch = graph ? kGraphCgIters : 4;
@@ -911,7 +994,10 @@ static int cg_run(fe_ctx *ctx, const double *b, double *x, double rel_tol, int m
             for (int k = 0; k < batch; k += kGraphCgIters) {
                 const int rc = run_graph(ctx, GraphKey{kActCg, x, nullptr, nullptr, lo ? 1 : 0},
                                          [&](hipStream_t s, bool branch) {
-                                             for (int i = 0; i < kGraphCgIters; ++i) iteration(s, branch);
+                                             for (int i = 0; i < kGraphCgIters; ++i) {
+                                                 mass_enqueue(ctx, ctx->r, ctx->Ap, lo, ctx->p, s, branch);
+                                                 step(s);
+                                             }
                                          });
                 if (rc) return rc;
             }
@@ -921,32 +1007,64 @@ static int cg_run(fe_ctx *ctx, const double *b, double *x, double rel_tol, int m
                     ScopedTimer tm(ctx, FE_TIMER_MASS);
                     mass_enqueue(ctx, ctx->r, ctx->Ap, lo, ctx->p, ctx->st, false);
                 }
-                cg_step(x, ctx->r, ctx->p, ctx->Ap, ctx->fr, n, ctx->part, (int)ctx->n_parts,
-                        ctx->cg, ctx->part2, ctx->st);
+                step(ctx->st);
             }
         }
         HIP_OK(hipGetLastError());
-        HIP_OK(hipMemcpyAsync(ctx->h_cg, ctx->cg, sizeof(CgState), hipMemcpyDeviceToHost, ctx->st));
+        if (ctx->multi)
+            HIP_OK(hipMemcpyAsync(ctx->h_glob, ctx->glob, sizeof(CgGlobal), hipMemcpyDeviceToHost, ctx->st));
+        else
+            HIP_OK(hipMemcpyAsync(ctx->h_cg, ctx->cg, sizeof(CgState), hipMemcpyDeviceToHost, ctx->st));
         HIP_OK(hipMemcpyAsync(ctx->h_flag, ctx->bad, sizeof(int), hipMemcpyDeviceToHost, ctx->st));
         HIP_OK(hipStreamSynchronize(ctx->st));
         if (*ctx->h_flag) return fail(ctx, FE_EINVAL, "essential DOF index out of range%s");
-        if (ctx->h_cg->done) break;
+        if (ctx->multi ? ctx->h_glob->done : ctx->h_cg->done) break;
         if (batch < 32) batch *= 2;
     }
-    *out = *ctx->h_cg;
+    if (ctx->multi) {
+        const size_t nm = ctx->mesh.size();
+        HIP_OK(hipMemcpyAsync(ctx->h_cgm, ctx->cgm, nm * sizeof(CgState), hipMemcpyDeviceToHost, ctx->st));
+        HIP_OK(hipStreamSynchronize(ctx->st));
+        out.assign(ctx->h_cgm, ctx->h_cgm + nm);
+    } else {
+        out.assign(1, *ctx->h_cg);
+    }
     return FE_OK;
 }
 
-// ||b_free - (M x)_free||^2 with the FP64 operator (synchronises)
-static int true_resid2(fe_ctx *ctx, const double *b, const double *x, double *res2)
+// per mesh (one value for a single-mesh context): ||b_free - Ax_free||^2 (synchronises)
+static int resid2_of(fe_ctx *ctx, const double *b, const double *Ax, std::vector<double> &r2)
 {
     const long long n = 3 * ctx->N_tot;
-    mass_launch(ctx, x, ctx->Ap, false);
-    resid_norm2(b, ctx->Ap, ctx->fr, n, ctx->part2, ctx->scal, ctx->st);
+    if (ctx->multi) {
+        const size_t nm = ctx->mesh.size();
+        cgm_resid(b, Ax, ctx->fr, ctx->cm, ctx->part3, ctx->mres, ctx->st);
+        HIP_OK(hipMemcpyAsync(ctx->h_mres, ctx->mres, nm * sizeof(double), hipMemcpyDeviceToHost, ctx->st));
+        HIP_OK(hipStreamSynchronize(ctx->st));
+        r2.assign(ctx->h_mres, ctx->h_mres + nm);
+        return FE_OK;
+    }
+    resid_norm2(b, Ax, ctx->fr, n, ctx->part2, ctx->scal, ctx->st);
     HIP_OK(hipMemcpyAsync(ctx->h_scal, ctx->scal, sizeof(double), hipMemcpyDeviceToHost, ctx->st));
     HIP_OK(hipStreamSynchronize(ctx->st));
-    *res2 = *ctx->h_scal;
+    r2.assign(1, *ctx->h_scal);
     return FE_OK;
+}
+
+// the same with Ax = M x of the FP64 operator (leaves M x in ctx->Ap)
+static int true_resid2(fe_ctx *ctx, const double *b, const double *x, std::vector<double> &r2)
+{
+    mass_launch(ctx, x, ctx->Ap, false);
+    return resid2_of(ctx, b, ctx->Ap, r2);
+}
+
+// largest relative residual over the meshes
+static double max_rel(const std::vector<double> &r2, const std::vector<double> &bb)
+{
+    double res = 0.0;
+    for (size_t m = 0; m < r2.size(); ++m)
+        res = std::max(res, std::sqrt(r2[m] / (bb[m] > 0.0 ? bb[m] : 1.0)));
+    return res;
 }
 
 extern "C" {
@@ -966,27 +1084,26 @@ int fe_mass_cg(fe_ctx_t *ctx, const double *b, double *x, const int32_t *ess_dof
     int rc = FE_OK, total = 0;
     bool limit = false;
     double res = 0.0;
+    std::vector<CgState> st;
+    std::vector<double> r2, bb;
     if (!ctx->lo) {
-        CgState st{};
-        if ((rc = cg_run(ctx, b, x, rel_tol, max_iter, false, &st))) return rc;
-        double r2 = 0.0;
-        if ((rc = true_resid2(ctx, b, x, &r2))) return rc;
-        res = std::sqrt(r2 / (st.bb > 0.0 ? st.bb : 1.0));
-        total = st.iter;
-        limit = st.done == 2;
+        if ((rc = cg_run(ctx, b, x, rel_tol, max_iter, false, st))) return rc;
+        if ((rc = true_resid2(ctx, b, x, r2))) return rc;
+        for (const CgState &s : st) {
+            bb.push_back(s.bb);
+            total = std::max(total, s.iter);
+            limit = limit || s.done == 2;
+        }
+        res = max_rel(r2, bb);
     } else {
         // iterative refinement: FP64 residual r = b - M x, inner CG on the FP32
         // operator for M d = r to a relative 1e-5 (or rel_tol if looser), x += d
         const double inner_tol = rel_tol > 1e-5 ? rel_tol : 1e-5;
         launch_fill(ctx->ref_d, n, 0.0, ctx->st);
-        resid_norm2(b, ctx->ref_d, ctx->fr, n, ctx->part2, ctx->scal, ctx->st);
-        HIP_OK(hipMemcpyAsync(ctx->h_scal, ctx->scal, sizeof(double), hipMemcpyDeviceToHost, ctx->st));
-        HIP_OK(hipStreamSynchronize(ctx->st));
-        const double bb = *ctx->h_scal;
+        if ((rc = resid2_of(ctx, b, ctx->ref_d, bb))) return rc;
         for (int sweep = 0;; ++sweep) {
-            double r2 = 0.0;
-            if ((rc = true_resid2(ctx, b, x, &r2))) return rc;  // leaves Ap = M x
-            res = std::sqrt(r2 / (bb > 0.0 ? bb : 1.0));
+            if ((rc = true_resid2(ctx, b, x, r2))) return rc;  // leaves Ap = M x
+            res = max_rel(r2, bb);
             if (res <= rel_tol) break;
             if (total >= max_iter || sweep >= 60) {
                 limit = true;
@@ -994,10 +1111,11 @@ int fe_mass_cg(fe_ctx_t *ctx, const double *b, double *x, const int32_t *ess_dof
             }
             vec_sub_masked(b, ctx->Ap, ctx->fr, ctx->ref_r, n, ctx->st);
             launch_fill(ctx->ref_d, n, 0.0, ctx->st);
-            CgState st{};
-            if ((rc = cg_run(ctx, ctx->ref_r, ctx->ref_d, inner_tol, max_iter - total, true, &st)))
+            if ((rc = cg_run(ctx, ctx->ref_r, ctx->ref_d, inner_tol, max_iter - total, true, st)))
                 return rc;
-            total += st.iter;
+            int inner = 0;
+            for (const CgState &s : st) inner = std::max(inner, s.iter);
+            total += inner;
             vec_add(x, ctx->ref_d, n, ctx->st);
         }
     }

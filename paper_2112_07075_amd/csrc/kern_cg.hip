@@ -154,6 +154,170 @@ __global__ void k_cg_beta(const double *__restrict__ part, int nparts, CgState *
     }
 }
 
+// ---------------------------------------------------------------- several meshes
+// One workgroup per chunk: r = b - Ax (free DOFs), p = r, partials of r.r and b.b.
+__global__ void k_cgm_start(const double *__restrict__ b, const double *__restrict__ Ax,
+                            double *__restrict__ r, double *__restrict__ p,
+                            const unsigned char *__restrict__ fr, const CgChunk *__restrict__ chunk,
+                            double *__restrict__ part_rr, double *__restrict__ part_bb,
+                            CgGlobal *__restrict__ glob)
+{
+    __shared__ double sred[16];
+    const CgChunk ck = chunk[blockIdx.x];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        glob->running = 0;
+        glob->done = 0;
+    }
+    double rr = 0.0, bb = 0.0;
+    for (int k = threadIdx.x; k < ck.len; k += blockDim.x) {
+        const long long i = (long long)ck.start + k;
+        const double bi = fr[i] ? b[i] : 0.0;
+        const double ri = fr[i] ? bi - Ax[i] : 0.0;
+        r[i] = ri;
+        p[i] = ri;
+        rr += ri * ri;
+        bb += bi * bi;
+    }
+    rr = block_sum(rr, sred);
+    bb = block_sum(bb, sred);
+    if (threadIdx.x == 0) {
+        part_rr[blockIdx.x] = rr;
+        part_bb[blockIdx.x] = bb;
+    }
+}
+
+// One workgroup per mesh: its start-up sums and whether it needs any iteration.
+__global__ void k_cgm_start_final(const double *__restrict__ part_rr,
+                                  const double *__restrict__ part_bb, const int *__restrict__ cbeg,
+                                  CgState *__restrict__ state, CgGlobal *__restrict__ glob,
+                                  double rel_tol, int max_iter)
+{
+    __shared__ double sred[16];
+    const int m = blockIdx.x;
+    double rr = 0.0, bb = 0.0;
+    for (int k = cbeg[m] + threadIdx.x; k < cbeg[m + 1]; k += blockDim.x) {
+        rr += part_rr[k];
+        bb += part_bb[k];
+    }
+    rr = block_sum(rr, sred);
+    bb = block_sum(bb, sred);
+    if (threadIdx.x == 0) {
+        CgState &st = state[m];
+        st.rr = rr;
+        st.bb = bb;
+        st.stop = rel_tol * rel_tol * bb;
+        st.iter = 0;
+        st.max_iter = max_iter;
+        st.done = (rr <= st.stop) ? 1 : (max_iter <= 0 ? 2 : 0);
+        st.alpha = st.beta = st.pAp = 0.0;
+        if (!st.done) atomicAdd(&glob->running, 1);
+    }
+}
+
+// one thread: done when no mesh needs an iteration
+__global__ void k_cgm_glob(CgGlobal *__restrict__ glob)
+{
+    if (threadIdx.x == 0) glob->done = glob->running == 0;
+}
+
+// One workgroup per mesh: alpha = rr / (p'.Ap) from the mesh's mass partials.
+__global__ void k_cgm_alpha(const double *__restrict__ part, const int *__restrict__ prange,
+                            CgState *__restrict__ state, const CgGlobal *__restrict__ glob)
+{
+    __shared__ double sred[16];
+    const int m = blockIdx.x;
+    if (glob->done || state[m].done) return;
+    double s = 0.0;
+    for (int k = prange[2 * m] + threadIdx.x; k < prange[2 * m + 1]; k += blockDim.x) s += part[k];
+    s = block_sum(s, sred);
+    if (threadIdx.x == 0) {
+        state[m].pAp = s;
+        state[m].alpha = state[m].rr / s;
+    }
+}
+
+// One workgroup per chunk: p = r + beta p, x += alpha p, r -= alpha Ap with the
+// chunk's mesh scalars; partial of the new r.r.
+__global__ void k_cgm_step(double *__restrict__ x, double *__restrict__ r, double *__restrict__ p,
+                           const double *__restrict__ Ap, const unsigned char *__restrict__ fr,
+                           const CgChunk *__restrict__ chunk, const CgState *__restrict__ state,
+                           const CgGlobal *__restrict__ glob, double *__restrict__ part)
+{
+    __shared__ double sred[16];
+    if (glob->done) return;
+    const CgChunk ck = chunk[blockIdx.x];
+    const CgState &st = state[ck.mesh];
+    if (st.done) return;
+    const double alpha = st.alpha, beta = st.beta;
+    double rr = 0.0;
+    for (int k = threadIdx.x; k < ck.len; k += blockDim.x) {
+        const long long i = (long long)ck.start + k;
+        const double ri = r[i];
+        const double pi = ri + beta * p[i];
+        p[i] = pi;
+        x[i] += alpha * pi;
+        const double rn = fr[i] ? ri - alpha * Ap[i] : 0.0;
+        r[i] = rn;
+        rr += rn * rn;
+    }
+    rr = block_sum(rr, sred);
+    if (threadIdx.x == 0) part[blockIdx.x] = rr;
+}
+
+// One workgroup per mesh: new r.r, beta, iteration count, convergence; the
+// workgroup that finishes the last running mesh sets the global done flag.
+__global__ void k_cgm_beta(const double *__restrict__ part, const int *__restrict__ cbeg,
+                           CgState *__restrict__ state, CgGlobal *__restrict__ glob)
+{
+    __shared__ double sred[16];
+    const int m = blockIdx.x;
+    if (glob->done || state[m].done) return;
+    double s = 0.0;
+    for (int k = cbeg[m] + threadIdx.x; k < cbeg[m + 1]; k += blockDim.x) s += part[k];
+    s = block_sum(s, sred);
+    if (threadIdx.x == 0) {
+        CgState &st = state[m];
+        st.iter += 1;
+        st.beta = s / st.rr;
+        st.rr = s;
+        if (s <= st.stop)
+            st.done = 1;
+        else if (st.iter >= st.max_iter)
+            st.done = 2;
+        if (st.done && atomicSub(&glob->running, 1) == 1) glob->done = 1;
+    }
+}
+
+// One workgroup per chunk: partial of ||b - Ax||^2 over free DOFs.
+__global__ void k_cgm_resid(const double *__restrict__ b, const double *__restrict__ Ax,
+                            const unsigned char *__restrict__ fr, const CgChunk *__restrict__ chunk,
+                            double *__restrict__ part)
+{
+    __shared__ double sred[16];
+    const CgChunk ck = chunk[blockIdx.x];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < ck.len; k += blockDim.x) {
+        const long long i = (long long)ck.start + k;
+        if (fr[i]) {
+            const double d = b[i] - Ax[i];
+            s += d * d;
+        }
+    }
+    s = block_sum(s, sred);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void k_cgm_sum(const double *__restrict__ part, const int *__restrict__ cbeg,
+                          double *__restrict__ out)
+{
+    __shared__ double sred[16];
+    const int m = blockIdx.x;
+    double s = 0.0;
+    for (int k = cbeg[m] + threadIdx.x; k < cbeg[m + 1]; k += blockDim.x) s += part[k];
+    s = block_sum(s, sred);
+    if (threadIdx.x == 0) out[m] = s;
+}
+
 // partials of the free-DOF residual norm ||b - Ax||^2
 __global__ void k_resid_norm(const double *__restrict__ b, const double *__restrict__ Ax,
                              const unsigned char *__restrict__ fr, long long n,
@@ -246,6 +410,35 @@ void resid_norm2(const double *b, const double *Ax, const unsigned char *fr, lon
 {
     hipLaunchKernelGGL(k_resid_norm, dim3(kVecBlocks), dim3(256), 0, st, b, Ax, fr, n, part);
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(1024), 0, st, part, kVecBlocks, out);
+}
+
+void cgm_start(const double *b, const double *Ax, double *r, double *p, const unsigned char *fr,
+               const CgMulti &cm, double *part_a, double *part_b, double rel_tol, int max_iter,
+               hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cgm_start, dim3(cm.n_chunk), dim3(256), 0, st, b, Ax, r, p, fr, cm.chunk,
+                       part_a, part_b, cm.glob);
+    hipLaunchKernelGGL(k_cgm_start_final, dim3(cm.n_mesh), dim3(256), 0, st, part_a, part_b, cm.cbeg,
+                       cm.state, cm.glob, rel_tol, max_iter);
+    hipLaunchKernelGGL(k_cgm_glob, dim3(1), dim3(64), 0, st, cm.glob);
+}
+
+void cgm_iterate(double *x, double *r, double *p, const double *Ap, const unsigned char *fr,
+                 const CgMulti &cm, const double *part_pap, double *part, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cgm_alpha, dim3(cm.n_mesh), dim3(256), 0, st, part_pap, cm.prange, cm.state,
+                       cm.glob);
+    hipLaunchKernelGGL(k_cgm_step, dim3(cm.n_chunk), dim3(256), 0, st, x, r, p, Ap, fr, cm.chunk,
+                       cm.state, cm.glob, part);
+    hipLaunchKernelGGL(k_cgm_beta, dim3(cm.n_mesh), dim3(256), 0, st, part, cm.cbeg, cm.state,
+                       cm.glob);
+}
+
+void cgm_resid(const double *b, const double *Ax, const unsigned char *fr, const CgMulti &cm,
+               double *part, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cgm_resid, dim3(cm.n_chunk), dim3(256), 0, st, b, Ax, fr, cm.chunk, part);
+    hipLaunchKernelGGL(k_cgm_sum, dim3(cm.n_mesh), dim3(256), 0, st, part, cm.cbeg, out);
 }
 
 }  // namespace fepa

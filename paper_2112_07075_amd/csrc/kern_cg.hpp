@@ -14,6 +14,35 @@ struct CgState {
 
 constexpr int kVecBlocks = 1024;  // workgroups of the vector kernels (partials per pass)
 
+// Several meshes solved at once, each with its own CG scalars (state[m]): the
+// DOF vector is cut into chunks that never straddle two meshes, and the
+// mass kernel's partials of mesh m are part_dot[prange[2m] .. prange[2m+1]).
+struct CgChunk {
+    int start, len, mesh, pad;
+};
+constexpr int kChunk = 2048;  // DOFs per chunk (one workgroup of 256 threads)
+// running: meshes still iterating; done: set once running reaches zero
+struct CgGlobal {
+    int running, done;
+};
+struct CgMulti {
+    const CgChunk *chunk = nullptr;
+    int n_chunk = 0;
+    const int *cbeg = nullptr;   // [n_mesh + 1] chunk ranges per mesh
+    const int *prange = nullptr; // [n_mesh][2] mass-partial ranges per mesh
+    int n_mesh = 0;
+    CgState *state = nullptr;    // [n_mesh]
+    CgGlobal *glob = nullptr;
+};
+void cgm_start(const double *b, const double *Ax, double *r, double *p, const unsigned char *fr,
+               const CgMulti &cm, double *part_a, double *part_b, double rel_tol, int max_iter,
+               hipStream_t st);
+void cgm_iterate(double *x, double *r, double *p, const double *Ap, const unsigned char *fr,
+                 const CgMulti &cm, const double *part_pap, double *part, hipStream_t st);
+// out[m] = ||b_m - (Ax)_m||^2 over free DOFs
+void cgm_resid(const double *b, const double *Ax, const unsigned char *fr, const CgMulti &cm,
+               double *part, double *out, hipStream_t st);
+
 void cg_mask(unsigned char *fr, long long n, const int32_t *ess, int n_ess, int *bad,
              hipStream_t st);
 void cg_mask_apply(double *x, const unsigned char *fr, long long n, hipStream_t st);

@@ -321,12 +321,15 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
        double *__restrict__ y, double *__restrict__ part, long long ncomp,
        const R *__restrict__ tab, double *__restrict__ part_dot,
        const int *__restrict__ skip, const double *__restrict__ x2,
-       const double *__restrict__ beta)
+       const double *__restrict__ beta, const int *__restrict__ pmesh, int sstride)
 {
     constexpr int NE = NW * wave_ne(Q), UMAX = patch_umax(D);
     constexpr int QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D;
     using T = Tab<D, Q>;
-    if (skip && *skip) return;  // a finished CG solve
+    const int pi = xcd_block(blockIdx.x, gridDim.x);
+    // CG flags and beta: one of each, or (with pmesh) one per mesh, sstride bytes apart
+    const size_t soff = pmesh ? (size_t)pmesh[pi] * sstride : 0;
+    if (skip && *(const int *)((const char *)skip + soff)) return;  // a finished CG solve
     __shared__ R acc[UMAX];
     __shared__ R xs[UMAX];
     __shared__ int sSl[NE + 1][D3];
@@ -337,7 +340,7 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
 
     const Lane L = lane_map<Q, NE>();
     const int tid = threadIdx.x, le = L.le, t = L.t, qx = t % Q, qy = t / Q;
-    const PatchRow pr = load_patch(ptab, xcd_block(blockIdx.x, gridDim.x));
+    const PatchRow pr = load_patch(ptab, pi);
     R rBx[D], rBy[D], cBy[Q], cBx[Q];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -350,7 +353,7 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
         cBx[k] = qx < D ? tab[T::B + k * D + qx] : (R)0;
     }
     double dot = 0.0;
-    const double bt = x2 ? *beta : 0.0;
+    const double bt = x2 ? *(const double *)((const char *)beta + soff) : 0.0;
 
 #pragma unroll 1
     for (int c = 0; c < 3; ++c) {
@@ -448,7 +451,7 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
         if (tid == 0) {
             double s = 0.0;
             for (int k = 0; k < (int)((blockDim.x + 63) >> 6); ++k) s += sred[k];
-            part_dot[blockIdx.x] = s;
+            part_dot[pi] = s;  // at the patch index: partial ranges per mesh follow patches
         }
     }
 }
@@ -729,11 +732,11 @@ struct Launch {
         if (cg.part_dot)
             hipLaunchKernelGGL((k_mass<D, Q, true, R, NW>), grid, block, 0, st, (const R *)mq, x,
                                pd.map, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab,
-                               cg.part_dot, cg.skip, cg.x2, cg.beta);
+                               cg.part_dot, cg.skip, cg.x2, cg.beta, cg.pmesh, cg.sstride);
         else
             hipLaunchKernelGGL((k_mass<D, Q, false, R, NW>), grid, block, 0, st, (const R *)mq, x,
                                pd.map, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab,
-                               cg.part_dot, cg.skip, cg.x2, cg.beta);
+                               cg.part_dot, cg.skip, cg.x2, cg.beta, cg.pmesh, cg.sstride);
     }
     static void mass(const void *mq, const double *x, const PatchDev &pd, double *y,
                      long long ncomp, const void *tab, const MassCg &cg, int nw, hipStream_t st)

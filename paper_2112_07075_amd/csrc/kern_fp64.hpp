@@ -30,12 +30,16 @@ struct PatchDev {
 
 // CG extras of a mass launch: part_dot receives per-workgroup partials of
 // x . M x; with x2 the operand is x + (*beta) x2; skip points at a device flag
-// that makes the launch a no-op when set. All null for a plain action.
+// that makes the launch a no-op when set. With pmesh (the mesh of every patch)
+// each patch takes its mesh's flag and beta, sstride bytes apart per mesh.
+// All null for a plain action.
 struct MassCg {
     double *part_dot = nullptr;
     const int *skip = nullptr;
     const double *x2 = nullptr;
     const double *beta = nullptr;
+    const int *pmesh = nullptr;
+    int sstride = 0;
 };
 
 // Launchers of one (p, Q) instance; ncomp is the component stride of H1 vectors.

@@ -238,3 +238,38 @@ def test_batch_workload_full_size_batched_vs_per_mesh(torch_cuda):
             yo = O.force_mult(m.elem_nodes, p, qs[k], m.n_nodes, S)
             ya = O.force_mult(m.elem_nodes, p, qs[k], m.n_nodes, S, absmode=True)
             assert rel_cw(y1[:, noff[k]:noff[k + 1]], yo, ya) < TOL, (k, p)
+
+
+def test_each_mesh_runs_its_own_cg(torch_cuda):
+    """Meshes of very different element sizes (and so mass-matrix scales) in one
+    context: every mesh converges with its own CG scalars, in about as many
+    iterations as it needs alone, and the iteration limit is reported."""
+    t = torch_cuda
+    # two meshes of one class, each of several patches (the class's workgroups are
+    # remapped across XCDs, so a mesh's partials must follow its patches)
+    cases = [make_case(3, 2, 4, seed=61), make_case(6, 2, 4, seed=62), make_case(2, 3, 5, seed=63),
+             make_case(1, 2, 4, seed=64)]
+    rng = np.random.default_rng(9)
+    xs = [rng.standard_normal((3, c.N)) for c in cases]
+    bs = [O.mass_mult(c.mesh.elem_nodes, c.p, c.Q, c.N, oracle_qdata(c)["mq"], xk)
+          for c, xk in zip(cases, xs)]
+    alone = []
+    for c, b in zip(cases, bs):
+        g1 = Multi(t, [c.mesh], [c.Q], 0)
+        xg = t.zeros((3, c.N), dtype=t.float64, device="cuda")
+        rc, it, rr = fe.fe_mass_cg(g1.ctx, dev(t, b), xg, None, rel_tol=1e-12)
+        assert rc == fe.FE_OK
+        alone.append(it)
+    for flags in (0, B | G):
+        g = Multi(t, [c.mesh for c in cases], [c.Q for c in cases], flags)
+        xg = t.zeros((3, g.Ntot), dtype=t.float64, device="cuda")
+        rc, it, rr = fe.fe_mass_cg(g.ctx, g.h1(bs), xg, None, rel_tol=1e-12)
+        assert rc == fe.FE_OK and rr <= 1e-12
+        assert abs(it - max(alone)) <= 2, (it, alone)
+        xh = xg.cpu().numpy()
+        for k, xk in enumerate(xs):
+            assert np.linalg.norm(g.h1_slice(xh, k) - xk) < 1e-9 * np.linalg.norm(xk), k
+        xg.zero_()
+        rc, it, rr = fe.fe_mass_cg(g.ctx, g.h1(bs), xg, None, rel_tol=1e-12, max_iter=3,
+                                   check=False)
+        assert rc == fe.FE_ENOTCONV and it == 3
