@@ -81,8 +81,12 @@ extern "C" {
 
 /* ------------------------------------------------------------ option flags */
 #define FE_OPT_TIMERS   0x1  /* record HIP events around the main kernels     */
-#define FE_OPT_BATCHED  0x2  /* multi-mesh: one persistent launch per action  */
-#define FE_OPT_GRAPH    0x4  /* CG iterations replayed from a captured graph  */
+#define FE_OPT_BATCHED  0x2  /* multi-mesh: one launch per (order, Q) class of
+                                meshes per action, over their joined patches */
+#define FE_OPT_GRAPH    0x4  /* actions and groups of CG iterations replayed
+                                from hipGraphs captured at first use (per
+                                argument set); class launches run as parallel
+                                branches                                    */
 
 /* kernels timed under FE_OPT_TIMERS */
 #define FE_TIMER_QDATA   0
@@ -106,10 +110,11 @@ typedef struct fe_mesh_desc {
     double rho0;               /* initial density (> 0), uniform            */
 } fe_mesh_desc_t;
 
-/* Tile shapes of the patch kernels. 0 selects, in order, the entry of the
- * tuning table named by the environment variable FEPA_TUNE_TABLE (text lines
- * "order q1d precision nw_force nw_force_t nw_mass patch", as written by the
- * package's autotuner), else the library default. */
+/* Tile shapes of the patch kernels. 0 selects, in order of precedence, the
+ * matching line of the tuning table named by the environment variable
+ * FEPA_TUNE_TABLE (text lines "order q1d precision nw_force nw_force_t nw_mass
+ * patch", as written by the package's autotuner), the library's built-in
+ * table (measured by the same autotuner on MI355X), else the default rule. */
 typedef struct fe_opts {
     int32_t precision;         /* FE_PREC_*                                 */
     int32_t flags;             /* FE_OPT_* bit set                          */
@@ -118,7 +123,7 @@ typedef struct fe_opts {
     int32_t tune_nw_force;     /* waves per workgroup of F e (2, 4 or 8)    */
     int32_t tune_nw_force_t;   /* waves per workgroup of F^T v              */
     int32_t tune_nw_mass;      /* waves per workgroup of M x                */
-    int32_t tune_patch;        /* elements per patch (8, 64 or 512)         */
+    int32_t tune_patch;        /* elements per patch, 1..4096 (0: default)  */
 } fe_opts_t;
 
 typedef struct fe_info {
@@ -127,7 +132,9 @@ typedef struct fe_info {
     int32_t patch;                          /* its elements per patch (cap)  */
     int64_t n_elem_total;      /* E_tot                                     */
     int64_t n_nodes_total;     /* N_tot (scalar); H1 vectors hold 3*N_tot    */
-    int64_t l2_size_total;     /* sum over meshes of E*p^3                  */
+    int64_t l2_size_total;     /* L2 vector length: sum over meshes of E*p^3,
+                                  each mesh's block starting at a multiple
+                                  of its p^3 (see fe_mesh_offsets)          */
     int64_t qdata_bytes;       /* device bytes of S and m_q                 */
     int64_t workspace_bytes;   /* all other context-owned device bytes      */
     int32_t precision;
@@ -202,6 +209,9 @@ int fe_mass_mult(fe_ctx_t *ctx, const double *x, double *y);
  * ||b_free - (M x)_free|| / ||b_free|| in *rel_res and the iteration count in
  * *iters (either pointer may be NULL). Under FE_PREC_FP32/BF16 the solve is
  * iterative refinement: FP64 outer residuals with an inner low-precision CG.
+ * A context of several meshes solves every mesh's (independent) system with
+ * its own CG scalars and stopping test; *iters is then the largest iteration
+ * count and *rel_res the largest relative residual over the meshes.
  * Synchronises the stream. Returns FE_ENOTCONV when max_iter iterations did
  * not reach rel_tol (x then holds the last iterate).
  */

@@ -28,7 +28,7 @@ WAVES = (2, 4, 8)
 
 
 def patch_choices(p: int):
-    return {1: (8, 64, 512), 2: (8, 64)}.get(p, (8,))
+    return {1: (16, 32, 64, 128, 256, 512), 2: (8, 16, 24, 32, 48, 64)}.get(p, (4, 6, 8))
 
 
 def time_actions(fe, torch, mesh, p, Q, precision, nw, patch, reps=20):

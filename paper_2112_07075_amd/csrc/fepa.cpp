@@ -409,8 +409,8 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
     for (int v : {o.tune_nw_force, o.tune_nw_force_t, o.tune_nw_mass})
         if (v != 0 && v != 2 && v != 4 && v != 8)
             return fail(nullptr, FE_EINVAL, "waves per workgroup must be 2, 4 or 8%s");
-    if (o.tune_patch != 0 && o.tune_patch != 8 && o.tune_patch != 64 && o.tune_patch != 512)
-        return fail(nullptr, FE_EINVAL, "patch size must be 8, 64 or 512%s");
+    if (o.tune_patch < 0 || o.tune_patch > 4096)
+        return fail(nullptr, FE_EINVAL, "elements per patch must be in [1, 4096] (0: default)%s");
     // host-side validation of every mesh before any device work
     for (int m = 0; m < n_mesh; ++m) {
         const fe_mesh_desc_t &d = meshes[m];

@@ -119,7 +119,9 @@ __host__ __device__ constexpr int fit_waves(int Q, int per_elem, int fixed)
 constexpr int kLdsMax = 160 * 1024;
 __host__ __device__ constexpr int force_lds(int D, int Q, int rs, int NW)
 {
-    return 3 * rs * patch_umax(D) + (NW * wave_ne(Q) + 1) * rs * (3 * D * Q * Q + 2 * D * D * Q);
+    // at Q = 4 the y and x stages run across lanes: only the accumulator
+    return Q == 4 ? 3 * rs * patch_umax(D)
+                  : 3 * rs * patch_umax(D) + (NW * wave_ne(Q) + 1) * rs * (3 * D * Q * Q + 2 * D * D * Q);
 }
 __host__ __device__ constexpr int force_t_lds(int D, int Q, int rs, int NW)
 {

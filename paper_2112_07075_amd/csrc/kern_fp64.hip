@@ -65,19 +65,27 @@ k_force(const R *__restrict__ S, const double *__restrict__ e,
     }
     __syncthreads();
 
+    // S columns (9*Q streaming loads per thread) are pipelined by component: as
+    // soon as a pass has contracted component c in z, the registers of c are
+    // refilled with the next pass's values, which then load while this pass
+    // works through its LDS stages.
+    R sv[9][Q];
+    {
+        const bool act0 = L.valid && le < pr.cnt;
+        const R *__restrict__ S0 = S + (long long)(pr.eb + (act0 ? le : 0)) * 9 * Q3 + t;
+#pragma unroll
+        for (int cd = 0; cd < 9; ++cd)
+#pragma unroll
+            for (int qz = 0; qz < Q; ++qz)
+                sv[cd][qz] = act0 ? __builtin_nontemporal_load(S0 + cd * Q3 + qz * QQ) : (R)0;
+    }
 #pragma unroll 1
     for (int base = 0; base < pr.cnt; base += NE) {
         const int idx = base + le;
         const bool act = L.valid && idx < pr.cnt;
         const long long el = pr.eb + (act ? idx : 0);
-        // the element's whole S column first: 9*Q independent streaming loads in flight
-        const R *__restrict__ Se = S + el * 9 * Q3 + t;
-        R sv[9][Q];
-#pragma unroll
-        for (int cd = 0; cd < 9; ++cd)
-#pragma unroll
-            for (int qz = 0; qz < Q; ++qz)
-                sv[cd][qz] = act ? __builtin_nontemporal_load(Se + cd * Q3 + qz * QQ) : (R)0;
+        const bool actn = L.valid && idx + NE < pr.cnt;
+        const R *__restrict__ Sn = S + (long long)(pr.eb + (actn ? idx + NE : 0)) * 9 * Q3 + t;
         int sl[D];
 #pragma unroll
         for (int iz = 0; iz < D; ++iz)
@@ -129,6 +137,12 @@ k_force(const R *__restrict__ S, const double *__restrict__ e,
                 }
             }
 #pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int qz = 0; qz < Q; ++qz)
+                    sv[c * 3 + d][qz] =
+                        actn ? __builtin_nontemporal_load(Sn + (c * 3 + d) * Q3 + qz * QQ) : (R)0;
+#pragma unroll
             for (int iz = 0; iz < D; ++iz) {
                 sA[le][0][iz][t] = a0[iz];
                 sA[le][1][iz][t] = a1[iz];
@@ -158,6 +172,180 @@ k_force(const R *__restrict__ S, const double *__restrict__ e,
                         r += cGx[k] * sC[le][0][iz][qy * Q + k] + cBx[k] * sC[le][1][iz][qy * Q + k];
                     atomicAdd(&acc[3 * sl[iz] + c], r);
                 }
+            }
+        }
+    }
+    __syncthreads();
+    patch_write<UMAX>(acc, pr, pn, y, part, ncomp);
+}
+
+// ------------------------------------------------- force F e, F 1 at Q = 4
+// The same action for four points per direction with the y and x contractions
+// done across lanes instead of through LDS. An element's 16 point columns are
+// one 16-lane DPP row, laid out qy-fastest: each quad holds the four qy of one
+// qx, so a quad broadcast (quad_perm) hands every lane the four values it
+// contracts in y, and rotations of the row by 4, 8 and 12 lanes hand it the
+// four values it contracts in x. LDS then only holds the patch accumulator.
+
+// value of the lane selected by a DPP control (row-local), for 32/64-bit types
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_r(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i<CTRL>((int)(b & 0xffffffffLL)), hi = dpp_i<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_r(float v)
+{
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+constexpr int kQuadBcast0 = 0x00, kQuadBcast1 = 0x55, kQuadBcast2 = 0xAA, kQuadBcast3 = 0xFF;
+constexpr int kRowRor4 = 0x124, kRowRor8 = 0x128, kRowRor12 = 0x12C;
+
+template <int D, bool ONE, typename R, int NW>
+__global__ void __launch_bounds__(NW * 64)
+k_force_q4(const R *__restrict__ S, const double *__restrict__ e,
+           const int32_t *__restrict__ perm, const uint16_t *__restrict__ slot,
+           const int32_t *__restrict__ pn, const int32_t *__restrict__ ptab,
+           double *__restrict__ y, double *__restrict__ part, long long ncomp,
+           const R *__restrict__ tab)
+{
+    constexpr int Q = 4, NE = NW * 4, UMAX = patch_umax(D);
+    constexpr int DL = D - 1, QQ = 16, Q3 = 64, D3 = D * D * D, DL3 = DL * DL * DL;
+    using T = Tab<D, Q>;
+    __shared__ R acc[3 * UMAX];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int le = (tid >> 6) * 4 + (lane >> 4);  // element slot of the lane's row
+    const int r = lane & 15, qy = r & 3, qx = r >> 2, t = qx + Q * qy;
+
+    // y: the quad broadcast of lane k brings point row k of column qx
+    R cBy[Q], cGy[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        cBy[k] = qy < D ? tab[T::B + k * D + qy] : (R)0;
+        cGy[k] = qy < D ? tab[T::G + k * D + qy] : (R)0;
+    }
+    // x: the row rotation by 4j brings the column of the source lane
+    int kx[Q];
+    kx[0] = qx;
+    kx[1] = dpp_i<kRowRor4>(qx);
+    kx[2] = dpp_i<kRowRor8>(qx);
+    kx[3] = dpp_i<kRowRor12>(qx);
+    R cBx[Q], cGx[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        cBx[j] = qx < D ? tab[T::B + kx[j] * D + qx] : (R)0;
+        cGx[j] = qx < D ? tab[T::G + kx[j] * D + qx] : (R)0;
+    }
+
+    const PatchRow pr = load_patch(ptab, xcd_block(blockIdx.x, gridDim.x));
+    for (int k = tid; k < 3 * pr.U; k += blockDim.x) acc[k] = 0.0;
+    __syncthreads();
+
+    // S pipelined by component as in the general kernel
+    R sv[9][Q];
+    {
+        const bool act0 = le < pr.cnt;
+        const R *__restrict__ S0 = S + (long long)(pr.eb + (act0 ? le : 0)) * 9 * Q3 + t;
+#pragma unroll
+        for (int cd = 0; cd < 9; ++cd)
+#pragma unroll
+            for (int qz = 0; qz < Q; ++qz)
+                sv[cd][qz] = act0 ? __builtin_nontemporal_load(S0 + cd * Q3 + qz * QQ) : (R)0;
+    }
+#pragma unroll 1
+    for (int base = 0; base < pr.cnt; base += NE) {
+        const int idx = base + le;
+        const bool act = idx < pr.cnt;
+        const long long el = pr.eb + (act ? idx : 0);
+        const bool actn = idx + NE < pr.cnt;
+        const R *__restrict__ Sn = S + (long long)(pr.eb + (actn ? idx + NE : 0)) * 9 * Q3 + t;
+        int sl[D];
+#pragma unroll
+        for (int iz = 0; iz < D; ++iz)
+            sl[iz] = (act && qx < D && qy < D) ? slot[el * D3 + iz * D * D + qy * D + qx] : 0;
+        R eq[Q];
+        if (ONE) {
+#pragma unroll
+            for (int k = 0; k < Q; ++k) eq[k] = 1.0;
+        } else {
+            const double *__restrict__ ee = e + (long long)perm[el] * DL3;
+            R tz[DL];
+#pragma unroll
+            for (int jz = 0; jz < DL; ++jz) {
+                R s = 0.0;
+#pragma unroll
+                for (int jy = 0; jy < DL; ++jy) {
+                    R u = 0.0;
+#pragma unroll
+                    for (int jx = 0; jx < DL; ++jx)
+                        u += tab[T::BL + qx * DL + jx] * (R)(act ? ee[(jz * DL + jy) * DL + jx] : 0.0);
+                    s += tab[T::BL + qy * DL + jy] * u;
+                }
+                tz[jz] = s;
+            }
+#pragma unroll
+            for (int qz = 0; qz < Q; ++qz) {
+                R s = 0.0;
+#pragma unroll
+                for (int jz = 0; jz < DL; ++jz) s += tab[T::BL + qz * DL + jz] * tz[jz];
+                eq[qz] = s;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            // z in registers
+            R a0[D], a1[D], a2[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) a0[i] = a1[i] = a2[i] = 0.0;
+#pragma unroll
+            for (int qz = 0; qz < Q; ++qz) {
+                const R s0 = sv[c * 3 + 0][qz] * eq[qz];
+                const R s1 = sv[c * 3 + 1][qz] * eq[qz];
+                const R s2 = sv[c * 3 + 2][qz] * eq[qz];
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) {
+                    const R b = tab[T::B + qz * D + iz], g = tab[T::G + qz * D + iz];
+                    a0[iz] += b * s0;
+                    a1[iz] += b * s1;
+                    a2[iz] += g * s2;
+                }
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int qz = 0; qz < Q; ++qz)
+                    sv[c * 3 + d][qz] =
+                        actn ? __builtin_nontemporal_load(Sn + (c * 3 + d) * Q3 + qz * QQ) : (R)0;
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) {
+                // y: thread (qx, iy = qy)
+                const R u0[Q] = {dpp_r<kQuadBcast0>(a0[iz]), dpp_r<kQuadBcast1>(a0[iz]),
+                                 dpp_r<kQuadBcast2>(a0[iz]), dpp_r<kQuadBcast3>(a0[iz])};
+                const R u1[Q] = {dpp_r<kQuadBcast0>(a1[iz]), dpp_r<kQuadBcast1>(a1[iz]),
+                                 dpp_r<kQuadBcast2>(a1[iz]), dpp_r<kQuadBcast3>(a1[iz])};
+                const R u2[Q] = {dpp_r<kQuadBcast0>(a2[iz]), dpp_r<kQuadBcast1>(a2[iz]),
+                                 dpp_r<kQuadBcast2>(a2[iz]), dpp_r<kQuadBcast3>(a2[iz])};
+                R c0 = 0.0, c1 = 0.0;
+#pragma unroll
+                for (int k = 0; k < Q; ++k) {
+                    c0 += cBy[k] * u0[k];
+                    c1 += cGy[k] * u1[k] + cBy[k] * u2[k];
+                }
+                // x: thread (ix = qx, iy = qy)
+                const R w0[Q] = {c0, dpp_r<kRowRor4>(c0), dpp_r<kRowRor8>(c0), dpp_r<kRowRor12>(c0)};
+                const R w1[Q] = {c1, dpp_r<kRowRor4>(c1), dpp_r<kRowRor8>(c1), dpp_r<kRowRor12>(c1)};
+                R rr = 0.0;
+#pragma unroll
+                for (int j = 0; j < Q; ++j) rr += cGx[j] * w0[j] + cBx[j] * w1[j];
+                if (act && qx < D && qy < D) atomicAdd(&acc[3 * sl[iz] + c], rr);
             }
         }
     }
@@ -692,12 +880,21 @@ struct Launch {
                          long long ncomp, const void *tab, hipStream_t st)
     {
         const dim3 grid(pd.n_patch), block(NW * 64);
-        if (e)
-            hipLaunchKernelGGL((k_force<D, Q, false, R, NW>), grid, block, 0, st, (const R *)S, e,
-                               pd.perm, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab);
-        else
-            hipLaunchKernelGGL((k_force<D, Q, true, R, NW>), grid, block, 0, st, (const R *)S, e,
-                               pd.perm, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab);
+        if constexpr (Q == 4) {
+            if (e)
+                hipLaunchKernelGGL((k_force_q4<D, false, R, NW>), grid, block, 0, st, (const R *)S, e,
+                                   pd.perm, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab);
+            else
+                hipLaunchKernelGGL((k_force_q4<D, true, R, NW>), grid, block, 0, st, (const R *)S, e,
+                                   pd.perm, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab);
+        } else {
+            if (e)
+                hipLaunchKernelGGL((k_force<D, Q, false, R, NW>), grid, block, 0, st, (const R *)S, e,
+                                   pd.perm, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab);
+            else
+                hipLaunchKernelGGL((k_force<D, Q, true, R, NW>), grid, block, 0, st, (const R *)S, e,
+                                   pd.perm, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab);
+        }
     }
     static void force(const void *S, const double *e, const PatchDev &pd, double *y,
                       long long ncomp, const void *tab, int nw, hipStream_t st)
@@ -760,8 +957,14 @@ struct Launch {
     {
         constexpr int rs = sizeof(R);
         if (kind == 0)
-            return force_lds(D, Q, rs, NW) <= kLdsMax && no_spill(k_force<D, Q, true, R, NW>) &&
-                   no_spill(k_force<D, Q, false, R, NW>);
+        {
+            if constexpr (Q == 4)
+                return force_lds(D, Q, rs, NW) <= kLdsMax && no_spill(k_force_q4<D, true, R, NW>) &&
+                       no_spill(k_force_q4<D, false, R, NW>);
+            else
+                return force_lds(D, Q, rs, NW) <= kLdsMax && no_spill(k_force<D, Q, true, R, NW>) &&
+                       no_spill(k_force<D, Q, false, R, NW>);
+        }
         if (kind == 1)
             return force_t_lds(D, Q, rs, NW) <= kLdsMax && no_spill(k_force_t<D, Q, R, R, NW>);
         return mass_lds(D, Q, rs, NW) <= kLdsMax && no_spill(k_mass<D, Q, true, R, NW>) &&

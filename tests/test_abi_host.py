@@ -83,7 +83,7 @@ def test_setup_rejects_invalid_arguments_without_device(case, expect):
     elif case == "bad_waves":
         opts = fe._Opts(0, 0, 5.0 / 3.0, 0.5, 2.0, 3, 0, 0, 0)
     elif case == "bad_patch":
-        opts = fe._Opts(0, 0, 5.0 / 3.0, 0.5, 2.0, 0, 0, 0, 100)
+        opts = fe._Opts(0, 0, 5.0 / 3.0, 0.5, 2.0, 0, 0, 0, 5000)
     rc, h = _setup([d], n, opts)
     assert rc == expect
     assert not h.value
