@@ -93,7 +93,8 @@ extern "C" {
 #define FE_TIMER_FORCE   1
 #define FE_TIMER_FORCE_T 2
 #define FE_TIMER_MASS    3
-#define FE_TIMER_COUNT   4
+#define FE_TIMER_PAIR    4  /* fe_force_mult_pair                          */
+#define FE_TIMER_COUNT   5
 
 typedef struct fe_ctx fe_ctx_t;
 
@@ -195,6 +196,17 @@ int fe_force_mult(fe_ctx_t *ctx, const double *e, double *y);
  * Element-local output, no scatter. Asynchronous.
  */
 int fe_force_mult_T(fe_ctx_t *ctx, const double *v, double *z);
+
+/*
+ * Both force actions from one pass over the quadrature data: y = F e (e NULL:
+ * y = F 1), as fe_force_mult, and z = F^T v, as fe_force_mult_T. The two share
+ * S = w detJ sigma J^-T and the Lagrange step needs both at every stage (the
+ * momentum and energy equations of Sec. 3.3), so the library reads S once.
+ * Same layouts and ownership as the two single calls; y, z must not overlap
+ * each other or the inputs (FE_EINVAL). Under FE_PREC_BF16 the two single
+ * actions run one after the other. Asynchronous.
+ */
+int fe_force_mult_pair(fe_ctx_t *ctx, const double *e, double *y, const double *v, double *z);
 
 /* Mass action y = M_v x ([3][N_tot] device in and out; y overwritten). Asynchronous. */
 int fe_mass_mult(fe_ctx_t *ctx, const double *x, double *y);

@@ -22,10 +22,10 @@ FE_OK, FE_EINVAL, FE_ENOMEM, FE_EDEVICE, FE_EUNSUPPORTED, FE_EBADMESH, FE_ENOTCO
     0, -1, -2, -3, -4, -5, -6
 FE_PREC_FP64, FE_PREC_FP32, FE_PREC_BF16 = 0, 1, 2
 FE_OPT_TIMERS, FE_OPT_BATCHED, FE_OPT_GRAPH = 0x1, 0x2, 0x4
-FE_TIMER_QDATA, FE_TIMER_FORCE, FE_TIMER_FORCE_T, FE_TIMER_MASS = 0, 1, 2, 3
+FE_TIMER_QDATA, FE_TIMER_FORCE, FE_TIMER_FORCE_T, FE_TIMER_MASS, FE_TIMER_PAIR = 0, 1, 2, 3, 4
 
 ABI_FUNCTIONS = ("fe_pa_setup", "fe_destroy", "fe_query", "fe_mesh_offsets", "fe_qdata_update",
-                 "fe_force_mult", "fe_force_mult_T", "fe_mass_mult", "fe_mass_cg",
+                 "fe_force_mult", "fe_force_mult_T", "fe_force_mult_pair", "fe_mass_mult", "fe_mass_cg",
                  "fe_get_diag", "fe_export_qdata", "fe_timer_read", "fe_timer_reset",
                  "fe_status_str", "fe_last_error")
 
@@ -83,6 +83,7 @@ def lib() -> C.CDLL:
     L.fe_qdata_update.argtypes = [vp, vp, vp, vp]
     L.fe_force_mult.argtypes = [vp, vp, vp]
     L.fe_force_mult_T.argtypes = [vp, vp, vp]
+    L.fe_force_mult_pair.argtypes = [vp, vp, vp, vp, vp]
     L.fe_mass_mult.argtypes = [vp, vp, vp]
     L.fe_mass_cg.argtypes = [vp, vp, vp, vp, i32, dbl, i32, C.POINTER(i32), C.POINTER(dbl)]
     L.fe_get_diag.argtypes = [vp, C.POINTER(_Diag)]
@@ -215,6 +216,10 @@ def fe_force_mult(ctx: Ctx, e, y) -> None:
 
 def fe_force_mult_T(ctx: Ctx, v, z) -> None:
     _check(lib().fe_force_mult_T(ctx.handle, _ptr(v), _ptr(z)), ctx.handle)
+
+
+def fe_force_mult_pair(ctx: Ctx, e, y, v, z) -> None:
+    _check(lib().fe_force_mult_pair(ctx.handle, _ptr(e), _ptr(y), _ptr(v), _ptr(z)), ctx.handle)
 
 
 def fe_mass_mult(ctx: Ctx, x, y) -> None:

@@ -37,6 +37,7 @@ struct MeshRec {
     KernelSet kl{};                  // kernels of the context's precision
     long long Sb_off = 0;            // offset of the mesh's S in the stored type
     int nw_force = 4, nw_force_t = 4, nw_mass = 4;  // waves per workgroup
+    int nw_pair = 4;                                 // of the fused F e + F^T v kernel
     int patch = 0;                                   // elements per patch (0: default)
     long long tabb_off = 0;          // BF16 form: byte offset of its operand buffer
     double rho0 = 1.0;
@@ -65,9 +66,10 @@ struct GraphKey {
     int action = 0;
     const void *a = nullptr, *b = nullptr, *c = nullptr;
     int extra = 0;
+    const void *d = nullptr;
     bool operator==(const GraphKey &o) const
     {
-        return action == o.action && a == o.a && b == o.b && c == o.c && extra == o.extra;
+        return action == o.action && a == o.a && b == o.b && c == o.c && extra == o.extra && d == o.d;
     }
 };
 struct GraphRec {
@@ -77,7 +79,7 @@ struct GraphRec {
 constexpr int kAuxStreams = 3;     // side streams of the unit branches in a graph
 constexpr size_t kMaxGraphs = 32;  // cached graphs per context (oldest dropped)
 constexpr int kGraphCgIters = 8;   // CG iterations per captured graph
-enum { kActQdata = 1, kActForce, kActForceT, kActMass, kActCg };
+enum { kActQdata = 1, kActForce, kActForceT, kActMass, kActCg, kActPair };
 
 }  // namespace
 
@@ -484,6 +486,7 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
             r.nw_force = std::min(r.nw_force, kc.max_nw(0));
             r.nw_force_t = std::min(r.nw_force_t, kc.max_nw(1));
             r.nw_mass = std::min(r.nw_mass, kc.max_nw(2));
+            r.nw_pair = std::min(r.nw_force, kc.max_nw(3));
         }
         if (ctx->bf) {
             r.kl.force = bf16_force(r.p, r.Q);
@@ -904,6 +907,30 @@ int fe_force_mult_T(fe_ctx_t *ctx, const double *v, double *z)
         enqueue_units(ctx, s, branch, [&](const MeshRec &r, hipStream_t su) {
             r.kl.force_t(S_of(ctx, r), v, r.pd, r.E, z + r.l2_off, ctx->N_tot, tab_of(ctx, r),
                          r.nw_force_t, su);
+        });
+    });
+}
+
+int fe_force_mult_pair(fe_ctx_t *ctx, const double *e, double *y, const double *v, double *z)
+{
+    if (!ctx) return FE_EINVAL;
+    if (!y || !v || !z) return fail(ctx, FE_EINVAL, "NULL argument%s");
+    const void *in[] = {e, v}, *out[] = {y, z};
+    if (out[0] == out[1]) return fail(ctx, FE_EINVAL, "outputs alias%s");
+    for (const void *i : in)
+        for (const void *o : out)
+            if (i && i == o) return fail(ctx, FE_EINVAL, "input aliases output%s");
+    if (ctx->bf) {  // the BF16 form has no fused kernel: its two actions
+        int rc = fe_force_mult(ctx, e, y);
+        return rc ? rc : fe_force_mult_T(ctx, v, z);
+    }
+    ScopedTimer tm(ctx, FE_TIMER_PAIR);
+    return run_graph(ctx, GraphKey{kActPair, e, y, v, 0, z}, [&](hipStream_t s, bool branch) {
+        enqueue_units(ctx, s, branch, [&](const MeshRec &r, hipStream_t su) {
+            r.kl.force_pair(S_of(ctx, r), e ? e + r.l2_off : nullptr, v, r.pd, y, z + r.l2_off,
+                            ctx->N_tot, tab_of(ctx, r), r.nw_pair, su);
+            launch_gather_shared(r.pd, y, ctx->N_tot, nullptr, su);
+            launch_zero_nodes(r.orphans, r.n_orphans, y, ctx->N_tot, nullptr, su);
         });
     });
 }

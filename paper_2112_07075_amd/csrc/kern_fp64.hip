@@ -65,19 +65,17 @@ k_force(const R *__restrict__ S, const double *__restrict__ e,
     }
     __syncthreads();
 
-    // S columns (9*Q streaming loads per thread) are pipelined by component: as
-    // soon as a pass has contracted component c in z, the registers of c are
-    // refilled with the next pass's values, which then load while this pass
-    // works through its LDS stages.
-    R sv[9][Q];
+    // S by component: sv holds component c of this pass while sn loads the next
+    // component (or component 0 of the next pass); loads never branch (lanes
+    // without an element read a valid one and store nothing)
+    R sv[3][Q], sn[3][Q];
     {
         const bool act0 = L.valid && le < pr.cnt;
         const R *__restrict__ S0 = S + (long long)(pr.eb + (act0 ? le : 0)) * 9 * Q3 + t;
 #pragma unroll
-        for (int cd = 0; cd < 9; ++cd)
+        for (int d = 0; d < 3; ++d)
 #pragma unroll
-            for (int qz = 0; qz < Q; ++qz)
-                sv[cd][qz] = act0 ? __builtin_nontemporal_load(S0 + cd * Q3 + qz * QQ) : (R)0;
+            for (int qz = 0; qz < Q; ++qz) sv[d][qz] = __builtin_nontemporal_load(S0 + d * Q3 + qz * QQ);
     }
 #pragma unroll 1
     for (int base = 0; base < pr.cnt; base += NE) {
@@ -85,11 +83,12 @@ k_force(const R *__restrict__ S, const double *__restrict__ e,
         const bool act = L.valid && idx < pr.cnt;
         const long long el = pr.eb + (act ? idx : 0);
         const bool actn = L.valid && idx + NE < pr.cnt;
+        const R *__restrict__ Sc = S + el * 9 * Q3 + t;
         const R *__restrict__ Sn = S + (long long)(pr.eb + (actn ? idx + NE : 0)) * 9 * Q3 + t;
         int sl[D];
+        const int qxc = qx < D ? qx : D - 1, qyc = qy < D ? qy : D - 1;
 #pragma unroll
-        for (int iz = 0; iz < D; ++iz)
-            sl[iz] = (act && qx < D && qy < D) ? slot[el * D3 + iz * D * D + qy * D + qx] : 0;
+        for (int iz = 0; iz < D; ++iz) sl[iz] = slot[el * D3 + iz * D * D + qyc * D + qxc];
         R eq[Q];
         if (ONE) {
 #pragma unroll
@@ -105,7 +104,7 @@ k_force(const R *__restrict__ S, const double *__restrict__ e,
                     R u = 0.0;
 #pragma unroll
                     for (int jx = 0; jx < DL; ++jx)
-                        u += tab[T::BL + qx * DL + jx] * (R)(act ? ee[(jz * DL + jy) * DL + jx] : 0.0);
+                        u += tab[T::BL + qx * DL + jx] * (R)ee[(jz * DL + jy) * DL + jx];
                     s += tab[T::BL + qy * DL + jy] * u;
                 }
                 tz[jz] = s;
@@ -120,14 +119,19 @@ k_force(const R *__restrict__ S, const double *__restrict__ e,
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int qz = 0; qz < Q; ++qz)
+                    sn[d][qz] = __builtin_nontemporal_load((c < 2 ? Sc + (c + 1) * 3 * Q3 : Sn) + d * Q3 + qz * QQ);
             R a0[D], a1[D], a2[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) a0[i] = a1[i] = a2[i] = 0.0;
 #pragma unroll
             for (int qz = 0; qz < Q; ++qz) {
-                const R s0 = sv[c * 3 + 0][qz] * eq[qz];
-                const R s1 = sv[c * 3 + 1][qz] * eq[qz];
-                const R s2 = sv[c * 3 + 2][qz] * eq[qz];
+                const R s0 = sv[0][qz] * eq[qz];
+                const R s1 = sv[1][qz] * eq[qz];
+                const R s2 = sv[2][qz] * eq[qz];
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
                     const R b = tab[T::B + qz * D + iz], g = tab[T::G + qz * D + iz];
@@ -136,12 +140,6 @@ k_force(const R *__restrict__ S, const double *__restrict__ e,
                     a2[iz] += g * s2;
                 }
             }
-#pragma unroll
-            for (int d = 0; d < 3; ++d)
-#pragma unroll
-                for (int qz = 0; qz < Q; ++qz)
-                    sv[c * 3 + d][qz] =
-                        actn ? __builtin_nontemporal_load(Sn + (c * 3 + d) * Q3 + qz * QQ) : (R)0;
 #pragma unroll
             for (int iz = 0; iz < D; ++iz) {
                 sA[le][0][iz][t] = a0[iz];
@@ -173,6 +171,11 @@ k_force(const R *__restrict__ S, const double *__restrict__ e,
                     atomicAdd(&acc[3 * sl[iz] + c], r);
                 }
             }
+            wave_sync();  // sA and sC are rewritten by the next component
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int qz = 0; qz < Q; ++qz) sv[d][qz] = sn[d][qz];
         }
     }
     __syncthreads();
@@ -186,12 +189,16 @@ k_force(const R *__restrict__ S, const double *__restrict__ e,
 // qx, so a quad broadcast (quad_perm) hands every lane the four values it
 // contracts in y, and rotations of the row by 4, 8 and 12 lanes hand it the
 // four values it contracts in x. LDS then only holds the patch accumulator.
+// S streams one component (3Q values per thread) at a time: the next
+// component's loads are issued before the current one is contracted.
 
-// value of the lane selected by a DPP control (row-local), for 32/64-bit types
+// value of the lane selected by a DPP control (row-local), for 32/64-bit types;
+// every control used here reads a lane of the same row, so no lane keeps an
+// old value and no initialisation of the destination is needed
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_r(double v)
@@ -249,16 +256,16 @@ k_force_q4(const R *__restrict__ S, const double *__restrict__ e,
     for (int k = tid; k < 3 * pr.U; k += blockDim.x) acc[k] = 0.0;
     __syncthreads();
 
-    // S pipelined by component as in the general kernel
-    R sv[9][Q];
+    // S by component: sv holds component c of this pass while sn loads the next
+    // component (or component 0 of the next pass)
+    R sv[3][Q], sn[3][Q];
     {
         const bool act0 = le < pr.cnt;
         const R *__restrict__ S0 = S + (long long)(pr.eb + (act0 ? le : 0)) * 9 * Q3 + t;
 #pragma unroll
-        for (int cd = 0; cd < 9; ++cd)
+        for (int d = 0; d < 3; ++d)
 #pragma unroll
-            for (int qz = 0; qz < Q; ++qz)
-                sv[cd][qz] = act0 ? __builtin_nontemporal_load(S0 + cd * Q3 + qz * QQ) : (R)0;
+            for (int qz = 0; qz < Q; ++qz) sv[d][qz] = __builtin_nontemporal_load(S0 + d * Q3 + qz * QQ);
     }
 #pragma unroll 1
     for (int base = 0; base < pr.cnt; base += NE) {
@@ -266,11 +273,14 @@ k_force_q4(const R *__restrict__ S, const double *__restrict__ e,
         const bool act = idx < pr.cnt;
         const long long el = pr.eb + (act ? idx : 0);
         const bool actn = idx + NE < pr.cnt;
+        const R *__restrict__ Sc = S + el * 9 * Q3 + t;
         const R *__restrict__ Sn = S + (long long)(pr.eb + (actn ? idx + NE : 0)) * 9 * Q3 + t;
+        // lanes past the element count or outside the D x D node columns load a
+        // valid neighbour's data and never store (loads without branches)
         int sl[D];
+        const int qxc = qx < D ? qx : D - 1, qyc = qy < D ? qy : D - 1;
 #pragma unroll
-        for (int iz = 0; iz < D; ++iz)
-            sl[iz] = (act && qx < D && qy < D) ? slot[el * D3 + iz * D * D + qy * D + qx] : 0;
+        for (int iz = 0; iz < D; ++iz) sl[iz] = slot[el * D3 + iz * D * D + qyc * D + qxc];
         R eq[Q];
         if (ONE) {
 #pragma unroll
@@ -286,7 +296,7 @@ k_force_q4(const R *__restrict__ S, const double *__restrict__ e,
                     R u = 0.0;
 #pragma unroll
                     for (int jx = 0; jx < DL; ++jx)
-                        u += tab[T::BL + qx * DL + jx] * (R)(act ? ee[(jz * DL + jy) * DL + jx] : 0.0);
+                        u += tab[T::BL + qx * DL + jx] * (R)ee[(jz * DL + jy) * DL + jx];
                     s += tab[T::BL + qy * DL + jy] * u;
                 }
                 tz[jz] = s;
@@ -299,17 +309,22 @@ k_force_q4(const R *__restrict__ S, const double *__restrict__ e,
                 eq[qz] = s;
             }
         }
-#pragma unroll
+#pragma unroll 1
         for (int c = 0; c < 3; ++c) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int qz = 0; qz < Q; ++qz)
+                    sn[d][qz] = __builtin_nontemporal_load((c < 2 ? Sc + (c + 1) * 3 * Q3 : Sn) + d * Q3 + qz * QQ);
             // z in registers
             R a0[D], a1[D], a2[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) a0[i] = a1[i] = a2[i] = 0.0;
 #pragma unroll
             for (int qz = 0; qz < Q; ++qz) {
-                const R s0 = sv[c * 3 + 0][qz] * eq[qz];
-                const R s1 = sv[c * 3 + 1][qz] * eq[qz];
-                const R s2 = sv[c * 3 + 2][qz] * eq[qz];
+                const R s0 = sv[0][qz] * eq[qz];
+                const R s1 = sv[1][qz] * eq[qz];
+                const R s2 = sv[2][qz] * eq[qz];
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
                     const R b = tab[T::B + qz * D + iz], g = tab[T::G + qz * D + iz];
@@ -318,12 +333,6 @@ k_force_q4(const R *__restrict__ S, const double *__restrict__ e,
                     a2[iz] += g * s2;
                 }
             }
-#pragma unroll
-            for (int d = 0; d < 3; ++d)
-#pragma unroll
-                for (int qz = 0; qz < Q; ++qz)
-                    sv[c * 3 + d][qz] =
-                        actn ? __builtin_nontemporal_load(Sn + (c * 3 + d) * Q3 + qz * QQ) : (R)0;
 #pragma unroll
             for (int iz = 0; iz < D; ++iz) {
                 // y: thread (qx, iy = qy)
@@ -347,6 +356,10 @@ k_force_q4(const R *__restrict__ S, const double *__restrict__ e,
                 for (int j = 0; j < Q; ++j) rr += cGx[j] * w0[j] + cBx[j] * w1[j];
                 if (act && qx < D && qy < D) atomicAdd(&acc[3 * sl[iz] + c], rr);
             }
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int qz = 0; qz < Q; ++qz) sv[d][qz] = sn[d][qz];
         }
     }
     __syncthreads();
@@ -406,8 +419,8 @@ k_force_t(const RS *__restrict__ S, const double *__restrict__ v,
         for (int cd = 0; cd < 9; ++cd)
 #pragma unroll
             for (int qz = 0; qz < Q; ++qz)
-                sv[cd][qz] = act ? (R)__builtin_nontemporal_load(Se + cd * SQ + qz * QQ) : (R)0;
-        for (int i = t; i < D3; i += QQ) sSl[le][i] = act ? slot[el * D3 + i] : 0;
+                sv[cd][qz] = (R)__builtin_nontemporal_load(Se + cd * SQ + qz * QQ);
+        for (int i = t; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
         wave_sync();
         R s[Q];
 #pragma unroll
@@ -492,6 +505,311 @@ k_force_t(const RS *__restrict__ S, const double *__restrict__ v,
     }
 }
 
+// ------------------------------------------------ both force actions at once
+// y = F e (or F 1) and z = F^T v in one pass over S: the two actions share S
+// and the Lagrange step needs both at every stage (momentum and energy
+// equations, Sec. 3.3), so one read of S serves both. Per component c a pass
+// runs the F e contraction of c, then the F^T v contraction of c, while the
+// next component's S loads. At Q = 4 the y and x stages of F e run across
+// lanes as in k_force_q4.
+template <int D, int Q, bool ONE, typename R, int NW>
+__global__ void __launch_bounds__(NW * 64)
+k_force_pair(const R *__restrict__ S, const double *__restrict__ e, const double *__restrict__ v,
+             const int32_t *__restrict__ perm, const uint16_t *__restrict__ slot,
+             const int32_t *__restrict__ pn, const int32_t *__restrict__ ptab,
+             double *__restrict__ y, double *__restrict__ part, double *__restrict__ z,
+             long long ncomp, const R *__restrict__ tab)
+{
+    constexpr int NE = NW * wave_ne(Q), UMAX = patch_umax(D);
+    constexpr int DL = D - 1, QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D, DL3 = DL * DL * DL;
+    constexpr bool LANES = Q == 4;
+    constexpr int NA = LANES ? 1 : NE + 1;  // F e staging (unused across lanes)
+    using T = Tab<D, Q>;
+    __shared__ R acc[3 * UMAX];
+    __shared__ R vs[3 * UMAX];
+    __shared__ int sSl[NE + 1][D3];
+    __shared__ R sX[NE + 1][2][D][D * Q];
+    __shared__ R sT[NE + 1][DL][QQ];
+    __shared__ R sT2[NE + 1][DL][DL * Q];
+    __shared__ R sA[NA][3][D][QQ];
+    __shared__ R sC[NA][2][D][D * Q];
+
+    const int tid = threadIdx.x;
+    int le, t, qx, qy;
+    bool valid;
+    if constexpr (LANES) {
+        const int lane = tid & 63, r = lane & 15;
+        le = (tid >> 6) * 4 + (lane >> 4);
+        qy = r & 3;
+        qx = r >> 2;
+        t = qx + Q * qy;
+        valid = true;
+    } else {
+        const Lane L = lane_map<Q, NE>();
+        le = L.le;
+        t = L.t;
+        qx = t % Q;
+        qy = t / Q;
+        valid = L.valid;
+    }
+    const PatchRow pr = load_patch(ptab, xcd_block(blockIdx.x, gridDim.x));
+    for (int k = tid; k < 3 * pr.U; k += blockDim.x) acc[k] = 0.0;
+    for (int u = tid; u < pr.U; u += blockDim.x) {
+        const long long g = pn[pr.pno + u];
+        vs[3 * u] = (R)v[g];
+        vs[3 * u + 1] = (R)v[ncomp + g];
+        vs[3 * u + 2] = (R)v[2 * ncomp + g];
+    }
+    // F e: y weights (column qy), x weights (column qx, or the rotated source column)
+    R cBy[Q], cGy[Q], cBx[Q], cGx[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        cBy[k] = qy < D ? tab[T::B + k * D + qy] : (R)0;
+        cGy[k] = qy < D ? tab[T::G + k * D + qy] : (R)0;
+    }
+    if constexpr (LANES) {
+        const int kx[Q] = {qx, dpp_i<kRowRor4>(qx), dpp_i<kRowRor8>(qx), dpp_i<kRowRor12>(qx)};
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+            cBx[j] = qx < D ? tab[T::B + kx[j] * D + qx] : (R)0;
+            cGx[j] = qx < D ? tab[T::G + kx[j] * D + qx] : (R)0;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            cBx[k] = qx < D ? tab[T::B + k * D + qx] : (R)0;
+            cGx[k] = qx < D ? tab[T::G + k * D + qx] : (R)0;
+        }
+    }
+    // F^T v: interpolation weights of the point row qy / column qx
+    R rBx[D], rGx[D], rBy[D], rGy[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        rBx[i] = tab[T::B + qx * D + i];
+        rGx[i] = tab[T::G + qx * D + i];
+        rBy[i] = tab[T::B + qy * D + i];
+        rGy[i] = tab[T::G + qy * D + i];
+    }
+    __syncthreads();
+
+    // S by component: sv holds component c of this pass while sn loads the next
+    // component (or component 0 of the next pass)
+    R sv[3][Q], sn[3][Q];
+    {
+        const bool act0 = valid && le < pr.cnt;
+        const R *__restrict__ S0 = S + (long long)(pr.eb + (act0 ? le : 0)) * 9 * Q3 + t;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int qz = 0; qz < Q; ++qz)
+                sv[d][qz] = __builtin_nontemporal_load(S0 + d * Q3 + qz * QQ);
+    }
+#pragma unroll 1
+    for (int base = 0; base < pr.cnt; base += NE) {
+        const int idx = base + le;
+        const bool act = valid && idx < pr.cnt;
+        const long long el = pr.eb + (act ? idx : 0);
+        const bool actn = valid && idx + NE < pr.cnt;
+        const R *__restrict__ Sc = S + el * 9 * Q3 + t;
+        const R *__restrict__ Sn = S + (long long)(pr.eb + (actn ? idx + NE : 0)) * 9 * Q3 + t;
+        for (int i = t; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
+        R eq[Q];
+        if (ONE) {
+#pragma unroll
+            for (int k = 0; k < Q; ++k) eq[k] = 1.0;
+        } else {
+            const double *__restrict__ ee = e + (long long)perm[el] * DL3;
+            R tz[DL];
+#pragma unroll
+            for (int jz = 0; jz < DL; ++jz) {
+                R s = 0.0;
+#pragma unroll
+                for (int jy = 0; jy < DL; ++jy) {
+                    R u = 0.0;
+#pragma unroll
+                    for (int jx = 0; jx < DL; ++jx)
+                        u += tab[T::BL + qx * DL + jx] * (R)ee[(jz * DL + jy) * DL + jx];
+                    s += tab[T::BL + qy * DL + jy] * u;
+                }
+                tz[jz] = s;
+            }
+#pragma unroll
+            for (int qz = 0; qz < Q; ++qz) {
+                R s = 0.0;
+#pragma unroll
+                for (int jz = 0; jz < DL; ++jz) s += tab[T::BL + qz * DL + jz] * tz[jz];
+                eq[qz] = s;
+            }
+        }
+        wave_sync();  // the element's slots are in LDS
+        R sf[Q];      // F^T v: S : grad v at the column's points
+#pragma unroll
+        for (int k = 0; k < Q; ++k) sf[k] = 0.0;
+#pragma unroll 1
+        for (int c = 0; c < 3; ++c) {
+            // next component's S: this pass's c+1, or the next pass's component 0
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int qz = 0; qz < Q; ++qz)
+                    sn[d][qz] = __builtin_nontemporal_load((c < 2 ? Sc + (c + 1) * 3 * Q3 : Sn) + d * Q3 + qz * QQ);
+            // ---- F e, component c: z in registers
+            R a0[D], a1[D], a2[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) a0[i] = a1[i] = a2[i] = 0.0;
+#pragma unroll
+            for (int qz = 0; qz < Q; ++qz) {
+                const R s0 = sv[0][qz] * eq[qz];
+                const R s1 = sv[1][qz] * eq[qz];
+                const R s2 = sv[2][qz] * eq[qz];
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) {
+                    const R b = tab[T::B + qz * D + iz], g = tab[T::G + qz * D + iz];
+                    a0[iz] += b * s0;
+                    a1[iz] += b * s1;
+                    a2[iz] += g * s2;
+                }
+            }
+            if constexpr (LANES) {
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) {
+                    const R u0[Q] = {dpp_r<kQuadBcast0>(a0[iz]), dpp_r<kQuadBcast1>(a0[iz]),
+                                     dpp_r<kQuadBcast2>(a0[iz]), dpp_r<kQuadBcast3>(a0[iz])};
+                    const R u1[Q] = {dpp_r<kQuadBcast0>(a1[iz]), dpp_r<kQuadBcast1>(a1[iz]),
+                                     dpp_r<kQuadBcast2>(a1[iz]), dpp_r<kQuadBcast3>(a1[iz])};
+                    const R u2[Q] = {dpp_r<kQuadBcast0>(a2[iz]), dpp_r<kQuadBcast1>(a2[iz]),
+                                     dpp_r<kQuadBcast2>(a2[iz]), dpp_r<kQuadBcast3>(a2[iz])};
+                    R c0 = 0.0, c1 = 0.0;
+#pragma unroll
+                    for (int k = 0; k < Q; ++k) {
+                        c0 += cBy[k] * u0[k];
+                        c1 += cGy[k] * u1[k] + cBy[k] * u2[k];
+                    }
+                    const R w0[Q] = {c0, dpp_r<kRowRor4>(c0), dpp_r<kRowRor8>(c0), dpp_r<kRowRor12>(c0)};
+                    const R w1[Q] = {c1, dpp_r<kRowRor4>(c1), dpp_r<kRowRor8>(c1), dpp_r<kRowRor12>(c1)};
+                    R rr = 0.0;
+#pragma unroll
+                    for (int j = 0; j < Q; ++j) rr += cGx[j] * w0[j] + cBx[j] * w1[j];
+                    if (act && qx < D && qy < D)
+                        atomicAdd(&acc[3 * sSl[le][(iz * D + qy) * D + qx] + c], rr);
+                }
+            } else {
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) {
+                    sA[le][0][iz][t] = a0[iz];
+                    sA[le][1][iz][t] = a1[iz];
+                    sA[le][2][iz][t] = a2[iz];
+                }
+                wave_sync();
+                if (qy < D) {
+#pragma unroll
+                    for (int iz = 0; iz < D; ++iz) {
+                        R c0 = 0.0, c1 = 0.0;
+#pragma unroll
+                        for (int k = 0; k < Q; ++k) {
+                            c0 += cBy[k] * sA[le][0][iz][k * Q + qx];
+                            c1 += cGy[k] * sA[le][1][iz][k * Q + qx] + cBy[k] * sA[le][2][iz][k * Q + qx];
+                        }
+                        sC[le][0][iz][qy * Q + qx] = c0;
+                        sC[le][1][iz][qy * Q + qx] = c1;
+                    }
+                }
+                wave_sync();
+                if (act && qx < D && qy < D) {
+#pragma unroll
+                    for (int iz = 0; iz < D; ++iz) {
+                        R rr = 0.0;
+#pragma unroll
+                        for (int k = 0; k < Q; ++k)
+                            rr += cGx[k] * sC[le][0][iz][qy * Q + k] + cBx[k] * sC[le][1][iz][qy * Q + k];
+                        atomicAdd(&acc[3 * sSl[le][(iz * D + qy) * D + qx] + c], rr);
+                    }
+                }
+            }
+            // ---- F^T v, component c: x-stage, thread (qx, iy = qy)
+            if (qy < D) {
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) {
+                    R ub = 0.0, ug = 0.0;
+#pragma unroll
+                    for (int ix = 0; ix < D; ++ix) {
+                        const R u = vs[3 * sSl[le][(iz * D + qy) * D + ix] + c];
+                        ub += rBx[ix] * u;
+                        ug += rGx[ix] * u;
+                    }
+                    sX[le][0][iz][qy * Q + qx] = ub;
+                    sX[le][1][iz][qy * Q + qx] = ug;
+                }
+            }
+            wave_sync();
+            R vx[D], vy[D], vz[D];
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) {
+                R a = 0.0, b = 0.0, cc = 0.0;
+#pragma unroll
+                for (int iy = 0; iy < D; ++iy) {
+                    const R ub = sX[le][0][iz][iy * Q + qx], ug = sX[le][1][iz][iy * Q + qx];
+                    a += rBy[iy] * ug;
+                    b += rGy[iy] * ub;
+                    cc += rBy[iy] * ub;
+                }
+                vx[iz] = a;
+                vy[iz] = b;
+                vz[iz] = cc;
+            }
+            wave_sync();  // sX (and sA, sC) are rewritten by the next component
+#pragma unroll
+            for (int qz = 0; qz < Q; ++qz) {
+                R dx = 0.0, dy = 0.0, dz = 0.0;
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) {
+                    const R bb = tab[T::B + qz * D + iz], gg = tab[T::G + qz * D + iz];
+                    dx += bb * vx[iz];
+                    dy += bb * vy[iz];
+                    dz += gg * vz[iz];
+                }
+                sf[qz] += sv[0][qz] * dx + sv[1][qz] * dy + sv[2][qz] * dz;
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int qz = 0; qz < Q; ++qz) sv[d][qz] = sn[d][qz];
+        }
+        // F^T v: L2 test functions, B_l^T in z (registers), y and x (LDS)
+#pragma unroll
+        for (int jz = 0; jz < DL; ++jz) {
+            R a = 0.0;
+#pragma unroll
+            for (int qz = 0; qz < Q; ++qz) a += tab[T::BL + qz * DL + jz] * sf[qz];
+            sT[le][jz][t] = a;
+        }
+        wave_sync();
+        if (qy < DL) {
+#pragma unroll
+            for (int jz = 0; jz < DL; ++jz) {
+                R a = 0.0;
+#pragma unroll
+                for (int k = 0; k < Q; ++k) a += tab[T::BL + k * DL + qy] * sT[le][jz][k * Q + qx];
+                sT2[le][jz][qy * Q + qx] = a;
+            }
+        }
+        wave_sync();
+        if (act && qx < DL && qy < DL) {
+            double *__restrict__ zr = z + (long long)perm[el] * DL3;
+#pragma unroll
+            for (int jz = 0; jz < DL; ++jz) {
+                R a = 0.0;
+#pragma unroll
+                for (int k = 0; k < Q; ++k) a += tab[T::BL + k * DL + qx] * sT2[le][jz][qy * Q + k];
+                zr[(jz * DL + qy) * DL + qx] = (double)a;
+            }
+        }
+        wave_sync();  // sSl, sT and sT2 are rewritten by the next pass
+    }
+    __syncthreads();
+    patch_write<UMAX>(acc, pr, pn, y, part, ncomp);
+}
+
 // -------------------------------------------------------------- mass M_v x
 // y_c = R^T B^T diag(m_q) B R x_c, one patch per workgroup, one component at a
 // time: the patch's distinct-node values of x_c are read once into LDS, each
@@ -558,8 +876,8 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
             const long long el = pr.eb + (act ? idx : 0);
             R m[Q];
 #pragma unroll
-            for (int k = 0; k < Q; ++k) m[k] = act ? mq[el * Q3 + k * QQ + t] : (R)0;
-            for (int i = t; i < D3; i += QQ) sSl[le][i] = act ? slot[el * D3 + i] : 0;
+            for (int k = 0; k < Q; ++k) m[k] = mq[el * Q3 + k * QQ + t];
+            for (int i = t; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
             wave_sync();
             // x-stage: thread (qx, iy = qy)
             if (qy < D) {
@@ -905,6 +1223,30 @@ struct Launch {
         return force_nw<2>(S, e, pd, y, ncomp, tab, st);
     }
     template <int NW>
+    static void force_pair_nw(const void *S, const double *e, const double *v, const PatchDev &pd,
+                              double *y, double *z, long long ncomp, const void *tab, hipStream_t st)
+    {
+        const dim3 grid(pd.n_patch), block(NW * 64);
+        if (e)
+            hipLaunchKernelGGL((k_force_pair<D, Q, false, R, NW>), grid, block, 0, st, (const R *)S, e, v,
+                               pd.perm, pd.slot, pd.pn, pd.ptab, y, pd.part, z, ncomp, (const R *)tab);
+        else
+            hipLaunchKernelGGL((k_force_pair<D, Q, true, R, NW>), grid, block, 0, st, (const R *)S, e, v,
+                               pd.perm, pd.slot, pd.pn, pd.ptab, y, pd.part, z, ncomp, (const R *)tab);
+    }
+    static void force_pair(const void *S, const double *e, const double *v, const PatchDev &pd,
+                           double *y, double *z, long long ncomp, const void *tab, int nw,
+                           hipStream_t st)
+    {
+        constexpr int rs = sizeof(R);
+        if constexpr (force_pair_lds(D, Q, rs, 8) <= kLdsMax)
+            if (nw >= 8) return force_pair_nw<8>(S, e, v, pd, y, z, ncomp, tab, st);
+        if constexpr (force_pair_lds(D, Q, rs, 4) <= kLdsMax)
+            if (nw >= 4) return force_pair_nw<4>(S, e, v, pd, y, z, ncomp, tab, st);
+        static_assert(force_pair_lds(D, Q, rs, 2) <= kLdsMax, "the 2-wave pair kernel must fit LDS");
+        return force_pair_nw<2>(S, e, v, pd, y, z, ncomp, tab, st);
+    }
+    template <int NW>
     static void force_t_nw(const void *S, const double *v, const PatchDev &pd, double *z,
                            long long ncomp, const void *tab, hipStream_t st)
     {
@@ -967,6 +1309,12 @@ struct Launch {
         }
         if (kind == 1)
             return force_t_lds(D, Q, rs, NW) <= kLdsMax && no_spill(k_force_t<D, Q, R, R, NW>);
+        if (kind == 3) {
+            if constexpr (force_pair_lds(D, Q, rs, NW) <= kLdsMax)
+                return no_spill(k_force_pair<D, Q, true, R, NW>) && no_spill(k_force_pair<D, Q, false, R, NW>);
+            else
+                return false;
+        }
         return mass_lds(D, Q, rs, NW) <= kLdsMax && no_spill(k_mass<D, Q, true, R, NW>) &&
                no_spill(k_mass<D, Q, false, R, NW>);
     }
@@ -1002,7 +1350,8 @@ static const KernelSet *kernels_for(int p, int Q)
 #define FEPA_ENTRY(P, QQ)                                                                        \
     static const KernelSet ks_##P##_##QQ = {                                                     \
         Launch<P + 1, QQ, R>::force, Launch<P + 1, QQ, R>::force_t, Launch<P + 1, QQ, R>::mass, \
-        Launch<P + 1, QQ, R>::qdata, patch_umax(P + 1), Launch<P + 1, QQ, R>::max_nw};           \
+        Launch<P + 1, QQ, R>::qdata, patch_umax(P + 1), Launch<P + 1, QQ, R>::max_nw,           \
+        Launch<P + 1, QQ, R>::force_pair};                                                       \
     if (p == P && Q == QQ) return &ks_##P##_##QQ;
     FEPA_PQ_LIST(FEPA_ENTRY)
 #undef FEPA_ENTRY
@@ -1049,6 +1398,7 @@ bool bf16_parts(int p, int Q, KernelSet *ks)
     if (p == P && Q == QQ) {                                \
         ks->force_t = LaunchBf16<P + 1, QQ>::force_t;       \
         ks->qdata = LaunchBf16<P + 1, QQ>::qdata;           \
+        ks->force_pair = nullptr;                           \
         return true;                                        \
     }
     FEPA_PQ_LIST(FEPA_ENTRY)

@@ -59,9 +59,14 @@ struct KernelSet {
                   long long ncomp, int node_off, double *mq, void *S, const double *tab,
                   QParams prm, long long *min_key, int *nonfinite, bool init, hipStream_t st);
     int umax;  // distinct-node capacity of a patch for this order
-    // largest waves per workgroup of kind 0 (force), 1 (force^T), 2 (mass)
-    // that fits the LDS limit without register spills
+    // largest waves per workgroup of kind 0 (force), 1 (force^T), 2 (mass),
+    // 3 (force pair) that fits the LDS limit without register spills
     int (*max_nw)(int kind);
+    // y = F e (F 1 when e is null) and z = F^T v in one pass over S; nullptr
+    // where the form has none (the BF16 form runs the two actions)
+    void (*force_pair)(const void *S, const double *e, const double *v, const PatchDev &pd,
+                       double *y, double *z, long long ncomp, const void *tab, int nw,
+                       hipStream_t st);
 };
 
 // nullptr when (p, Q) is not instantiated.
