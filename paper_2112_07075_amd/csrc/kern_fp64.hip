@@ -962,6 +962,149 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
     }
 }
 
+// The mass action at Q = 4 with the y, z^T-side y and x^T contractions across
+// lanes (quad broadcasts and row rotations as in k_force_q4): LDS holds only
+// the patch's node values, its accumulator and the element slots.
+template <int D, bool DOT, typename R, int NW>
+__global__ void __launch_bounds__(NW * 64)
+k_mass_q4(const R *__restrict__ mq, const double *__restrict__ x,
+          const int32_t *__restrict__ map, const uint16_t *__restrict__ slot,
+          const int32_t *__restrict__ pn, const int32_t *__restrict__ ptab,
+          double *__restrict__ y, double *__restrict__ part, long long ncomp,
+          const R *__restrict__ tab, double *__restrict__ part_dot,
+          const int *__restrict__ skip, const double *__restrict__ x2,
+          const double *__restrict__ beta, const int *__restrict__ pmesh, int sstride)
+{
+    constexpr int Q = 4, NE = NW * 4, UMAX = patch_umax(D);
+    constexpr int QQ = 16, Q3 = 64, D3 = D * D * D;
+    using T = Tab<D, Q>;
+    const int pi = xcd_block(blockIdx.x, gridDim.x);
+    const size_t soff = pmesh ? (size_t)pmesh[pi] * sstride : 0;
+    if (skip && *(const int *)((const char *)skip + soff)) return;  // a finished CG solve
+    __shared__ R acc[UMAX];
+    __shared__ R xs[UMAX];
+    __shared__ int sSl[NE][D3];
+    __shared__ double sred[8];
+    (void)map;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int le = (tid >> 6) * 4 + (lane >> 4);
+    const int r = lane & 15, qy = r & 3, qx = r >> 2, t = qx + Q * qy;
+    const PatchRow pr = load_patch(ptab, pi);
+    // x: interpolation weights of column qx; y: weights of row qy (broadcast lane k
+    // brings node row k); y^T: weights of node row qy over the quad's points;
+    // x^T: weights over the rotated source columns
+    R rBx[D], rBy[D], cBy[Q], cBx[Q];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        rBx[i] = tab[T::B + qx * D + i];
+        rBy[i] = tab[T::B + qy * D + i];
+    }
+    const int kx[Q] = {qx, dpp_i<kRowRor4>(qx), dpp_i<kRowRor8>(qx), dpp_i<kRowRor12>(qx)};
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        cBy[k] = qy < D ? tab[T::B + k * D + qy] : (R)0;
+        cBx[k] = qx < D ? tab[T::B + kx[k] * D + qx] : (R)0;
+    }
+    const int qyc = qy < D ? qy : D - 1;
+    double dot = 0.0;
+    const double bt = x2 ? *(const double *)((const char *)beta + soff) : 0.0;
+
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) {
+        for (int u = tid; u < pr.U; u += blockDim.x) {
+            const long long g = c * ncomp + pn[pr.pno + u];
+            xs[u] = (R)(x2 ? x[g] + bt * x2[g] : x[g]);
+            acc[u] = (R)0;
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int base = 0; base < pr.cnt; base += NE) {
+            const int idx = base + le;
+            const bool act = idx < pr.cnt;
+            const long long el = pr.eb + (act ? idx : 0);
+            R m[Q];
+#pragma unroll
+            for (int k = 0; k < Q; ++k) m[k] = mq[el * Q3 + k * QQ + t];
+            for (int i = r; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
+            wave_sync();
+            // x: thread (qx, iy = qy) from the node values in LDS
+            R X[D];
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) {
+                R a = 0;
+#pragma unroll
+                for (int ix = 0; ix < D; ++ix) a += rBx[ix] * xs[sSl[le][(iz * D + qyc) * D + ix]];
+                X[iz] = a;
+            }
+            // y: thread (qx, qy) over the quad's node rows iy < D
+            R w[D];
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) {
+                const R u[Q] = {dpp_r<kQuadBcast0>(X[iz]), dpp_r<kQuadBcast1>(X[iz]),
+                                dpp_r<kQuadBcast2>(X[iz]), dpp_r<kQuadBcast3>(X[iz])};
+                R a = 0;
+#pragma unroll
+                for (int iy = 0; iy < D; ++iy) a += rBy[iy] * u[iy];
+                w[iz] = a;
+            }
+            // z, weights, z^T in registers
+            R a[D];
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) a[iz] = 0;
+#pragma unroll
+            for (int qz = 0; qz < Q; ++qz) {
+                R u = 0;
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) u += tab[T::B + qz * D + iz] * w[iz];
+                u *= m[qz];
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) a[iz] += tab[T::B + qz * D + iz] * u;
+            }
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) {
+                // y^T: thread (qx, iy = qy) over the quad's points
+                const R u[Q] = {dpp_r<kQuadBcast0>(a[iz]), dpp_r<kQuadBcast1>(a[iz]),
+                                dpp_r<kQuadBcast2>(a[iz]), dpp_r<kQuadBcast3>(a[iz])};
+                R b = 0;
+#pragma unroll
+                for (int k = 0; k < Q; ++k) b += cBy[k] * u[k];
+                // x^T: thread (ix = qx, iy = qy) over the row's point columns
+                const R v4[Q] = {b, dpp_r<kRowRor4>(b), dpp_r<kRowRor8>(b), dpp_r<kRowRor12>(b)};
+                R rr = 0;
+#pragma unroll
+                for (int j = 0; j < Q; ++j) rr += cBx[j] * v4[j];
+                if (act && qx < D && qy < D) {
+                    const int s = sSl[le][(iz * D + qy) * D + qx];
+                    atomicAdd(&acc[s], rr);
+                    if (DOT) dot += (double)rr * (double)xs[s];
+                }
+            }
+            wave_sync();  // sSl is rewritten by the next pass
+        }
+        __syncthreads();
+        for (int u = tid; u < pr.U; u += blockDim.x) {
+            const double av = (double)acc[u];
+            if (u < pr.P)
+                y[c * ncomp + pn[pr.pno + u]] = av;
+            else
+                part[3 * (long long)(pr.sho + u - pr.P) + c] = av;
+        }
+        __syncthreads();  // xs and acc are rewritten by the next component
+    }
+    if (DOT) {
+        for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off);
+        const int wl = tid & 63, wv = tid >> 6;
+        if (wl == 0) sred[wv] = dot;
+        __syncthreads();
+        if (tid == 0) {
+            double sum = 0.0;
+            for (int k = 0; k < (int)((blockDim.x + 63) >> 6); ++k) sum += sred[k];
+            part_dot[pi] = sum;  // at the patch index: partial ranges per mesh follow patches
+        }
+    }
+}
+
 // Shared nodes: y[c][g] = sum of the patch partials of g, in ascending patch order.
 __global__ void k_gather_shared(const double *__restrict__ part, const int32_t *__restrict__ sh_node,
                                 const int32_t *__restrict__ sh_ptr,
@@ -1268,14 +1411,25 @@ struct Launch {
                         long long ncomp, const void *tab, const MassCg &cg, hipStream_t st)
     {
         const dim3 grid(pd.n_patch), block(NW * 64);
-        if (cg.part_dot)
-            hipLaunchKernelGGL((k_mass<D, Q, true, R, NW>), grid, block, 0, st, (const R *)mq, x,
-                               pd.map, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab,
-                               cg.part_dot, cg.skip, cg.x2, cg.beta, cg.pmesh, cg.sstride);
-        else
-            hipLaunchKernelGGL((k_mass<D, Q, false, R, NW>), grid, block, 0, st, (const R *)mq, x,
-                               pd.map, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab,
-                               cg.part_dot, cg.skip, cg.x2, cg.beta, cg.pmesh, cg.sstride);
+        if constexpr (Q == 4) {
+            if (cg.part_dot)
+                hipLaunchKernelGGL((k_mass_q4<D, true, R, NW>), grid, block, 0, st, (const R *)mq, x,
+                                   pd.map, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab,
+                                   cg.part_dot, cg.skip, cg.x2, cg.beta, cg.pmesh, cg.sstride);
+            else
+                hipLaunchKernelGGL((k_mass_q4<D, false, R, NW>), grid, block, 0, st, (const R *)mq, x,
+                                   pd.map, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab,
+                                   cg.part_dot, cg.skip, cg.x2, cg.beta, cg.pmesh, cg.sstride);
+        } else {
+            if (cg.part_dot)
+                hipLaunchKernelGGL((k_mass<D, Q, true, R, NW>), grid, block, 0, st, (const R *)mq, x,
+                                   pd.map, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab,
+                                   cg.part_dot, cg.skip, cg.x2, cg.beta, cg.pmesh, cg.sstride);
+            else
+                hipLaunchKernelGGL((k_mass<D, Q, false, R, NW>), grid, block, 0, st, (const R *)mq, x,
+                                   pd.map, pd.slot, pd.pn, pd.ptab, y, pd.part, ncomp, (const R *)tab,
+                                   cg.part_dot, cg.skip, cg.x2, cg.beta, cg.pmesh, cg.sstride);
+        }
     }
     static void mass(const void *mq, const double *x, const PatchDev &pd, double *y,
                      long long ncomp, const void *tab, const MassCg &cg, int nw, hipStream_t st)
@@ -1315,8 +1469,12 @@ struct Launch {
             else
                 return false;
         }
-        return mass_lds(D, Q, rs, NW) <= kLdsMax && no_spill(k_mass<D, Q, true, R, NW>) &&
-               no_spill(k_mass<D, Q, false, R, NW>);
+        if constexpr (Q == 4)
+            return mass_lds(D, Q, rs, NW) <= kLdsMax && no_spill(k_mass_q4<D, true, R, NW>) &&
+                   no_spill(k_mass_q4<D, false, R, NW>);
+        else
+            return mass_lds(D, Q, rs, NW) <= kLdsMax && no_spill(k_mass<D, Q, true, R, NW>) &&
+                   no_spill(k_mass<D, Q, false, R, NW>);
     }
     static int max_nw(int kind)
     {
