@@ -1,10 +1,10 @@
 """Autotuner of the patch-kernel tile shapes.
 
 For one workload (order p, points Q, precision) it sweeps the elements per
-patch and the waves per workgroup of the F.1, F^T.v and M x kernels, times each
-action with the library's event timers on the GPU, and writes the fastest
-choice as one line "p Q precision nw_force nw_force_t nw_mass patch" of a
-tuning table. fe_pa_setup reads that table when the environment variable
+patch and the waves per workgroup of the F.1, F^T.v, M x and fused F.1 + F^T.v
+kernels, times each action with the library's event timers on the GPU, and
+writes the fastest choice as one line "p Q precision nw_force nw_force_t
+nw_mass patch nw_pair" of a tuning table. fe_pa_setup reads that table when the environment variable
 FEPA_TUNE_TABLE names it (explicit fe_opts_t tune fields take precedence).
 
 The --builtin mode tunes every (p, Q) pair in FP64 and the Q = p+2 pairs in
@@ -28,7 +28,7 @@ WAVES = (2, 4, 8)
 
 
 def patch_choices(p: int):
-    return {1: (16, 32, 64, 128, 256, 512), 2: (8, 16, 24, 32, 48, 64)}.get(p, (4, 6, 8))
+    return {1: (32, 64, 128, 256), 2: (16, 32, 48, 64)}.get(p, (4, 6, 8))
 
 
 def time_actions(fe, torch, mesh, p, Q, precision, nw, patch, reps=20):
@@ -47,16 +47,20 @@ def time_actions(fe, torch, mesh, p, Q, precision, nw, patch, reps=20):
         fe.fe_force_mult(ctx, None, y)
         fe.fe_force_mult_T(ctx, v, z)
         fe.fe_mass_mult(ctx, v, y)
+        fe.fe_force_mult_pair(ctx, None, y, v, z)
     fe.fe_timer_reset(ctx)
     for _ in range(reps):
         fe.fe_force_mult(ctx, None, y)
         fe.fe_force_mult_T(ctx, v, z)
         fe.fe_mass_mult(ctx, v, y)
+        fe.fe_force_mult_pair(ctx, None, y, v, z)
     out = {}
     for name, which in (("force", fe.FE_TIMER_FORCE), ("force_t", fe.FE_TIMER_FORCE_T),
-                        ("mass", fe.FE_TIMER_MASS)):
+                        ("mass", fe.FE_TIMER_MASS), ("pair", fe.FE_TIMER_PAIR)):
         ms, cnt = fe.fe_timer_read(ctx, which)
-        out[name] = ms / cnt * 1e3
+        out[name] = ms / cnt * 1e3 if cnt else float("nan")
+    if out["pair"] != out["pair"]:  # a form without the fused kernel runs the two actions
+        out["pair"] = out["force"] + out["force_t"]
     info = fe.fe_query(ctx)
     out["used"] = (info["nw_force"], info["nw_force_t"], info["nw_mass"], info["patch"])
     fe.fe_destroy(ctx)
@@ -83,24 +87,30 @@ def tune(n: int, p: int, Q: int, precision: int = 0, verbose: bool = True):
     for patch in patch_choices(p):
         for nw in WAVES:
             t = time_actions(fe, torch, mesh, p, Q, precision, nw, patch)
-            trials.append({"patch": patch, "nw": nw, **{k: t[k] for k in ("force", "force_t", "mass")},
+            trials.append({"patch": patch, "nw": nw,
+                           **{k: t[k] for k in ("force", "force_t", "mass", "pair")},
                            "used": t["used"]})
             if verbose:
                 print(f"patch {patch:3d} waves {nw}: F.1 {t['force']:8.1f} us  F^T.v "
-                      f"{t['force_t']:8.1f} us  M x {t['mass']:8.1f} us  (in use {t['used']})",
-                      flush=True)
+                      f"{t['force_t']:8.1f} us  M x {t['mass']:8.1f} us  pair {t['pair']:8.1f} us"
+                      f"  (in use {t['used']})", flush=True)
     # patches are shared by the three actions: choose the patch size minimising the sum
     # of the best times, then the waves per workgroup of each action for that patch size
+    # the step runs the fused pair and the mass action; the single actions are
+    # tuned too (they are called on their own)
     def best_for(patch):
         rows = [r for r in trials if r["patch"] == patch]
-        pick = {k: min(rows, key=lambda r: r[k]) for k in ("force", "force_t", "mass")}
-        return sum(pick[k][k] for k in pick), pick
+        pick = {k: min(rows, key=lambda r: r[k]) for k in ("force", "force_t", "mass", "pair")}
+        return pick["pair"]["pair"] + pick["mass"]["mass"], pick
 
     total, pick, patch = min((best_for(pt) + (pt,) for pt in patch_choices(p)),
                              key=lambda x: x[0])
     best = {"p": p, "Q": Q, "precision": precision, "patch": patch,
             "nw_force": pick["force"]["used"][0], "nw_force_t": pick["force_t"]["used"][1],
             "nw_mass": pick["mass"]["used"][2],
+            # -1: the two single kernels beat the fused one (the pair then runs them)
+            "nw_pair": (pick["pair"]["nw"] if pick["pair"]["pair"] <= pick["force"]["force"] +
+                        pick["force_t"]["force_t"] else -1),
             "us": {k: pick[k][k] for k in pick}, "trials": trials}
     return best
 
@@ -135,17 +145,19 @@ def write_builtin(path: str):
         print("   best:", table_line(b), json.dumps(b["us"]), flush=True)
     with open(path, "w") as f:
         f.write("// Generated by paper_2112_07075_amd/autotune.py --builtin: {p, Q, precision,\n"
-                "// waves F, waves F^T, waves M, elements per patch}, fastest measured on MI355X.\n")
+                "// waves F, waves F^T, waves M, elements per patch, waves F + F^T fused\n"
+                "// (-1: the pair runs as the two single kernels)},\n"
+                "// fastest measured on MI355X.\n")
         for b in rows:
             us = b["us"]
             f.write(f"{{{b['p']}, {b['Q']}, {b['precision']}, {b['nw_force']}, {b['nw_force_t']}, "
-                    f"{b['nw_mass']}, {b['patch']}}},  // F.1 {us['force']:.1f} us, "
-                    f"F^T.v {us['force_t']:.1f} us, M x {us['mass']:.1f} us\n")
+                    f"{b['nw_mass']}, {b['patch']}, {b['nw_pair']}}},  // F.1 {us['force']:.1f} us, "
+                    f"F^T.v {us['force_t']:.1f} us, M x {us['mass']:.1f} us, pair {us['pair']:.1f} us\n")
 
 
 def table_line(b) -> str:
     return (f"{b['p']} {b['Q']} {b['precision']} {b['nw_force']} {b['nw_force_t']} "
-            f"{b['nw_mass']} {b['patch']}")
+            f"{b['nw_mass']} {b['patch']} {b['nw_pair']}")
 
 
 def main():

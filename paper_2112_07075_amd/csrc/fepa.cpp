@@ -38,6 +38,7 @@ struct MeshRec {
     long long Sb_off = 0;            // offset of the mesh's S in the stored type
     int nw_force = 4, nw_force_t = 4, nw_mass = 4;  // waves per workgroup
     int nw_pair = 4;                                 // of the fused F e + F^T v kernel
+    bool pair_split = false;                         // the pair runs as the two actions
     int patch = 0;                                   // elements per patch (0: default)
     long long tabb_off = 0;          // BF16 form: byte offset of its operand buffer
     double rho0 = 1.0;
@@ -244,14 +245,14 @@ struct ScopedTimer {
 bool supported_pq(int p, int Q) { return fp64_kernels(p, Q) != nullptr; }
 
 struct TuneEntry {
-    int p, Q, prec, nwf, nwt, nwm, patch;
+    int p, Q, prec, nwf, nwt, nwm, patch, nwp;  // nwp: fused pair (0: as F e)
 };
 
 // Tile shapes measured by the autotuner (paper_2112_07075_amd/autotune.py,
 // --builtin) on MI355X, one row per (p, Q, precision); ends with a zero row.
 const TuneEntry kBuiltinTune[] = {
 #include "tune_table.inc"
-    {0, 0, 0, 0, 0, 0, 0}};
+    {0, 0, 0, 0, 0, 0, 0, 0}};
 
 // the built-in table followed by the one named by FEPA_TUNE_TABLE (missing or
 // unreadable: none); later rows take precedence
@@ -268,8 +269,8 @@ std::vector<TuneEntry> read_tune_table()
     while (std::fgets(line, sizeof(line), f)) {
         TuneEntry e{};
         if (line[0] == '#') continue;
-        if (std::sscanf(line, "%d %d %d %d %d %d %d", &e.p, &e.Q, &e.prec, &e.nwf, &e.nwt, &e.nwm,
-                        &e.patch) == 7)
+        if (std::sscanf(line, "%d %d %d %d %d %d %d %d", &e.p, &e.Q, &e.prec, &e.nwf, &e.nwt, &e.nwm,
+                        &e.patch, &e.nwp) >= 7)
             t.push_back(e);
     }
     std::fclose(f);
@@ -470,12 +471,16 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
             r.nw_force_t = default_nw(4, force_t_lds(D, r.Q, rs, 8), force_t_lds(D, r.Q, rs, 4));
             r.nw_mass = default_nw(8, mass_lds(D, r.Q, rs, 8), mass_lds(D, r.Q, rs, 4));
             r.patch = 0;
+            r.nw_pair = 0;
+            r.pair_split = false;
             for (const TuneEntry &te : tune)
                 if (te.p == r.p && te.Q == r.Q && te.prec == o.precision) {
                     if (te.nwf) r.nw_force = te.nwf;
                     if (te.nwt) r.nw_force_t = te.nwt;
                     if (te.nwm) r.nw_mass = te.nwm;
                     if (te.patch) r.patch = te.patch;
+                    r.nw_pair = te.nwp > 0 ? te.nwp : 0;
+                    r.pair_split = te.nwp < 0;
                 }
             if (o.tune_nw_force) r.nw_force = o.tune_nw_force;
             if (o.tune_nw_force_t) r.nw_force_t = o.tune_nw_force_t;
@@ -486,7 +491,8 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
             r.nw_force = std::min(r.nw_force, kc.max_nw(0));
             r.nw_force_t = std::min(r.nw_force_t, kc.max_nw(1));
             r.nw_mass = std::min(r.nw_mass, kc.max_nw(2));
-            r.nw_pair = std::min(r.nw_force, kc.max_nw(3));
+            if (o.tune_nw_force || !r.nw_pair) r.nw_pair = r.nw_force;  // explicit shapes: one for both
+            r.nw_pair = std::min(r.nw_pair, kc.max_nw(3));
         }
         if (ctx->bf) {
             r.kl.force = bf16_force(r.p, r.Q);
@@ -927,8 +933,15 @@ int fe_force_mult_pair(fe_ctx_t *ctx, const double *e, double *y, const double *
     ScopedTimer tm(ctx, FE_TIMER_PAIR);
     return run_graph(ctx, GraphKey{kActPair, e, y, v, 0, z}, [&](hipStream_t s, bool branch) {
         enqueue_units(ctx, s, branch, [&](const MeshRec &r, hipStream_t su) {
-            r.kl.force_pair(S_of(ctx, r), e ? e + r.l2_off : nullptr, v, r.pd, y, z + r.l2_off,
-                            ctx->N_tot, tab_of(ctx, r), r.nw_pair, su);
+            if (r.pair_split) {  // the tile table measured the two kernels faster here
+                r.kl.force(S_of(ctx, r), e ? e + r.l2_off : nullptr, r.pd, y, ctx->N_tot,
+                           tab_of(ctx, r), r.nw_force, su);
+                r.kl.force_t(S_of(ctx, r), v, r.pd, r.E, z + r.l2_off, ctx->N_tot, tab_of(ctx, r),
+                             r.nw_force_t, su);
+            } else {
+                r.kl.force_pair(S_of(ctx, r), e ? e + r.l2_off : nullptr, v, r.pd, y, z + r.l2_off,
+                                ctx->N_tot, tab_of(ctx, r), r.nw_pair, su);
+            }
             launch_gather_shared(r.pd, y, ctx->N_tot, nullptr, su);
             launch_zero_nodes(r.orphans, r.n_orphans, y, ctx->N_tot, nullptr, su);
         });
