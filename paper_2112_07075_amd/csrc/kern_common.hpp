@@ -138,7 +138,7 @@ __host__ __device__ constexpr int force_t_lds(int D, int Q, int rs, int NW)
 __host__ __device__ constexpr int mass_lds(int D, int Q, int rs, int NW)
 {
     // at Q = 4 only the node values, the accumulator and the element slots
-    return Q == 4 ? 2 * rs * patch_umax(D) + NW * 4 * 4 * D * D * D + 64
+    return Q == 4 ? 6 * rs * patch_umax(D) + NW * 4 * 4 * D * D * D + 64
                   : 2 * rs * patch_umax(D) + (NW * wave_ne(Q) + 1) * (4 * D * D * D + rs * (D * D * Q + D * Q * Q)) + 64;
 }
 

@@ -962,9 +962,11 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
     }
 }
 
-// The mass action at Q = 4 with the y, z^T-side y and x^T contractions across
-// lanes (quad broadcasts and row rotations as in k_force_q4): LDS holds only
-// the patch's node values, its accumulator and the element slots.
+// The mass action at Q = 4 with the y, y^T and x^T contractions across lanes
+// (quad broadcasts and row rotations as in k_force_q4): LDS holds only the
+// patch's node values, its accumulator and the element slots, so all three
+// components fit at once and a patch needs one gather, one pass over its
+// elements and one write-out.
 template <int D, bool DOT, typename R, int NW>
 __global__ void __launch_bounds__(NW * 64)
 k_mass_q4(const R *__restrict__ mq, const double *__restrict__ x,
@@ -981,8 +983,8 @@ k_mass_q4(const R *__restrict__ mq, const double *__restrict__ x,
     const int pi = xcd_block(blockIdx.x, gridDim.x);
     const size_t soff = pmesh ? (size_t)pmesh[pi] * sstride : 0;
     if (skip && *(const int *)((const char *)skip + soff)) return;  // a finished CG solve
-    __shared__ R acc[UMAX];
-    __shared__ R xs[UMAX];
+    __shared__ R acc[3 * UMAX];
+    __shared__ R xs[3 * UMAX];
     __shared__ int sSl[NE][D3];
     __shared__ double sred[8];
     (void)map;
@@ -1010,31 +1012,37 @@ k_mass_q4(const R *__restrict__ mq, const double *__restrict__ x,
     double dot = 0.0;
     const double bt = x2 ? *(const double *)((const char *)beta + soff) : 0.0;
 
-#pragma unroll 1
-    for (int c = 0; c < 3; ++c) {
-        for (int u = tid; u < pr.U; u += blockDim.x) {
-            const long long g = c * ncomp + pn[pr.pno + u];
-            xs[u] = (R)(x2 ? x[g] + bt * x2[g] : x[g]);
-            acc[u] = (R)0;
-        }
-        __syncthreads();
-#pragma unroll 1
-        for (int base = 0; base < pr.cnt; base += NE) {
-            const int idx = base + le;
-            const bool act = idx < pr.cnt;
-            const long long el = pr.eb + (act ? idx : 0);
-            R m[Q];
+    // the three components together: one gather of the patch's node values, one
+    // pass over the elements (m_q and the slots read once), one write-out
+    for (int u = tid; u < pr.U; u += blockDim.x) {
+        const long long g = pn[pr.pno + u];
 #pragma unroll
-            for (int k = 0; k < Q; ++k) m[k] = mq[el * Q3 + k * QQ + t];
-            for (int i = r; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
-            wave_sync();
+        for (int c = 0; c < 3; ++c) {
+            const long long gc = c * ncomp + g;
+            xs[3 * u + c] = (R)(x2 ? x[gc] + bt * x2[gc] : x[gc]);
+            acc[3 * u + c] = (R)0;
+        }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int base = 0; base < pr.cnt; base += NE) {
+        const int idx = base + le;
+        const bool act = idx < pr.cnt;
+        const long long el = pr.eb + (act ? idx : 0);
+        R m[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) m[k] = mq[el * Q3 + k * QQ + t];
+        for (int i = r; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
+        wave_sync();
+#pragma unroll 1
+        for (int c = 0; c < 3; ++c) {
             // x: thread (qx, iy = qy) from the node values in LDS
             R X[D];
 #pragma unroll
             for (int iz = 0; iz < D; ++iz) {
                 R a = 0;
 #pragma unroll
-                for (int ix = 0; ix < D; ++ix) a += rBx[ix] * xs[sSl[le][(iz * D + qyc) * D + ix]];
+                for (int ix = 0; ix < D; ++ix) a += rBx[ix] * xs[3 * sSl[le][(iz * D + qyc) * D + ix] + c];
                 X[iz] = a;
             }
             // y: thread (qx, qy) over the quad's node rows iy < D
@@ -1075,23 +1083,16 @@ k_mass_q4(const R *__restrict__ mq, const double *__restrict__ x,
 #pragma unroll
                 for (int j = 0; j < Q; ++j) rr += cBx[j] * v4[j];
                 if (act && qx < D && qy < D) {
-                    const int s = sSl[le][(iz * D + qy) * D + qx];
+                    const int s = 3 * sSl[le][(iz * D + qy) * D + qx] + c;
                     atomicAdd(&acc[s], rr);
                     if (DOT) dot += (double)rr * (double)xs[s];
                 }
             }
-            wave_sync();  // sSl is rewritten by the next pass
         }
-        __syncthreads();
-        for (int u = tid; u < pr.U; u += blockDim.x) {
-            const double av = (double)acc[u];
-            if (u < pr.P)
-                y[c * ncomp + pn[pr.pno + u]] = av;
-            else
-                part[3 * (long long)(pr.sho + u - pr.P) + c] = av;
-        }
-        __syncthreads();  // xs and acc are rewritten by the next component
+        wave_sync();  // sSl is rewritten by the next pass
     }
+    __syncthreads();
+    patch_write<UMAX>(acc, pr, pn, y, part, ncomp);
     if (DOT) {
         for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off);
         const int wl = tid & 63, wv = tid >> 6;
