@@ -139,7 +139,7 @@ __host__ __device__ constexpr int mass_lds(int D, int Q, int rs, int NW)
 {
     // at Q = 4 only the node values, the accumulator and the element slots
     return Q == 4 ? 6 * rs * patch_umax(D) + NW * 4 * 4 * D * D * D + 64
-                  : 2 * rs * patch_umax(D) + (NW * wave_ne(Q) + 1) * (4 * D * D * D + rs * (D * D * Q + D * Q * Q)) + 64;
+                  : 6 * rs * patch_umax(D) + (NW * wave_ne(Q) + 1) * (4 * D * D * D + rs * (D * D * Q + D * Q * Q)) + 64;
 }
 
 // One row of the patch table: first element, element count, offset of the

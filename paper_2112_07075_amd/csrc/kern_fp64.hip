@@ -811,10 +811,10 @@ k_force_pair(const R *__restrict__ S, const double *__restrict__ e, const double
 }
 
 // -------------------------------------------------------------- mass M_v x
-// y_c = R^T B^T diag(m_q) B R x_c, one patch per workgroup, one component at a
-// time: the patch's distinct-node values of x_c are read once into LDS, each
-// wave works through its own elements and sums into the patch's LDS slots,
-// and the component is written out before the next one starts. With DOT, the
+// y_c = R^T B^T diag(m_q) B R x_c, one patch per workgroup: the patch's
+// distinct-node values of the three components are read once into LDS, each
+// wave works through its own elements (m_q read once for the three) and sums
+// into the patch's LDS slots, then the patch is written out. With DOT, the
 // workgroup also writes sum_E x_E^T (M_E x_E) (= x^T M x over its elements).
 // With x2 the operand is x + beta x2, formed during the gather (a CG
 // iteration's new direction r + beta p, never stored by this kernel).
@@ -836,8 +836,8 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
     // CG flags and beta: one of each, or (with pmesh) one per mesh, sstride bytes apart
     const size_t soff = pmesh ? (size_t)pmesh[pi] * sstride : 0;
     if (skip && *(const int *)((const char *)skip + soff)) return;  // a finished CG solve
-    __shared__ R acc[UMAX];
-    __shared__ R xs[UMAX];
+    __shared__ R acc[3 * UMAX];
+    __shared__ R xs[3 * UMAX];
     __shared__ int sSl[NE + 1][D3];
     __shared__ R sX[NE + 1][D][D * Q];  // x-stage out, then y^T out
     __shared__ R sZ[NE + 1][D][QQ];
@@ -861,31 +861,37 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
     double dot = 0.0;
     const double bt = x2 ? *(const double *)((const char *)beta + soff) : 0.0;
 
-#pragma unroll 1
-    for (int c = 0; c < 3; ++c) {
-        for (int u = tid; u < pr.U; u += blockDim.x) {
-            const long long g = c * ncomp + pn[pr.pno + u];
-            xs[u] = (R)(x2 ? x[g] + bt * x2[g] : x[g]);
-            acc[u] = (R)0;
-        }
-        __syncthreads();
-#pragma unroll 1
-        for (int base = 0; base < pr.cnt; base += NE) {
-            const int idx = base + le;
-            const bool act = L.valid && idx < pr.cnt;
-            const long long el = pr.eb + (act ? idx : 0);
-            R m[Q];
+    // the three components together: one gather, one pass over the elements
+    // (m_q and the slots read once), one write-out
+    for (int u = tid; u < pr.U; u += blockDim.x) {
+        const long long g = pn[pr.pno + u];
 #pragma unroll
-            for (int k = 0; k < Q; ++k) m[k] = mq[el * Q3 + k * QQ + t];
-            for (int i = t; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
-            wave_sync();
+        for (int c = 0; c < 3; ++c) {
+            const long long gc = c * ncomp + g;
+            xs[3 * u + c] = (R)(x2 ? x[gc] + bt * x2[gc] : x[gc]);
+            acc[3 * u + c] = (R)0;
+        }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int base = 0; base < pr.cnt; base += NE) {
+        const int idx = base + le;
+        const bool act = L.valid && idx < pr.cnt;
+        const long long el = pr.eb + (act ? idx : 0);
+        R m[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) m[k] = mq[el * Q3 + k * QQ + t];
+        for (int i = t; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
+        wave_sync();
+#pragma unroll 1
+        for (int c = 0; c < 3; ++c) {
             // x-stage: thread (qx, iy = qy)
             if (qy < D) {
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
                     R a = 0;
 #pragma unroll
-                    for (int ix = 0; ix < D; ++ix) a += rBx[ix] * xs[sSl[le][(iz * D + qy) * D + ix]];
+                    for (int ix = 0; ix < D; ++ix) a += rBx[ix] * xs[3 * sSl[le][(iz * D + qy) * D + ix] + c];
                     sX[le][iz][qy * Q + qx] = a;
                 }
             }
@@ -929,7 +935,7 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
             if (act && qx < D && qy < D) {
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
-                    const int s = sSl[le][(iz * D + qy) * D + qx];
+                    const int s = 3 * sSl[le][(iz * D + qy) * D + qx] + c;
                     R r = 0;
 #pragma unroll
                     for (int k = 0; k < Q; ++k) r += cBx[k] * sX[le][iz][qy * Q + k];
@@ -937,18 +943,11 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
                     if (DOT) dot += (double)r * (double)xs[s];
                 }
             }
-            wave_sync();  // sSl and sX are rewritten by the next pass
+            wave_sync();  // sX is rewritten by the next component
         }
-        __syncthreads();
-        for (int u = tid; u < pr.U; u += blockDim.x) {
-            const double a = (double)acc[u];
-            if (u < pr.P)
-                y[c * ncomp + pn[pr.pno + u]] = a;
-            else
-                part[3 * (long long)(pr.sho + u - pr.P) + c] = a;
-        }
-        __syncthreads();  // xs and acc are rewritten by the next component
     }
+    __syncthreads();
+    patch_write<UMAX>(acc, pr, pn, y, part, ncomp);
     if (DOT) {
         for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off);
         const int lane = tid & 63, wv = tid >> 6;
