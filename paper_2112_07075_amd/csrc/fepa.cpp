@@ -114,6 +114,9 @@ struct fe_ctx {
     CgState *cg = nullptr;
     int *bad = nullptr;
     long long n_parts = 0;
+    // one mesh: the shared-node row of every node (-1: private or unreferenced),
+    // so the CG step reads shared Ap from the patch partials (no gather pass)
+    int32_t *node_sh = nullptr;
     // several meshes: one CG per mesh (chunked vectors, per-mesh scalars)
     bool multi = false;
     CgMulti cm;
@@ -747,6 +750,22 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
     // several meshes: chunks of at most kChunk DOFs inside one mesh and component,
     // ordered by mesh; each mesh's range of mass partials; the mesh of each partial
     ctx->multi = n_mesh > 1;
+    if (!ctx->multi) {
+        const MeshRec &r = ctx->units()[0];
+        std::vector<int32_t> nsh((size_t)ctx->N_tot, -1), shn((size_t)r.pd.n_shared);
+        if (r.pd.n_shared &&
+            hipMemcpy(shn.data(), r.pd.sh_node, shn.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+            ctx->err = "cannot read the shared-node list";
+            return bail(FE_EDEVICE);
+        }
+        for (size_t k = 0; k < shn.size(); ++k) nsh[(size_t)shn[k]] = (int32_t)k;
+        void *dp = nullptr;
+        if (upload(nsh.data(), nsh.size() * 4, &dp)) {
+            ctx->err = "CG workspace allocation failed";
+            return bail(FE_ENOMEM);
+        }
+        ctx->node_sh = (int32_t *)dp;
+    }
     if (ctx->multi) {
         std::vector<CgChunk> ch;
         std::vector<int> cbeg(n_mesh + 1), prange(2 * (size_t)n_mesh), pmesh((size_t)ctx->n_parts);
@@ -953,7 +972,7 @@ int fe_force_mult_pair(fe_ctx_t *ctx, const double *e, double *y, const double *
 // (x = r, x2 = p; beta and the done flag from the device CG state) and the
 // kernels leave partials of the operand's M-norm in ctx->part.
 static void mass_enqueue(fe_ctx *ctx, const double *x, double *y, bool lo, const double *x2,
-                         hipStream_t s, bool branch)
+                         hipStream_t s, bool branch, bool gather = true)
 {
     // one CG: its done flag; several meshes: all-done for the gathers, and each
     // patch's own mesh state in the mass kernel
@@ -979,7 +998,7 @@ static void mass_enqueue(fe_ctx *ctx, const double *x, double *y, bool lo, const
         else
             r.ks->mass(ctx->mq + r.mq_off, x, r.pd, y, ctx->N_tot, ctx->tabs + r.tab_slot, cg,
                        r.nw_mass, su);
-        launch_gather_shared(r.pd, y, ctx->N_tot, skip, su);
+        if (gather) launch_gather_shared(r.pd, y, ctx->N_tot, skip, su);
         launch_zero_nodes(r.orphans, r.n_orphans, y, ctx->N_tot, skip, su);
     });
 }
@@ -1019,12 +1038,18 @@ static int cg_run(fe_ctx *ctx, const double *b, double *x, double rel_tol, int m
     HIP_OK(hipGetLastError());
     // one iteration: Ap = M (r + beta p) with partials of its M-norm, then the
     // step kernels (alpha, the axpys and the new r.r, beta)
+    // one mesh: the step reads shared Ap from the partials, so the mass launch
+    // of an iteration skips the gather
+    const bool fused = !ctx->multi;
     auto step = [&](hipStream_t s) {
-        if (ctx->multi)
+        if (ctx->multi) {
             cgm_iterate(x, ctx->r, ctx->p, ctx->Ap, ctx->fr, ctx->cm, ctx->part, ctx->part2, s);
-        else
-            cg_step(x, ctx->r, ctx->p, ctx->Ap, ctx->fr, n, ctx->part, (int)ctx->n_parts, ctx->cg,
-                    ctx->part2, s);
+        } else {
+            const MeshRec &r = ctx->units()[0];
+            cg_step_shared(x, ctx->r, ctx->p, ctx->Ap, ctx->fr, ctx->N_tot, ctx->part,
+                           (int)ctx->n_parts, ctx->cg, ctx->part2, ctx->node_sh, r.pd.sh_ptr,
+                           r.pd.sh_idx, r.pd.part, s);
+        }
     };
     const bool graph = (ctx->opts.flags & FE_OPT_GRAPH) != 0;
     int batch = graph ? kGraphCgIters : 4;
@@ -1035,7 +1060,8 @@ static int cg_run(fe_ctx *ctx, const double *b, double *x, double rel_tol, int m
                 const int rc = run_graph(ctx, GraphKey{kActCg, x, nullptr, nullptr, lo ? 1 : 0},
                                          [&](hipStream_t s, bool branch) {
                                              for (int i = 0; i < kGraphCgIters; ++i) {
-                                                 mass_enqueue(ctx, ctx->r, ctx->Ap, lo, ctx->p, s, branch);
+                                                 mass_enqueue(ctx, ctx->r, ctx->Ap, lo, ctx->p, s, branch,
+                                                              !fused);
                                                  step(s);
                                              }
                                          });
@@ -1045,7 +1071,7 @@ static int cg_run(fe_ctx *ctx, const double *b, double *x, double rel_tol, int m
             for (int k = 0; k < batch; ++k) {
                 {
                     ScopedTimer tm(ctx, FE_TIMER_MASS);
-                    mass_enqueue(ctx, ctx->r, ctx->Ap, lo, ctx->p, ctx->st, false);
+                    mass_enqueue(ctx, ctx->r, ctx->Ap, lo, ctx->p, ctx->st, false, !fused);
                 }
                 step(ctx->st);
             }

@@ -135,6 +135,59 @@ __global__ void k_cg_step(double *__restrict__ x, double *__restrict__ r, double
     if (threadIdx.x == 0) part[blockIdx.x] = rr;
 }
 
+// The step of a one-mesh solve whose mass launch left the shared nodes as
+// patch partials (no gather pass): the step reads Ap of a shared node as the
+// sum of its partials in ascending patch order (the order of the gather it
+// replaces), node by node with the three components of a node in one thread.
+__global__ void k_cg_step_sh(double *__restrict__ x, double *__restrict__ r, double *__restrict__ p,
+                             const double *__restrict__ Ap, const unsigned char *__restrict__ fr,
+                             long long nn, const double *__restrict__ part_pap, int n_pap,
+                             const CgState *__restrict__ st, double *__restrict__ part,
+                             const int32_t *__restrict__ node_sh, const int32_t *__restrict__ sh_ptr,
+                             const int32_t *__restrict__ sh_idx, const double *__restrict__ shpart)
+{
+    __shared__ double sred[16];
+    __shared__ double s_alpha;
+    if (st->done) return;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n_pap; k += blockDim.x) s += part_pap[k];
+    s = block_sum(s, sred);
+    if (threadIdx.x == 0) s_alpha = st->rr / s;
+    __syncthreads();
+    const double alpha = s_alpha, beta = st->beta;
+    double rr = 0.0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < nn; g += stride) {
+        const int sh = node_sh[g];
+        double ap[3];
+        if (sh < 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ap[c] = Ap[c * nn + g];
+        } else {
+            ap[0] = ap[1] = ap[2] = 0.0;
+            for (int j = sh_ptr[sh]; j < sh_ptr[sh + 1]; ++j) {
+                const double *src = shpart + 3 * (long long)sh_idx[j];
+                ap[0] += src[0];
+                ap[1] += src[1];
+                ap[2] += src[2];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const long long i = c * nn + g;
+            const double ri = r[i];
+            const double pi = ri + beta * p[i];
+            p[i] = pi;
+            x[i] += alpha * pi;
+            const double rn = fr[i] ? ri - alpha * ap[c] : 0.0;
+            r[i] = rn;
+            rr += rn * rn;
+        }
+    }
+    rr = block_sum(rr, sred);
+    if (threadIdx.x == 0) part[blockIdx.x] = rr;
+}
+
 // One workgroup: the new r.r, beta = rr_new / rr, convergence and limit checks.
 __global__ void k_cg_beta(const double *__restrict__ part, int nparts, CgState *__restrict__ st)
 {
@@ -394,6 +447,16 @@ void cg_start(const double *b, const double *Ax, double *r, double *p, const uns
                        part_b);
     hipLaunchKernelGGL(k_cg_start_final, dim3(1), dim3(1024), 0, st, part_a, part_b, kVecBlocks,
                        state, rel_tol, max_iter);
+}
+
+void cg_step_shared(double *x, double *r, double *p, const double *Ap, const unsigned char *fr,
+                    long long nn, const double *part_pap, int n_pap, CgState *state, double *part,
+                    const int32_t *node_sh, const int32_t *sh_ptr, const int32_t *sh_idx,
+                    const double *shpart, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_step_sh, dim3(kVecBlocks), dim3(256), 0, st, x, r, p, Ap, fr, nn,
+                       part_pap, n_pap, state, part, node_sh, sh_ptr, sh_idx, shpart);
+    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1024), 0, st, part, kVecBlocks, state);
 }
 
 void cg_step(double *x, double *r, double *p, const double *Ap, const unsigned char *fr,

@@ -56,6 +56,13 @@ void cg_start(const double *b, const double *Ax, double *r, double *p, const uns
 void cg_step(double *x, double *r, double *p, const double *Ap, const unsigned char *fr,
              long long n, const double *part_pap, int n_pap, CgState *state, double *part,
              hipStream_t st);
+// The same step for one mesh whose mass launch skipped the shared-node gather:
+// Ap of a shared node is the sum of its patch partials (node_sh[g]: its row in
+// the shared-node lists sh_ptr/sh_idx over shpart, or -1); nn = nodes.
+void cg_step_shared(double *x, double *r, double *p, const double *Ap, const unsigned char *fr,
+                    long long nn, const double *part_pap, int n_pap, CgState *state, double *part,
+                    const int32_t *node_sh, const int32_t *sh_ptr, const int32_t *sh_idx,
+                    const double *shpart, hipStream_t st);
 void vec_sub_masked(const double *b, const double *Ax, const unsigned char *fr, double *out,
                     long long n, hipStream_t st);
 void vec_add(double *x, const double *d, long long n, hipStream_t st);
