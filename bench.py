@@ -50,8 +50,8 @@ HBM_PEAK_GBS = 8000.0
 # SHA-256 prefixes of the kernel sources and tile table they were taken with:
 # reported only while those are unchanged (profiles/c2_fp64_step.md).
 TRAFFIC = {
-    ("c2", "fp64"): {"action": "pair", "kernel": "k_force_pair<3,4,ONE,double,4>", "bytes": 611.4e6,
-                     "src": {"kern_fp64.hip": "67f5d211ca27158f", "kern_common.hpp": "ae771032f592f9ca",
+    ("c2", "fp64"): {"action": "pair", "kernel": "k_force_pair<3,4,ONE,double,4>", "bytes": 611.2e6,
+                     "src": {"kern_fp64.hip": "86e914a3fd0d9e90", "kern_common.hpp": "7929ca9fa00e3092",
                              "tune_table.inc": "21aa53fe79937d0b"}},
 }
 
@@ -229,17 +229,19 @@ class Runner:
         t.cuda.synchronize()
         step_s = (time.perf_counter() - t0) / steps
         per = {}
-        for name, which in (("qdata", fe.FE_TIMER_QDATA), ("pair", fe.FE_TIMER_PAIR),
-                            ("mass", fe.FE_TIMER_MASS)):
+        for name, which in (("qdata", fe.FE_TIMER_QDATA), ("pair", fe.FE_TIMER_PAIR)):
             ms, cnt = fe.fe_timer_read(self.ctx, which)
             per[name] = (ms / cnt if cnt else float("nan"), ms)
-        # the single actions, timed once each after the steps (not part of a step)
+        # the single actions and the mass action, timed after the steps (not part
+        # of a step; inside the step the CG's mass launches run in graphs)
         fe.fe_timer_reset(self.ctx)
         for _ in range(10):
             fe.fe_force_mult(self.ctx, None, self.y)
             fe.fe_force_mult_T(self.ctx, self.v, self.z)
+            fe.fe_mass_mult(self.ctx, self.v, self.a)
         t.cuda.synchronize()
-        for name, which in (("force_1", fe.FE_TIMER_FORCE), ("force_T", fe.FE_TIMER_FORCE_T)):
+        for name, which in (("force_1", fe.FE_TIMER_FORCE), ("force_T", fe.FE_TIMER_FORCE_T),
+                            ("mass", fe.FE_TIMER_MASS)):
             ms, cnt = fe.fe_timer_read(self.ctx, which)
             per[name] = (ms / cnt if cnt else float("nan"), ms)
         return step_s, per
@@ -299,8 +301,10 @@ def main():
     meshes, qs, fields, label = build_workload(args.config, W)
     E = sum(m.n_elem for m in meshes)
     N = sum(m.n_nodes for m in meshes)
-    base = fe.FE_OPT_TIMERS
-    flags = base | (fe.FE_OPT_BATCHED | fe.FE_OPT_GRAPH if args.config == "c5" else 0)
+    # every action and every group of 8 CG iterations is replayed from a captured
+    # hipGraph (the CG is launch-bound: three short kernels per iteration)
+    base = fe.FE_OPT_TIMERS | fe.FE_OPT_GRAPH
+    flags = base | (fe.FE_OPT_BATCHED if args.config == "c5" else 0)
     run = Runner(torch, fe, W, meshes, qs, fields,
                  fe.Opts(precision=PRECISIONS[args.precision], flags=flags))
     step_s, per = run.time(args.steps, args.warmup)
@@ -340,7 +344,7 @@ def main():
                         f" fused) + mass CG to 1e-12",
             "meshes": len(meshes), "elements": E, "h1_dofs": 3 * N, "order": order,
             "precision": args.precision, "parallelism": "single GPU",
-            "launch": "batched + hipGraph" if args.config == "c5" else "plain",
+            "launch": "batched + hipGraph" if args.config == "c5" else "hipGraph replay",
         },
         "kernels_us": {k: round(vv[0] * 1e3, 2) for k, vv in per.items()},
         "kernels_gbs": {k: round(ab[k] / (per[k][0] * 1e-3) / 1e9, 1) for k in per},
@@ -362,7 +366,7 @@ def main():
         # the same step as per-mesh launches of the plain path (one context, no batching)
         del run
         torch.cuda.empty_cache()
-        plain = Runner(torch, fe, W, meshes, qs, fields, fe.Opts(flags=base))
+        plain = Runner(torch, fe, W, meshes, qs, fields, fe.Opts(flags=fe.FE_OPT_TIMERS))
         p_step, p_per = plain.time(max(1, args.steps // 2), 1)
         out["per_mesh_plain"] = {"value": 3 * N * 2 * N_PAIRS / p_step / 1e9,
                                  "ms_per_step": p_step * 1e3,
