@@ -332,3 +332,27 @@ def test_unreferenced_node_gets_zero(torch_cuda):
     M = c.mesh.elem_nodes
     assert rel_cw(y[:, :-1], O.force_mult(M, 2, 4, c.N, qd["S"]),
                   O.force_mult(M, 2, 4, c.N, qd["S"], absmode=True)) < TOL
+
+
+@pytest.mark.parametrize("ess", [False, True])
+def test_mass_cg_graph_replay_matches_oracle(torch_cuda, ess):
+    """One-mesh CG replayed from captured 8-iteration graphs (the step kernel sums
+    the shared-node partials itself): two solves in a row, the second replaying
+    the graphs, both against the oracle's solution."""
+    c = make_case(4, 2, 4, seed=16)
+    g = GpuRun(torch_cuda, c, flags=fe.FE_OPT_GRAPH)
+    mq = oracle_qdata(c)["mq"]
+    rng = np.random.default_rng(17)
+    xs = rng.standard_normal((3, c.N))
+    ess_idx = W.boundary_normal_dofs(c.mesh) if ess else None
+    if ess:
+        xs.ravel()[ess_idx] = 0.0
+    b = dev(torch_cuda, O.mass_mult(c.mesh.elem_nodes, 2, 4, c.N, mq, xs))
+    ess_t = None if ess_idx is None else dev(torch_cuda, ess_idx)
+    xg = torch_cuda.zeros((3, c.N), dtype=torch_cuda.float64, device="cuda")
+    for rep in range(2):
+        xg.zero_()
+        rc, it, rr = fe.fe_mass_cg(g.ctx, b, xg, ess_t, rel_tol=1e-12)
+        assert rc == fe.FE_OK and rr < 2e-12, (rep, rr)
+        xh = xg.cpu().numpy()
+        assert np.linalg.norm(xh - xs) < 1e-9 * np.linalg.norm(xs), rep
