@@ -317,7 +317,7 @@ def main():
         rs = 4 if args.precision == "fp32" else 2
         for m, Q in zip(meshes, qs):
             S = 9 * Q ** 3 * m.n_elem
-            for k in ("force_1", "force_e", "force_T", "qdata"):
+            for k in ("force_1", "force_e", "force_T", "pair", "qdata"):
                 ab[k] -= S * (8 - rs)
             ab["mass"] -= Q ** 3 * m.n_elem * 4  # m_q in FP32 (both forms)
     if per["pair"][1] == 0.0:  # a form without the fused kernel runs the two actions

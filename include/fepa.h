@@ -203,8 +203,11 @@ int fe_force_mult_T(fe_ctx_t *ctx, const double *v, double *z);
  * S = w detJ sigma J^-T and the Lagrange step needs both at every stage (the
  * momentum and energy equations of Sec. 3.3), so the library reads S once.
  * Same layouts and ownership as the two single calls; y, z must not overlap
- * each other or the inputs (FE_EINVAL). Under FE_PREC_BF16 the two single
- * actions run one after the other. Asynchronous.
+ * each other or the inputs (FE_EINVAL). Under FE_PREC_BF16 the fused kernel
+ * reads the BF16 S and contracts in FP32 (y may then differ from the single
+ * call's MFMA result by the BF16 rounding of the basis table). Where the tile
+ * table measured the two single kernels faster, they run one after the
+ * other. Asynchronous.
  */
 int fe_force_mult_pair(fe_ctx_t *ctx, const double *e, double *y, const double *v, double *z);
 

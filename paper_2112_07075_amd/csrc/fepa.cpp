@@ -945,10 +945,6 @@ int fe_force_mult_pair(fe_ctx_t *ctx, const double *e, double *y, const double *
     for (const void *i : in)
         for (const void *o : out)
             if (i && i == o) return fail(ctx, FE_EINVAL, "input aliases output%s");
-    if (ctx->bf) {  // the BF16 form has no fused kernel: its two actions
-        int rc = fe_force_mult(ctx, e, y);
-        return rc ? rc : fe_force_mult_T(ctx, v, z);
-    }
     ScopedTimer tm(ctx, FE_TIMER_PAIR);
     return run_graph(ctx, GraphKey{kActPair, e, y, v, 0, z}, [&](hipStream_t s, bool branch) {
         enqueue_units(ctx, s, branch, [&](const MeshRec &r, hipStream_t su) {

@@ -35,16 +35,17 @@ __global__ void k_fill(double *__restrict__ y, long long n, double val)
 // per workgroup. Three H1 contraction stages per component with the three
 // derivative terms fused: z-stage -> (B, B, G), y-stage -> (B | G + B),
 // x-stage -> (G + B); element results are summed into the patch's LDS slots.
-template <int D, int Q, bool ONE, typename R, int NW>
+template <int D, int Q, bool ONE, typename R, int NW, typename RS = R>
 __global__ void __launch_bounds__(NW * 64)
-k_force(const R *__restrict__ S, const double *__restrict__ e,
+k_force(const RS *__restrict__ S, const double *__restrict__ e,
         const int32_t *__restrict__ perm, const uint16_t *__restrict__ slot,
         const int32_t *__restrict__ pn, const int32_t *__restrict__ ptab,
         double *__restrict__ y, double *__restrict__ part, long long ncomp,
         const R *__restrict__ tab)
 {
     constexpr int NE = NW * wave_ne(Q), UMAX = patch_umax(D);
-    constexpr int DL = D - 1, QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D, DL3 = DL * DL * DL;
+    constexpr int DL = D - 1, QQ = Q * Q, D3 = D * D * D, DL3 = DL * DL * DL;
+    constexpr int SQ = s_stride<RS>(Q);  // points per stored (c, d) row
     using T = Tab<D, Q>;
     __shared__ R acc[3 * UMAX];
     __shared__ R sA[NE + 1][3][D][QQ];
@@ -71,11 +72,11 @@ k_force(const R *__restrict__ S, const double *__restrict__ e,
     R sv[3][Q], sn[3][Q];
     {
         const bool act0 = L.valid && le < pr.cnt;
-        const R *__restrict__ S0 = S + (long long)(pr.eb + (act0 ? le : 0)) * 9 * Q3 + t;
+        const RS *__restrict__ S0 = S + (long long)(pr.eb + (act0 ? le : 0)) * 9 * SQ + t;
 #pragma unroll
         for (int d = 0; d < 3; ++d)
 #pragma unroll
-            for (int qz = 0; qz < Q; ++qz) sv[d][qz] = __builtin_nontemporal_load(S0 + d * Q3 + qz * QQ);
+            for (int qz = 0; qz < Q; ++qz) sv[d][qz] = (R)__builtin_nontemporal_load(S0 + d * SQ + qz * QQ);
     }
 #pragma unroll 1
     for (int base = 0; base < pr.cnt; base += NE) {
@@ -83,8 +84,8 @@ k_force(const R *__restrict__ S, const double *__restrict__ e,
         const bool act = L.valid && idx < pr.cnt;
         const long long el = pr.eb + (act ? idx : 0);
         const bool actn = L.valid && idx + NE < pr.cnt;
-        const R *__restrict__ Sc = S + el * 9 * Q3 + t;
-        const R *__restrict__ Sn = S + (long long)(pr.eb + (actn ? idx + NE : 0)) * 9 * Q3 + t;
+        const RS *__restrict__ Sc = S + el * 9 * SQ + t;
+        const RS *__restrict__ Sn = S + (long long)(pr.eb + (actn ? idx + NE : 0)) * 9 * SQ + t;
         int sl[D];
         const int qxc = qx < D ? qx : D - 1, qyc = qy < D ? qy : D - 1;
 #pragma unroll
@@ -123,7 +124,7 @@ k_force(const R *__restrict__ S, const double *__restrict__ e,
             for (int d = 0; d < 3; ++d)
 #pragma unroll
                 for (int qz = 0; qz < Q; ++qz)
-                    sn[d][qz] = __builtin_nontemporal_load((c < 2 ? Sc + (c + 1) * 3 * Q3 : Sn) + d * Q3 + qz * QQ);
+                    sn[d][qz] = (R)__builtin_nontemporal_load((c < 2 ? Sc + (c + 1) * 3 * SQ : Sn) + d * SQ + qz * QQ);
             R a0[D], a1[D], a2[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) a0[i] = a1[i] = a2[i] = 0.0;
@@ -215,16 +216,17 @@ __device__ __forceinline__ float dpp_r(float v)
 constexpr int kQuadBcast0 = 0x00, kQuadBcast1 = 0x55, kQuadBcast2 = 0xAA, kQuadBcast3 = 0xFF;
 constexpr int kRowRor4 = 0x124, kRowRor8 = 0x128, kRowRor12 = 0x12C;
 
-template <int D, bool ONE, typename R, int NW>
+template <int D, bool ONE, typename R, int NW, typename RS = R>
 __global__ void __launch_bounds__(NW * 64)
-k_force_q4(const R *__restrict__ S, const double *__restrict__ e,
+k_force_q4(const RS *__restrict__ S, const double *__restrict__ e,
            const int32_t *__restrict__ perm, const uint16_t *__restrict__ slot,
            const int32_t *__restrict__ pn, const int32_t *__restrict__ ptab,
            double *__restrict__ y, double *__restrict__ part, long long ncomp,
            const R *__restrict__ tab)
 {
     constexpr int Q = 4, NE = NW * 4, UMAX = patch_umax(D);
-    constexpr int DL = D - 1, QQ = 16, Q3 = 64, D3 = D * D * D, DL3 = DL * DL * DL;
+    constexpr int DL = D - 1, QQ = 16, D3 = D * D * D, DL3 = DL * DL * DL;
+    constexpr int SQ = s_stride<RS>(Q);  // points per stored (c, d) row
     using T = Tab<D, Q>;
     __shared__ R acc[3 * UMAX];
 
@@ -261,11 +263,11 @@ k_force_q4(const R *__restrict__ S, const double *__restrict__ e,
     R sv[3][Q], sn[3][Q];
     {
         const bool act0 = le < pr.cnt;
-        const R *__restrict__ S0 = S + (long long)(pr.eb + (act0 ? le : 0)) * 9 * Q3 + t;
+        const RS *__restrict__ S0 = S + (long long)(pr.eb + (act0 ? le : 0)) * 9 * SQ + t;
 #pragma unroll
         for (int d = 0; d < 3; ++d)
 #pragma unroll
-            for (int qz = 0; qz < Q; ++qz) sv[d][qz] = __builtin_nontemporal_load(S0 + d * Q3 + qz * QQ);
+            for (int qz = 0; qz < Q; ++qz) sv[d][qz] = (R)__builtin_nontemporal_load(S0 + d * SQ + qz * QQ);
     }
 #pragma unroll 1
     for (int base = 0; base < pr.cnt; base += NE) {
@@ -273,8 +275,8 @@ k_force_q4(const R *__restrict__ S, const double *__restrict__ e,
         const bool act = idx < pr.cnt;
         const long long el = pr.eb + (act ? idx : 0);
         const bool actn = idx + NE < pr.cnt;
-        const R *__restrict__ Sc = S + el * 9 * Q3 + t;
-        const R *__restrict__ Sn = S + (long long)(pr.eb + (actn ? idx + NE : 0)) * 9 * Q3 + t;
+        const RS *__restrict__ Sc = S + el * 9 * SQ + t;
+        const RS *__restrict__ Sn = S + (long long)(pr.eb + (actn ? idx + NE : 0)) * 9 * SQ + t;
         // lanes past the element count or outside the D x D node columns load a
         // valid neighbour's data and never store (loads without branches)
         int sl[D];
@@ -315,7 +317,7 @@ k_force_q4(const R *__restrict__ S, const double *__restrict__ e,
             for (int d = 0; d < 3; ++d)
 #pragma unroll
                 for (int qz = 0; qz < Q; ++qz)
-                    sn[d][qz] = __builtin_nontemporal_load((c < 2 ? Sc + (c + 1) * 3 * Q3 : Sn) + d * Q3 + qz * QQ);
+                    sn[d][qz] = (R)__builtin_nontemporal_load((c < 2 ? Sc + (c + 1) * 3 * SQ : Sn) + d * SQ + qz * QQ);
             // z in registers
             R a0[D], a1[D], a2[D];
 #pragma unroll
@@ -379,7 +381,7 @@ k_force_t(const RS *__restrict__ S, const double *__restrict__ v,
           double *__restrict__ z, long long ncomp, const R *__restrict__ tab)
 {
     constexpr int NE = NW * wave_ne(Q), UMAX = patch_umax(D);
-    constexpr int DL = D - 1, QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D, DL3 = DL * DL * DL;
+    constexpr int DL = D - 1, QQ = Q * Q, D3 = D * D * D, DL3 = DL * DL * DL;
     using T = Tab<D, Q>;
     __shared__ R vs[3 * UMAX];
     __shared__ int sSl[NE + 1][D3];
@@ -512,18 +514,19 @@ k_force_t(const RS *__restrict__ S, const double *__restrict__ v,
 // runs the F e contraction of c, then the F^T v contraction of c, while the
 // next component's S loads. At Q = 4 the y and x stages of F e run across
 // lanes as in k_force_q4.
-template <int D, int Q, bool ONE, typename R, int NW>
+template <int D, int Q, bool ONE, typename R, int NW, typename RS = R>
 __global__ void __launch_bounds__(NW * 64)
-k_force_pair(const R *__restrict__ S, const double *__restrict__ e, const double *__restrict__ v,
+k_force_pair(const RS *__restrict__ S, const double *__restrict__ e, const double *__restrict__ v,
              const int32_t *__restrict__ perm, const uint16_t *__restrict__ slot,
              const int32_t *__restrict__ pn, const int32_t *__restrict__ ptab,
              double *__restrict__ y, double *__restrict__ part, double *__restrict__ z,
              long long ncomp, const R *__restrict__ tab)
 {
     constexpr int NE = NW * wave_ne(Q), UMAX = patch_umax(D);
-    constexpr int DL = D - 1, QQ = Q * Q, Q3 = Q * Q * Q, D3 = D * D * D, DL3 = DL * DL * DL;
+    constexpr int DL = D - 1, QQ = Q * Q, D3 = D * D * D, DL3 = DL * DL * DL;
     constexpr bool LANES = Q == 4;
     constexpr int NA = LANES ? 1 : NE + 1;  // F e staging (unused across lanes)
+    constexpr int SQ = s_stride<RS>(Q);  // points per stored (c, d) row
     using T = Tab<D, Q>;
     __shared__ R acc[3 * UMAX];
     __shared__ R vs[3 * UMAX];
@@ -597,12 +600,12 @@ k_force_pair(const R *__restrict__ S, const double *__restrict__ e, const double
     R sv[3][Q], sn[3][Q];
     {
         const bool act0 = valid && le < pr.cnt;
-        const R *__restrict__ S0 = S + (long long)(pr.eb + (act0 ? le : 0)) * 9 * Q3 + t;
+        const RS *__restrict__ S0 = S + (long long)(pr.eb + (act0 ? le : 0)) * 9 * SQ + t;
 #pragma unroll
         for (int d = 0; d < 3; ++d)
 #pragma unroll
             for (int qz = 0; qz < Q; ++qz)
-                sv[d][qz] = __builtin_nontemporal_load(S0 + d * Q3 + qz * QQ);
+                sv[d][qz] = (R)__builtin_nontemporal_load(S0 + d * SQ + qz * QQ);
     }
 #pragma unroll 1
     for (int base = 0; base < pr.cnt; base += NE) {
@@ -610,8 +613,8 @@ k_force_pair(const R *__restrict__ S, const double *__restrict__ e, const double
         const bool act = valid && idx < pr.cnt;
         const long long el = pr.eb + (act ? idx : 0);
         const bool actn = valid && idx + NE < pr.cnt;
-        const R *__restrict__ Sc = S + el * 9 * Q3 + t;
-        const R *__restrict__ Sn = S + (long long)(pr.eb + (actn ? idx + NE : 0)) * 9 * Q3 + t;
+        const RS *__restrict__ Sc = S + el * 9 * SQ + t;
+        const RS *__restrict__ Sn = S + (long long)(pr.eb + (actn ? idx + NE : 0)) * 9 * SQ + t;
         for (int i = t; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
         R eq[Q];
         if (ONE) {
@@ -652,7 +655,7 @@ k_force_pair(const R *__restrict__ S, const double *__restrict__ e, const double
             for (int d = 0; d < 3; ++d)
 #pragma unroll
                 for (int qz = 0; qz < Q; ++qz)
-                    sn[d][qz] = __builtin_nontemporal_load((c < 2 ? Sc + (c + 1) * 3 * Q3 : Sn) + d * Q3 + qz * QQ);
+                    sn[d][qz] = (R)__builtin_nontemporal_load((c < 2 ? Sc + (c + 1) * 3 * SQ : Sn) + d * SQ + qz * QQ);
             // ---- F e, component c: z in registers
             R a0[D], a1[D], a2[D];
 #pragma unroll
@@ -1518,9 +1521,35 @@ static const KernelSet *kernels_for(int p, int Q)
 
 const KernelSet *fp64_kernels(int p, int Q) { return kernels_for<double>(p, Q); }
 
-// BF16 form: F^T v reads BF16 S with FP32 contractions; qdata writes BF16 S.
+// BF16 form: F^T v and the fused pair read BF16 S with FP32 contractions;
+// qdata writes BF16 S. (The single F e runs on MFMA, kern_bf16.hip.)
 template <int D, int Q>
 struct LaunchBf16 {
+    template <int NW>
+    static void force_pair_nw(const void *S, const double *e, const double *v, const PatchDev &pd,
+                              double *y, double *z, long long ncomp, const void *tab, hipStream_t st)
+    {
+        const dim3 grid(pd.n_patch), block(NW * 64);
+        if (e)
+            hipLaunchKernelGGL((k_force_pair<D, Q, false, float, NW, __bf16>), grid, block, 0, st,
+                               (const __bf16 *)S, e, v, pd.perm, pd.slot, pd.pn, pd.ptab, y, pd.part, z,
+                               ncomp, (const float *)tab);
+        else
+            hipLaunchKernelGGL((k_force_pair<D, Q, true, float, NW, __bf16>), grid, block, 0, st,
+                               (const __bf16 *)S, e, v, pd.perm, pd.slot, pd.pn, pd.ptab, y, pd.part, z,
+                               ncomp, (const float *)tab);
+    }
+    static void force_pair(const void *S, const double *e, const double *v, const PatchDev &pd,
+                           double *y, double *z, long long ncomp, const void *tab, int nw,
+                           hipStream_t st)
+    {
+        if constexpr (force_pair_lds(D, Q, 4, 8) <= kLdsMax)
+            if (nw >= 8) return force_pair_nw<8>(S, e, v, pd, y, z, ncomp, tab, st);
+        if constexpr (force_pair_lds(D, Q, 4, 4) <= kLdsMax)
+            if (nw >= 4) return force_pair_nw<4>(S, e, v, pd, y, z, ncomp, tab, st);
+        static_assert(force_pair_lds(D, Q, 4, 2) <= kLdsMax, "the 2-wave pair kernel must fit LDS");
+        return force_pair_nw<2>(S, e, v, pd, y, z, ncomp, tab, st);
+    }
     template <int NW>
     static void force_t_nw(const void *S, const double *v, const PatchDev &pd, double *z,
                            long long ncomp, const void *tab, hipStream_t st)
@@ -1556,7 +1585,7 @@ bool bf16_parts(int p, int Q, KernelSet *ks)
     if (p == P && Q == QQ) {                                \
         ks->force_t = LaunchBf16<P + 1, QQ>::force_t;       \
         ks->qdata = LaunchBf16<P + 1, QQ>::qdata;           \
-        ks->force_pair = nullptr;                           \
+        ks->force_pair = LaunchBf16<P + 1, QQ>::force_pair; \
         return true;                                        \
     }
     FEPA_PQ_LIST(FEPA_ENTRY)
