@@ -48,11 +48,15 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by a plain 1 GiB copy (fetch x2, write x1), and the
 # SHA-256 prefixes of the kernel sources and tile table they were taken with:
-# reported only while those are unchanged (profiles/c2_fp64_step.md).
+# reported only while those are unchanged (profiles/c2_fp64_step.md,
+# profiles/c4_step.md).
 TRAFFIC = {
-    ("c2", "fp64"): {"action": "pair", "kernel": "k_force_pair<3,4,ONE,double,4>", "bytes": 611.2e6,
-                     "src": {"kern_fp64.hip": "86e914a3fd0d9e90", "kern_common.hpp": "7929ca9fa00e3092",
-                             "tune_table.inc": "21aa53fe79937d0b"}},
+    ("c2", "fp64"): {"action": "pair", "kernel": "k_force_pair<3,4,ONE,double,4>", "bytes": 611.3e6,
+                     "src": {"kern_fp64.hip": "3d1dc536f9ef19be", "kern_common.hpp": "7929ca9fa00e3092",
+                             "tune_table.inc": "da1065314c46e33b"}},
+    ("c4", "fp64"): {"action": "pair", "kernel": "k_force_pair<4,5,ONE,double,4>", "bytes": 3351.3e6,
+                     "src": {"kern_fp64.hip": "3d1dc536f9ef19be", "kern_common.hpp": "7929ca9fa00e3092",
+                             "tune_table.inc": "da1065314c46e33b"}},
 }
 
 
