@@ -123,12 +123,13 @@ __host__ __device__ constexpr int force_lds(int D, int Q, int rs, int NW)
     return Q == 4 ? 3 * rs * patch_umax(D)
                   : 3 * rs * patch_umax(D) + (NW * wave_ne(Q) + 1) * rs * (3 * D * Q * Q + 2 * D * D * Q);
 }
-// F e and F^T v in one kernel: both accumulator/node tables and both stagings
+// F e and F^T v in one kernel: both accumulator/node tables, the element
+// slots and (except at Q = 4, where the stages run across lanes) both stagings
 __host__ __device__ constexpr int force_pair_lds(int D, int Q, int rs, int NW)
 {
-    return 6 * rs * patch_umax(D) +
-           (NW * wave_ne(Q) + 1) * (4 * D * D * D + rs * (2 * D * D * Q + (D - 1) * Q * Q + (D - 1) * (D - 1) * Q)) +
-           (Q == 4 ? 1 : NW * wave_ne(Q) + 1) * rs * (3 * D * Q * Q + 2 * D * D * Q);
+    return 6 * rs * patch_umax(D) + (NW * wave_ne(Q) + 1) * 4 * D * D * D +
+           (Q == 4 ? 1 : NW * wave_ne(Q) + 1) *
+               rs * (2 * D * D * Q + (D - 1) * Q * Q + (D - 1) * (D - 1) * Q + 3 * D * Q * Q + 2 * D * D * Q);
 }
 __host__ __device__ constexpr int force_t_lds(int D, int Q, int rs, int NW)
 {

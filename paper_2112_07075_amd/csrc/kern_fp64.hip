@@ -525,15 +525,15 @@ k_force_pair(const RS *__restrict__ S, const double *__restrict__ e, const doubl
     constexpr int NE = NW * wave_ne(Q), UMAX = patch_umax(D);
     constexpr int DL = D - 1, QQ = Q * Q, D3 = D * D * D, DL3 = DL * DL * DL;
     constexpr bool LANES = Q == 4;
-    constexpr int NA = LANES ? 1 : NE + 1;  // F e staging (unused across lanes)
+    constexpr int NA = LANES ? 1 : NE + 1;  // staging of the LDS-staged stages (unused across lanes)
     constexpr int SQ = s_stride<RS>(Q);  // points per stored (c, d) row
     using T = Tab<D, Q>;
     __shared__ R acc[3 * UMAX];
     __shared__ R vs[3 * UMAX];
     __shared__ int sSl[NE + 1][D3];
-    __shared__ R sX[NE + 1][2][D][D * Q];
-    __shared__ R sT[NE + 1][DL][QQ];
-    __shared__ R sT2[NE + 1][DL][DL * Q];
+    __shared__ R sX[NA][2][D][D * Q];
+    __shared__ R sT[NA][DL][QQ];
+    __shared__ R sT2[NA][DL][DL * Q];
     __shared__ R sA[NA][3][D][QQ];
     __shared__ R sC[NA][2][D][D * Q];
 
@@ -570,12 +570,17 @@ k_force_pair(const RS *__restrict__ S, const double *__restrict__ e, const doubl
         cBy[k] = qy < D ? tab[T::B + k * D + qy] : (R)0;
         cGy[k] = qy < D ? tab[T::G + k * D + qy] : (R)0;
     }
+    // F^T v across lanes: L2 weights of the point row qy, and of the rotated
+    // source columns for the x stage
+    R cLy[LANES ? Q : 1], cLx[LANES ? Q : 1];
     if constexpr (LANES) {
         const int kx[Q] = {qx, dpp_i<kRowRor4>(qx), dpp_i<kRowRor8>(qx), dpp_i<kRowRor12>(qx)};
 #pragma unroll
         for (int j = 0; j < Q; ++j) {
             cBx[j] = qx < D ? tab[T::B + kx[j] * D + qx] : (R)0;
             cGx[j] = qx < D ? tab[T::G + kx[j] * D + qx] : (R)0;
+            cLx[j] = qx < DL ? tab[T::BL + kx[j] * DL + qx] : (R)0;
+            cLy[j] = qy < DL ? tab[T::BL + j * DL + qy] : (R)0;
         }
     } else {
 #pragma unroll
@@ -645,6 +650,18 @@ k_force_pair(const RS *__restrict__ S, const double *__restrict__ e, const doubl
             }
         }
         wave_sync();  // the element's slots are in LDS
+        // across lanes: 3 x the LDS slots this thread reads (nodes (ix, row
+        // qy, iz)) and adds to (node (qx, qy, iz)), for all three components
+        int sx[LANES ? D * D : 1], so[LANES ? D : 1];
+        if constexpr (LANES) {
+            const int qyc = qy < D ? qy : D - 1, qxc = qx < D ? qx : D - 1;
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) {
+#pragma unroll
+                for (int ix = 0; ix < D; ++ix) sx[iz * D + ix] = 3 * sSl[le][(iz * D + qyc) * D + ix];
+                so[iz] = 3 * sSl[le][(iz * D + qyc) * D + qxc];
+            }
+        }
         R sf[Q];      // F^T v: S : grad v at the column's points
 #pragma unroll
         for (int k = 0; k < Q; ++k) sf[k] = 0.0;
@@ -693,8 +710,7 @@ k_force_pair(const RS *__restrict__ S, const double *__restrict__ e, const doubl
                     R rr = 0.0;
 #pragma unroll
                     for (int j = 0; j < Q; ++j) rr += cGx[j] * w0[j] + cBx[j] * w1[j];
-                    if (act && qx < D && qy < D)
-                        atomicAdd(&acc[3 * sSl[le][(iz * D + qy) * D + qx] + c], rr);
+                    if (act && qx < D && qy < D) atomicAdd(&acc[so[iz] + c], rr);
                 }
             } else {
 #pragma unroll
@@ -729,38 +745,68 @@ k_force_pair(const RS *__restrict__ S, const double *__restrict__ e, const doubl
                     }
                 }
             }
-            // ---- F^T v, component c: x-stage, thread (qx, iy = qy)
-            if (qy < D) {
+            // ---- F^T v, component c
+            R vx[D], vy[D], vz[D];
+            if constexpr (LANES) {
+                // x-stage: thread (qx, iy = qy) from the node values; y-stage
+                // over the quad's node rows
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
                     R ub = 0.0, ug = 0.0;
 #pragma unroll
                     for (int ix = 0; ix < D; ++ix) {
-                        const R u = vs[3 * sSl[le][(iz * D + qy) * D + ix] + c];
+                        const R u = vs[sx[iz * D + ix] + c];
                         ub += rBx[ix] * u;
                         ug += rGx[ix] * u;
                     }
-                    sX[le][0][iz][qy * Q + qx] = ub;
-                    sX[le][1][iz][qy * Q + qx] = ug;
-                }
-            }
-            wave_sync();
-            R vx[D], vy[D], vz[D];
+                    const R bb[Q] = {dpp_r<kQuadBcast0>(ub), dpp_r<kQuadBcast1>(ub),
+                                     dpp_r<kQuadBcast2>(ub), dpp_r<kQuadBcast3>(ub)};
+                    const R bg[Q] = {dpp_r<kQuadBcast0>(ug), dpp_r<kQuadBcast1>(ug),
+                                     dpp_r<kQuadBcast2>(ug), dpp_r<kQuadBcast3>(ug)};
+                    R a = 0.0, b = 0.0, cc = 0.0;
 #pragma unroll
-            for (int iz = 0; iz < D; ++iz) {
-                R a = 0.0, b = 0.0, cc = 0.0;
-#pragma unroll
-                for (int iy = 0; iy < D; ++iy) {
-                    const R ub = sX[le][0][iz][iy * Q + qx], ug = sX[le][1][iz][iy * Q + qx];
-                    a += rBy[iy] * ug;
-                    b += rGy[iy] * ub;
-                    cc += rBy[iy] * ub;
+                    for (int iy = 0; iy < D; ++iy) {
+                        a += rBy[iy] * bg[iy];
+                        b += rGy[iy] * bb[iy];
+                        cc += rBy[iy] * bb[iy];
+                    }
+                    vx[iz] = a;
+                    vy[iz] = b;
+                    vz[iz] = cc;
                 }
-                vx[iz] = a;
-                vy[iz] = b;
-                vz[iz] = cc;
+            } else {
+                // x-stage, thread (qx, iy = qy)
+                if (qy < D) {
+#pragma unroll
+                    for (int iz = 0; iz < D; ++iz) {
+                        R ub = 0.0, ug = 0.0;
+#pragma unroll
+                        for (int ix = 0; ix < D; ++ix) {
+                            const R u = vs[3 * sSl[le][(iz * D + qy) * D + ix] + c];
+                            ub += rBx[ix] * u;
+                            ug += rGx[ix] * u;
+                        }
+                        sX[le][0][iz][qy * Q + qx] = ub;
+                        sX[le][1][iz][qy * Q + qx] = ug;
+                    }
+                }
+                wave_sync();
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) {
+                    R a = 0.0, b = 0.0, cc = 0.0;
+#pragma unroll
+                    for (int iy = 0; iy < D; ++iy) {
+                        const R ub = sX[le][0][iz][iy * Q + qx], ug = sX[le][1][iz][iy * Q + qx];
+                        a += rBy[iy] * ug;
+                        b += rGy[iy] * ub;
+                        cc += rBy[iy] * ub;
+                    }
+                    vx[iz] = a;
+                    vy[iz] = b;
+                    vz[iz] = cc;
+                }
+                wave_sync();  // sX (and sA, sC) are rewritten by the next component
             }
-            wave_sync();  // sX (and sA, sC) are rewritten by the next component
 #pragma unroll
             for (int qz = 0; qz < Q; ++qz) {
                 R dx = 0.0, dy = 0.0, dz = 0.0;
@@ -778,36 +824,57 @@ k_force_pair(const RS *__restrict__ S, const double *__restrict__ e, const doubl
 #pragma unroll
                 for (int qz = 0; qz < Q; ++qz) sv[d][qz] = sn[d][qz];
         }
-        // F^T v: L2 test functions, B_l^T in z (registers), y and x (LDS)
-#pragma unroll
-        for (int jz = 0; jz < DL; ++jz) {
-            R a = 0.0;
-#pragma unroll
-            for (int qz = 0; qz < Q; ++qz) a += tab[T::BL + qz * DL + jz] * sf[qz];
-            sT[le][jz][t] = a;
-        }
-        wave_sync();
-        if (qy < DL) {
-#pragma unroll
-            for (int jz = 0; jz < DL; ++jz) {
-                R a = 0.0;
-#pragma unroll
-                for (int k = 0; k < Q; ++k) a += tab[T::BL + k * DL + qy] * sT[le][jz][k * Q + qx];
-                sT2[le][jz][qy * Q + qx] = a;
-            }
-        }
-        wave_sync();
-        if (act && qx < DL && qy < DL) {
+        // F^T v: L2 test functions, B_l^T in z (registers), y and x (LDS, or
+        // across lanes at Q = 4)
+        if constexpr (LANES) {
             double *__restrict__ zr = z + (long long)perm[el] * DL3;
 #pragma unroll
             for (int jz = 0; jz < DL; ++jz) {
                 R a = 0.0;
 #pragma unroll
-                for (int k = 0; k < Q; ++k) a += tab[T::BL + k * DL + qx] * sT2[le][jz][qy * Q + k];
-                zr[(jz * DL + qy) * DL + qx] = (double)a;
+                for (int qz = 0; qz < Q; ++qz) a += tab[T::BL + qz * DL + jz] * sf[qz];
+                const R u[Q] = {dpp_r<kQuadBcast0>(a), dpp_r<kQuadBcast1>(a), dpp_r<kQuadBcast2>(a),
+                                dpp_r<kQuadBcast3>(a)};
+                R b = 0.0;
+#pragma unroll
+                for (int k = 0; k < Q; ++k) b += cLy[k] * u[k];
+                const R w[Q] = {b, dpp_r<kRowRor4>(b), dpp_r<kRowRor8>(b), dpp_r<kRowRor12>(b)};
+                R o = 0.0;
+#pragma unroll
+                for (int j = 0; j < Q; ++j) o += cLx[j] * w[j];
+                if (act && qx < DL && qy < DL) zr[(jz * DL + qy) * DL + qx] = (double)o;
+            }
+        } else {
+#pragma unroll
+            for (int jz = 0; jz < DL; ++jz) {
+                R a = 0.0;
+#pragma unroll
+                for (int qz = 0; qz < Q; ++qz) a += tab[T::BL + qz * DL + jz] * sf[qz];
+                sT[le][jz][t] = a;
+            }
+            wave_sync();
+            if (qy < DL) {
+#pragma unroll
+                for (int jz = 0; jz < DL; ++jz) {
+                    R a = 0.0;
+#pragma unroll
+                    for (int k = 0; k < Q; ++k) a += tab[T::BL + k * DL + qy] * sT[le][jz][k * Q + qx];
+                    sT2[le][jz][qy * Q + qx] = a;
+                }
+            }
+            wave_sync();
+            if (act && qx < DL && qy < DL) {
+                double *__restrict__ zr = z + (long long)perm[el] * DL3;
+#pragma unroll
+                for (int jz = 0; jz < DL; ++jz) {
+                    R a = 0.0;
+#pragma unroll
+                    for (int k = 0; k < Q; ++k) a += tab[T::BL + k * DL + qx] * sT2[le][jz][qy * Q + k];
+                    zr[(jz * DL + qy) * DL + qx] = (double)a;
+                }
             }
         }
-        wave_sync();  // sSl, sT and sT2 are rewritten by the next pass
+        wave_sync();  // sSl (and sT, sT2) are rewritten by the next pass
     }
     __syncthreads();
     patch_write<UMAX>(acc, pr, pn, y, part, ncomp);
