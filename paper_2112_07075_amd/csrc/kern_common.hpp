@@ -131,10 +131,12 @@ __host__ __device__ constexpr int force_pair_lds(int D, int Q, int rs, int NW)
            (Q == 4 ? 1 : NW * wave_ne(Q) + 1) *
                rs * (2 * D * D * Q + (D - 1) * Q * Q + (D - 1) * (D - 1) * Q + 3 * D * Q * Q + 2 * D * D * Q);
 }
+// F^T v: node table, element slots and (except at Q = 4, where the stages run
+// across lanes) the stagings
 __host__ __device__ constexpr int force_t_lds(int D, int Q, int rs, int NW)
 {
-    return 3 * rs * patch_umax(D) +
-           (NW * wave_ne(Q) + 1) * (4 * D * D * D + rs * (2 * D * D * Q + (D - 1) * Q * Q + (D - 1) * (D - 1) * Q));
+    return 3 * rs * patch_umax(D) + (NW * wave_ne(Q) + 1) * 4 * D * D * D +
+           (Q == 4 ? 1 : NW * wave_ne(Q) + 1) * rs * (2 * D * D * Q + (D - 1) * Q * Q + (D - 1) * (D - 1) * Q);
 }
 __host__ __device__ constexpr int mass_lds(int D, int Q, int rs, int NW)
 {

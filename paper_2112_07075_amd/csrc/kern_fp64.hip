@@ -383,14 +383,33 @@ k_force_t(const RS *__restrict__ S, const double *__restrict__ v,
     constexpr int NE = NW * wave_ne(Q), UMAX = patch_umax(D);
     constexpr int DL = D - 1, QQ = Q * Q, D3 = D * D * D, DL3 = DL * DL * DL;
     using T = Tab<D, Q>;
+    constexpr bool LANES = Q == 4;          // y, x stages across lanes
+    constexpr int NA = LANES ? 1 : NE + 1;  // staging of the LDS-staged stages
     __shared__ R vs[3 * UMAX];
     __shared__ int sSl[NE + 1][D3];
-    __shared__ R sX[NE + 1][2][D][D * Q];
-    __shared__ R sT[NE + 1][DL][QQ];
-    __shared__ R sT2[NE + 1][DL][DL * Q];
+    __shared__ R sX[NA][2][D][D * Q];
+    __shared__ R sT[NA][DL][QQ];
+    __shared__ R sT2[NA][DL][DL * Q];
 
-    const Lane L = lane_map<Q, NE>();
-    const int tid = threadIdx.x, le = L.le, t = L.t, qx = t % Q, qy = t / Q;
+    const int tid = threadIdx.x;
+    int le, t, qx, qy;
+    bool valid;
+    if constexpr (LANES) {
+        // an element is one 16-lane row, point row qy fastest (quads share qx)
+        const int lane = tid & 63, r = lane & 15;
+        le = (tid >> 6) * 4 + (lane >> 4);
+        qy = r & 3;
+        qx = r >> 2;
+        t = qx + Q * qy;
+        valid = true;
+    } else {
+        const Lane L = lane_map<Q, NE>();
+        le = L.le;
+        t = L.t;
+        qx = t % Q;
+        qy = t / Q;
+        valid = L.valid;
+    }
     const PatchRow pr = load_patch(ptab, xcd_block(blockIdx.x, gridDim.x));
     for (int u = tid; u < pr.U; u += blockDim.x) {
         const long long g = pn[pr.pno + u];
@@ -406,13 +425,24 @@ k_force_t(const RS *__restrict__ S, const double *__restrict__ v,
         rBy[i] = tab[T::B + qy * D + i];
         rGy[i] = tab[T::G + qy * D + i];
     }
+    // across lanes: L2 weights of the point row qy, and of the rotated source
+    // columns of the x stage
+    R cLy[LANES ? Q : 1], cLx[LANES ? Q : 1];
+    if constexpr (LANES) {
+        const int kx[Q] = {qx, dpp_i<kRowRor4>(qx), dpp_i<kRowRor8>(qx), dpp_i<kRowRor12>(qx)};
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+            cLx[j] = qx < DL ? tab[T::BL + kx[j] * DL + qx] : (R)0;
+            cLy[j] = qy < DL ? tab[T::BL + j * DL + qy] : (R)0;
+        }
+    }
 
     __syncthreads();
 
 #pragma unroll 1
     for (int base = 0; base < pr.cnt; base += NE) {
         const int idx = base + le;
-        const bool act = L.valid && idx < pr.cnt;
+        const bool act = valid && idx < pr.cnt;
         const long long el = pr.eb + (act ? idx : 0);
         constexpr int SQ = s_stride<RS>(Q);
         const RS *__restrict__ Se = S + el * 9 * SQ + t;
@@ -429,39 +459,70 @@ k_force_t(const RS *__restrict__ S, const double *__restrict__ v,
         for (int k = 0; k < Q; ++k) s[k] = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            // x-stage: thread (qx, iy = qy)
-            if (qy < D) {
+            R vx[D], vy[D], vz[D];
+            if constexpr (LANES) {
+                // x-stage: thread (qx, iy = qy) from the node values; y-stage
+                // over the quad's node rows
+                const int qyc = qy < D ? qy : D - 1;
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
                     R ub = 0.0, ug = 0.0;
 #pragma unroll
                     for (int ix = 0; ix < D; ++ix) {
-                        const R u = vs[3 * sSl[le][(iz * D + qy) * D + ix] + c];
+                        const R u = vs[3 * sSl[le][(iz * D + qyc) * D + ix] + c];
                         ub += rBx[ix] * u;
                         ug += rGx[ix] * u;
                     }
-                    sX[le][0][iz][qy * Q + qx] = ub;
-                    sX[le][1][iz][qy * Q + qx] = ug;
-                }
-            }
-            wave_sync();
-            // y-stage into registers, then z-stage and the pointwise S : grad v
-            R vx[D], vy[D], vz[D];
+                    const R bb[Q] = {dpp_r<kQuadBcast0>(ub), dpp_r<kQuadBcast1>(ub),
+                                     dpp_r<kQuadBcast2>(ub), dpp_r<kQuadBcast3>(ub)};
+                    const R bg[Q] = {dpp_r<kQuadBcast0>(ug), dpp_r<kQuadBcast1>(ug),
+                                     dpp_r<kQuadBcast2>(ug), dpp_r<kQuadBcast3>(ug)};
+                    R a = 0.0, b = 0.0, cc = 0.0;
 #pragma unroll
-            for (int iz = 0; iz < D; ++iz) {
-                R a = 0.0, b = 0.0, cc = 0.0;
-#pragma unroll
-                for (int iy = 0; iy < D; ++iy) {
-                    const R ub = sX[le][0][iz][iy * Q + qx], ug = sX[le][1][iz][iy * Q + qx];
-                    a += rBy[iy] * ug;
-                    b += rGy[iy] * ub;
-                    cc += rBy[iy] * ub;
+                    for (int iy = 0; iy < D; ++iy) {
+                        a += rBy[iy] * bg[iy];
+                        b += rGy[iy] * bb[iy];
+                        cc += rBy[iy] * bb[iy];
+                    }
+                    vx[iz] = a;
+                    vy[iz] = b;
+                    vz[iz] = cc;
                 }
-                vx[iz] = a;
-                vy[iz] = b;
-                vz[iz] = cc;
+            } else {
+                // x-stage: thread (qx, iy = qy)
+                if (qy < D) {
+#pragma unroll
+                    for (int iz = 0; iz < D; ++iz) {
+                        R ub = 0.0, ug = 0.0;
+#pragma unroll
+                        for (int ix = 0; ix < D; ++ix) {
+                            const R u = vs[3 * sSl[le][(iz * D + qy) * D + ix] + c];
+                            ub += rBx[ix] * u;
+                            ug += rGx[ix] * u;
+                        }
+                        sX[le][0][iz][qy * Q + qx] = ub;
+                        sX[le][1][iz][qy * Q + qx] = ug;
+                    }
+                }
+                wave_sync();
+                // y-stage into registers
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) {
+                    R a = 0.0, b = 0.0, cc = 0.0;
+#pragma unroll
+                    for (int iy = 0; iy < D; ++iy) {
+                        const R ub = sX[le][0][iz][iy * Q + qx], ug = sX[le][1][iz][iy * Q + qx];
+                        a += rBy[iy] * ug;
+                        b += rGy[iy] * ub;
+                        cc += rBy[iy] * ub;
+                    }
+                    vx[iz] = a;
+                    vy[iz] = b;
+                    vz[iz] = cc;
+                }
+                wave_sync();  // sX is rewritten by the next component
             }
-            wave_sync();  // sX is rewritten by the next component
+            // z-stage and the pointwise S : grad v
 #pragma unroll
             for (int qz = 0; qz < Q; ++qz) {
                 R dx = 0.0, dy = 0.0, dz = 0.0;
@@ -475,33 +536,55 @@ k_force_t(const RS *__restrict__ S, const double *__restrict__ v,
                 s[qz] += sv[c * 3 + 0][qz] * dx + sv[c * 3 + 1][qz] * dy + sv[c * 3 + 2][qz] * dz;
             }
         }
-        // L2 test functions: B_l^T in z (registers), y and x (LDS)
-#pragma unroll
-        for (int jz = 0; jz < DL; ++jz) {
-            R a = 0.0;
-#pragma unroll
-            for (int qz = 0; qz < Q; ++qz) a += tab[T::BL + qz * DL + jz] * s[qz];
-            sT[le][jz][t] = a;
-        }
-        wave_sync();
-        if (qy < DL) {
-#pragma unroll
-            for (int jz = 0; jz < DL; ++jz) {
-                R a = 0.0;
-#pragma unroll
-                for (int k = 0; k < Q; ++k) a += tab[T::BL + k * DL + qy] * sT[le][jz][k * Q + qx];
-                sT2[le][jz][qy * Q + qx] = a;
-            }
-        }
-        wave_sync();
-        if (act && qx < DL && qy < DL) {
+        // L2 test functions: B_l^T in z (registers), y and x (LDS, or across
+        // lanes at Q = 4)
+        if constexpr (LANES) {
             double *__restrict__ zr = z + (long long)perm[el] * DL3;
 #pragma unroll
             for (int jz = 0; jz < DL; ++jz) {
                 R a = 0.0;
 #pragma unroll
-                for (int k = 0; k < Q; ++k) a += tab[T::BL + k * DL + qx] * sT2[le][jz][qy * Q + k];
-                zr[(jz * DL + qy) * DL + qx] = (double)a;
+                for (int qz = 0; qz < Q; ++qz) a += tab[T::BL + qz * DL + jz] * s[qz];
+                const R u[Q] = {dpp_r<kQuadBcast0>(a), dpp_r<kQuadBcast1>(a), dpp_r<kQuadBcast2>(a),
+                                dpp_r<kQuadBcast3>(a)};
+                R b = 0.0;
+#pragma unroll
+                for (int k = 0; k < Q; ++k) b += cLy[k] * u[k];
+                const R w[Q] = {b, dpp_r<kRowRor4>(b), dpp_r<kRowRor8>(b), dpp_r<kRowRor12>(b)};
+                R o = 0.0;
+#pragma unroll
+                for (int j = 0; j < Q; ++j) o += cLx[j] * w[j];
+                if (act && qx < DL && qy < DL) zr[(jz * DL + qy) * DL + qx] = (double)o;
+            }
+            wave_sync();  // sSl is rewritten by the next pass
+        } else {
+#pragma unroll
+            for (int jz = 0; jz < DL; ++jz) {
+                R a = 0.0;
+#pragma unroll
+                for (int qz = 0; qz < Q; ++qz) a += tab[T::BL + qz * DL + jz] * s[qz];
+                sT[le][jz][t] = a;
+            }
+            wave_sync();
+            if (qy < DL) {
+#pragma unroll
+                for (int jz = 0; jz < DL; ++jz) {
+                    R a = 0.0;
+#pragma unroll
+                    for (int k = 0; k < Q; ++k) a += tab[T::BL + k * DL + qy] * sT[le][jz][k * Q + qx];
+                    sT2[le][jz][qy * Q + qx] = a;
+                }
+            }
+            wave_sync();
+            if (act && qx < DL && qy < DL) {
+                double *__restrict__ zr = z + (long long)perm[el] * DL3;
+#pragma unroll
+                for (int jz = 0; jz < DL; ++jz) {
+                    R a = 0.0;
+#pragma unroll
+                    for (int k = 0; k < Q; ++k) a += tab[T::BL + k * DL + qx] * sT2[le][jz][qy * Q + k];
+                    zr[(jz * DL + qy) * DL + qx] = (double)a;
+                }
             }
         }
     }
