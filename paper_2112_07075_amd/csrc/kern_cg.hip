@@ -97,52 +97,25 @@ __global__ void k_cg_start_final(const double *__restrict__ part_rr,
         st->iter = 0;
         st->max_iter = max_iter;
         st->done = (rr <= st->stop) ? 1 : (max_iter <= 0 ? 2 : 0);
-        st->alpha = st->beta = st->pAp = 0.0;
+        st->alpha = st->beta = st->pAp = st->alpha_p = 0.0;
+        st->pend = 0;
     }
 }
 
-// One step of the iteration. Every workgroup sums the mass kernel's partials
-// of p'.Ap in the same order, so all agree on alpha without another launch;
-// the new r.r is left as per-workgroup partials for k_cg_beta. (A last-
-// workgroup reduction here would need a device-scope release fence per
-// workgroup, which writes back the XCD's L2 and costs more than a launch.)
-__global__ void k_cg_step(double *__restrict__ x, double *__restrict__ r, double *__restrict__ p,
-                          const double *__restrict__ Ap, const unsigned char *__restrict__ fr,
-                          long long n, const double *__restrict__ part_pap, int n_pap,
-                          const CgState *__restrict__ st, double *__restrict__ part)
-{
-    __shared__ double sred[16];
-    __shared__ double s_alpha;
-    if (st->done) return;
-    double s = 0.0;
-    for (int k = threadIdx.x; k < n_pap; k += blockDim.x) s += part_pap[k];
-    s = block_sum(s, sred);
-    if (threadIdx.x == 0) s_alpha = st->rr / s;
-    __syncthreads();
-    const double alpha = s_alpha, beta = st->beta;
-    double rr = 0.0;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const double ri = r[i];
-        const double pi = ri + beta * p[i];
-        p[i] = pi;
-        x[i] += alpha * pi;
-        const double rn = fr[i] ? ri - alpha * Ap[i] : 0.0;
-        r[i] = rn;
-        rr += rn * rn;
-    }
-    rr = block_sum(rr, sred);
-    if (threadIdx.x == 0) part[blockIdx.x] = rr;
-}
-
-// The step of a one-mesh solve whose mass launch left the shared nodes as
-// patch partials (no gather pass): the step reads Ap of a shared node as the
-// sum of its partials in ascending patch order (the order of the gather it
-// replaces), node by node with the three components of a node in one thread.
+// One step of a one-mesh solve, after Ap = M p' with p' = r + beta p (the
+// mass kernel forms p' during its gather, leaves partials of p'.Ap and leaves
+// the shared nodes of Ap as patch partials, no gather pass): p = p', alpha =
+// rr / (p.Ap), r -= alpha Ap on free DOFs, x += alpha p every second step,
+// partials of the new r.r. Every workgroup sums the p'.Ap partials in the same
+// order, so all agree on alpha without another launch (a last-workgroup
+// reduction would need a device-scope release fence per workgroup, which
+// writes back the XCD's L2 and costs more than a launch). Ap of a shared node
+// is the sum of its partials in ascending patch order (the order of the
+// gather it replaces), node by node with the three components in one thread.
 __global__ void k_cg_step_sh(double *__restrict__ x, double *__restrict__ r, double *__restrict__ p,
                              const double *__restrict__ Ap, const unsigned char *__restrict__ fr,
                              long long nn, const double *__restrict__ part_pap, int n_pap,
-                             const CgState *__restrict__ st, double *__restrict__ part,
+                             CgState *__restrict__ st, double *__restrict__ part,
                              const int32_t *__restrict__ node_sh, const int32_t *__restrict__ sh_ptr,
                              const int32_t *__restrict__ sh_idx, const double *__restrict__ shpart)
 {
@@ -155,6 +128,10 @@ __global__ void k_cg_step_sh(double *__restrict__ x, double *__restrict__ r, dou
     if (threadIdx.x == 0) s_alpha = st->rr / s;
     __syncthreads();
     const double alpha = s_alpha, beta = st->beta;
+    // x takes the directions of two iterations at once: after an even
+    // iteration alpha is left pending, after an odd one both are added
+    const bool flush = (st->iter & 1) != 0;
+    const double alpha_p = st->alpha_p;
     double rr = 0.0;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < nn; g += stride) {
@@ -175,10 +152,10 @@ __global__ void k_cg_step_sh(double *__restrict__ x, double *__restrict__ r, dou
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const long long i = c * nn + g;
-            const double ri = r[i];
-            const double pi = ri + beta * p[i];
+            const double ri = r[i], po = p[i];
+            const double pi = ri + beta * po;
             p[i] = pi;
-            x[i] += alpha * pi;
+            if (flush) x[i] += alpha_p * po + alpha * pi;
             const double rn = fr[i] ? ri - alpha * ap[c] : 0.0;
             r[i] = rn;
             rr += rn * rn;
@@ -186,6 +163,22 @@ __global__ void k_cg_step_sh(double *__restrict__ x, double *__restrict__ r, dou
     }
     rr = block_sum(rr, sred);
     if (threadIdx.x == 0) part[blockIdx.x] = rr;
+    // the pending alpha is read by every workgroup of a flushing step only, and
+    // written (by one) only in the steps that do not flush
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (!flush) st->alpha_p = alpha;
+        st->pend = flush ? 0 : 1;
+    }
+}
+
+__global__ void k_cg_finish(double *__restrict__ x, const double *__restrict__ p, long long n,
+                            const CgState *__restrict__ st)
+{
+    if (!st->pend) return;
+    const double a = st->alpha_p;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        x[i] += a * p[i];
 }
 
 // One workgroup: the new r.r, beta = rr_new / rr, convergence and limit checks.
@@ -459,13 +452,9 @@ void cg_step_shared(double *x, double *r, double *p, const double *Ap, const uns
     hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1024), 0, st, part, kVecBlocks, state);
 }
 
-void cg_step(double *x, double *r, double *p, const double *Ap, const unsigned char *fr,
-             long long n, const double *part_pap, int n_pap, CgState *state, double *part,
-             hipStream_t st)
+void cg_finish(double *x, const double *p, long long n, const CgState *state, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cg_step, dim3(kVecBlocks), dim3(256), 0, st, x, r, p, Ap, fr, n, part_pap,
-                       n_pap, state, part);
-    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1024), 0, st, part, kVecBlocks, state);
+    hipLaunchKernelGGL(k_cg_finish, dim3(kVecBlocks), dim3(256), 0, st, x, p, n, state);
 }
 
 void resid_norm2(const double *b, const double *Ax, const unsigned char *fr, long long n,

@@ -6,10 +6,12 @@
 namespace fepa {
 
 // Device-resident state of one CG solve. done: 0 running, 1 converged,
-// 2 iteration limit reached.
+// 2 iteration limit reached. The one-mesh step adds alpha p to x every second
+// iteration (two directions at once); pend = 1 while x still lacks
+// alpha_p * p of the last iteration (cg_finish applies it).
 struct CgState {
-    double rr, alpha, beta, bb, stop, pAp;
-    int iter, done, max_iter, pad;
+    double rr, alpha, beta, bb, stop, pAp, alpha_p;
+    int iter, done, max_iter, pend;
 };
 
 constexpr int kVecBlocks = 1024;  // workgroups of the vector kernels (partials per pass)
@@ -49,20 +51,21 @@ void cg_mask_apply(double *x, const unsigned char *fr, long long n, hipStream_t 
 void cg_start(const double *b, const double *Ax, double *r, double *p, const unsigned char *fr,
               long long n, double *part_a, double *part_b, CgState *state, double rel_tol,
               int max_iter, hipStream_t st);
-// One CG step after Ap = M p' with p' = r + beta p (the mass kernel forms p'
-// during its gather and leaves partials of p'.Ap in part_pap): p = p',
-// alpha = rr / (p.Ap), x += alpha p, r -= alpha Ap on free DOFs; then one
-// workgroup finishes r.r and sets beta, the iteration count and done.
-void cg_step(double *x, double *r, double *p, const double *Ap, const unsigned char *fr,
-             long long n, const double *part_pap, int n_pap, CgState *state, double *part,
-             hipStream_t st);
-// The same step for one mesh whose mass launch skipped the shared-node gather:
-// Ap of a shared node is the sum of its patch partials (node_sh[g]: its row in
-// the shared-node lists sh_ptr/sh_idx over shpart, or -1); nn = nodes.
+// One CG step of a one-mesh solve after Ap = M p' with p' = r + beta p (the
+// mass kernel forms p' during its gather, leaves partials of p'.Ap in part_pap
+// and skips the shared-node gather): p = p', alpha = rr / (p.Ap), r -= alpha
+// Ap on free DOFs, x += alpha p every second step (cg_finish adds a pending
+// last one); then one workgroup finishes r.r and sets beta, the iteration
+// count and done. Ap of a shared node is the sum of its patch partials
+// (node_sh[g]: its row in the shared-node lists sh_ptr/sh_idx over shpart, or
+// -1); nn = nodes.
 void cg_step_shared(double *x, double *r, double *p, const double *Ap, const unsigned char *fr,
                     long long nn, const double *part_pap, int n_pap, CgState *state, double *part,
                     const int32_t *node_sh, const int32_t *sh_ptr, const int32_t *sh_idx,
                     const double *shpart, hipStream_t st);
+// After the iterations of a one-mesh solve: x += alpha_p p if the last
+// iteration's direction is still pending.
+void cg_finish(double *x, const double *p, long long n, const CgState *state, hipStream_t st);
 void vec_sub_masked(const double *b, const double *Ax, const unsigned char *fr, double *out,
                     long long n, hipStream_t st);
 void vec_add(double *x, const double *d, long long n, hipStream_t st);

@@ -224,6 +224,32 @@ def test_cg_iteration_limit_and_bad_dofs(torch_cuda):
     assert ei.value.status == fe.FE_EINVAL
 
 
+@pytest.mark.parametrize("k", [1, 2, 3, 6])
+@pytest.mark.parametrize("flags", [0, fe.FE_OPT_GRAPH])
+def test_cg_iterate_after_k_steps_matches_oracle(torch_cuda, k, flags):
+    # A solve stopped by its iteration limit leaves the k-th CG iterate in x,
+    # after odd and even k, eager and replayed from graphs (the step adds the
+    # directions of two iterations at once and the last one may be pending).
+    c = make_case(3, 2, 4, seed=8)
+    g = GpuRun(torch_cuda, c, flags=flags)
+    mq = oracle_qdata(c)["mq"]
+    ess_idx = W.boundary_normal_dofs(c.mesh)
+    b = np.random.default_rng(9).standard_normal((3, c.N))
+    xo, it_o, _, ok = O.mass_cg(c.mesh.elem_nodes, 2, 4, c.N, mq, b, ess=ess_idx, rel_tol=0.0,
+                                max_iter=k)
+    assert not ok and it_o == k
+    xg = torch_cuda.zeros((3, c.N), dtype=torch_cuda.float64, device="cuda")
+    rc, it_g, _ = fe.fe_mass_cg(g.ctx, dev(torch_cuda, b), xg, dev(torch_cuda, ess_idx), rel_tol=0.0,
+                                max_iter=k, check=False)
+    assert rc == fe.FE_ENOTCONV and it_g == k
+    xg = xg.cpu().numpy()
+    assert np.linalg.norm(xg - xo) <= 1e-11 * np.linalg.norm(xo)
+    # a second solve from this x continues from it (x is complete on return)
+    rc, it_g, rr_g = fe.fe_mass_cg(g.ctx, dev(torch_cuda, b), dev(torch_cuda, xg),
+                                   dev(torch_cuda, ess_idx), rel_tol=1e-12)
+    assert rc == fe.FE_OK and rr_g < 2e-12
+
+
 def test_inverted_mesh_and_nonfinite_flags(torch_cuda):
     mesh = W.cube_mesh(2, 2, 0.0)
     x0 = mesh.x0.copy()
