@@ -51,12 +51,12 @@ HBM_PEAK_GBS = 8000.0
 # reported only while those are unchanged (profiles/c2_fp64_step.md,
 # profiles/c4_step.md).
 TRAFFIC = {
-    ("c2", "fp64"): {"action": "pair", "kernel": "k_force_pair<3,4,ONE,double,4>", "bytes": 611.3e6,
-                     "src": {"kern_fp64.hip": "3d1dc536f9ef19be", "kern_common.hpp": "7929ca9fa00e3092",
-                             "tune_table.inc": "da1065314c46e33b"}},
-    ("c4", "fp64"): {"action": "pair", "kernel": "k_force_pair<4,5,ONE,double,4>", "bytes": 3351.3e6,
-                     "src": {"kern_fp64.hip": "3d1dc536f9ef19be", "kern_common.hpp": "7929ca9fa00e3092",
-                             "tune_table.inc": "da1065314c46e33b"}},
+    ("c2", "fp64"): {"action": "pair", "kernel": "k_force_pair<3,4,ONE,double,2>", "bytes": 614.9e6,
+                     "src": {"kern_fp64.hip": "5c1f7413bda2bcdc", "kern_common.hpp": "243f1c42df2ea2ef",
+                             "tune_table.inc": "57afa8d182eb45ab"}},
+    ("c4", "fp64"): {"action": "pair", "kernel": "k_force_pair<4,5,ONE,double,4>", "bytes": 3350.6e6,
+                     "src": {"kern_fp64.hip": "5c1f7413bda2bcdc", "kern_common.hpp": "243f1c42df2ea2ef",
+                             "tune_table.inc": "57afa8d182eb45ab"}},
 }
 
 
