@@ -357,7 +357,10 @@ def main():
         "cg": {"iters": run.cg.get("iters"), "true_rel_res": run.cg.get("rel_res"),
                "mass_us": round(per["mass"][0] * 1e3, 2)},
         "min_detj": diag["min_detj"],
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+        "roofline": {"bound": "hbm", "kernel": dom,
+                     "timed": "whole action: k_force_pair (or k_force + k_force_t) + k_gather_shared, "
+                              "HIP events around every action of the timed steps",
+                     "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(args.config, args.precision, dom),
                      "traffic_unit": "MB per launch", "algorithmic_MB": round(ab[dom] / 1e6, 1)},
