@@ -1083,10 +1083,12 @@ static int cg_run(fe_ctx *ctx, const double *b, double *x, double rel_tol, int m
         if (ctx->multi ? ctx->h_glob->done : ctx->h_cg->done) break;
         if (batch < 32) batch *= 2;
     }
-    if (!ctx->multi) {  // the last direction, if the step left it pending
+    // the last direction, where the step left it pending
+    if (ctx->multi)
+        cgm_finish(x, ctx->p, ctx->cm, ctx->st);
+    else
         cg_finish(x, ctx->p, n, ctx->cg, ctx->st);
-        HIP_OK(hipGetLastError());
-    }
+    HIP_OK(hipGetLastError());
     if (ctx->multi) {
         const size_t nm = ctx->mesh.size();
         HIP_OK(hipMemcpyAsync(ctx->h_cgm, ctx->cgm, nm * sizeof(CgState), hipMemcpyDeviceToHost, ctx->st));

@@ -255,7 +255,8 @@ __global__ void k_cgm_start_final(const double *__restrict__ part_rr,
         st.iter = 0;
         st.max_iter = max_iter;
         st.done = (rr <= st.stop) ? 1 : (max_iter <= 0 ? 2 : 0);
-        st.alpha = st.beta = st.pAp = 0.0;
+        st.alpha = st.beta = st.pAp = st.alpha_p = 0.0;
+        st.pend = 0;
         if (!st.done) atomicAdd(&glob->running, 1);
     }
 }
@@ -277,13 +278,20 @@ __global__ void k_cgm_alpha(const double *__restrict__ part, const int *__restri
     for (int k = prange[2 * m] + threadIdx.x; k < prange[2 * m + 1]; k += blockDim.x) s += part[k];
     s = block_sum(s, sred);
     if (threadIdx.x == 0) {
-        state[m].pAp = s;
-        state[m].alpha = state[m].rr / s;
+        // x takes two iterations' directions every second step: keep the
+        // previous alpha for an odd iteration; an even one leaves its own pending
+        CgState &st = state[m];
+        const bool odd = (st.iter & 1) != 0;
+        if (odd) st.alpha_p = st.alpha;
+        st.pend = odd ? 0 : 1;
+        st.pAp = s;
+        st.alpha = st.rr / s;
     }
 }
 
-// One workgroup per chunk: p = r + beta p, x += alpha p, r -= alpha Ap with the
-// chunk's mesh scalars; partial of the new r.r.
+// One workgroup per chunk: p = r + beta p, r -= alpha Ap with the chunk's
+// mesh scalars, x += alpha_(k-1) p_(k-1) + alpha_k p_k after odd iterations k;
+// partial of the new r.r.
 __global__ void k_cgm_step(double *__restrict__ x, double *__restrict__ r, double *__restrict__ p,
                            const double *__restrict__ Ap, const unsigned char *__restrict__ fr,
                            const CgChunk *__restrict__ chunk, const CgState *__restrict__ state,
@@ -294,20 +302,36 @@ __global__ void k_cgm_step(double *__restrict__ x, double *__restrict__ r, doubl
     const CgChunk ck = chunk[blockIdx.x];
     const CgState &st = state[ck.mesh];
     if (st.done) return;
-    const double alpha = st.alpha, beta = st.beta;
+    const double alpha = st.alpha, beta = st.beta, alpha_p = st.alpha_p;
+    const bool flush = (st.iter & 1) != 0;  // odd iteration: both directions into x
     double rr = 0.0;
     for (int k = threadIdx.x; k < ck.len; k += blockDim.x) {
         const long long i = (long long)ck.start + k;
-        const double ri = r[i];
-        const double pi = ri + beta * p[i];
+        const double ri = r[i], po = p[i];
+        const double pi = ri + beta * po;
         p[i] = pi;
-        x[i] += alpha * pi;
+        if (flush) x[i] += alpha_p * po + alpha * pi;
         const double rn = fr[i] ? ri - alpha * Ap[i] : 0.0;
         r[i] = rn;
         rr += rn * rn;
     }
     rr = block_sum(rr, sred);
     if (threadIdx.x == 0) part[blockIdx.x] = rr;
+}
+
+// After the iterations: x += alpha p in the chunks of every mesh whose last
+// (even) iteration left its direction pending.
+__global__ void k_cgm_finish(double *__restrict__ x, const double *__restrict__ p,
+                             const CgChunk *__restrict__ chunk, const CgState *__restrict__ state)
+{
+    const CgChunk ck = chunk[blockIdx.x];
+    const CgState &st = state[ck.mesh];
+    if (!st.pend) return;
+    const double a = st.alpha;
+    for (int k = threadIdx.x; k < ck.len; k += blockDim.x) {
+        const long long i = (long long)ck.start + k;
+        x[i] += a * p[i];
+    }
 }
 
 // One workgroup per mesh: new r.r, beta, iteration count, convergence; the
@@ -473,6 +497,11 @@ void cgm_start(const double *b, const double *Ax, double *r, double *p, const un
     hipLaunchKernelGGL(k_cgm_start_final, dim3(cm.n_mesh), dim3(256), 0, st, part_a, part_b, cm.cbeg,
                        cm.state, cm.glob, rel_tol, max_iter);
     hipLaunchKernelGGL(k_cgm_glob, dim3(1), dim3(64), 0, st, cm.glob);
+}
+
+void cgm_finish(double *x, const double *p, const CgMulti &cm, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cgm_finish, dim3(cm.n_chunk), dim3(256), 0, st, x, p, cm.chunk, cm.state);
 }
 
 void cgm_iterate(double *x, double *r, double *p, const double *Ap, const unsigned char *fr,

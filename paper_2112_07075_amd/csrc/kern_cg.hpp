@@ -6,9 +6,9 @@
 namespace fepa {
 
 // Device-resident state of one CG solve. done: 0 running, 1 converged,
-// 2 iteration limit reached. The one-mesh step adds alpha p to x every second
-// iteration (two directions at once); pend = 1 while x still lacks
-// alpha_p * p of the last iteration (cg_finish applies it).
+// 2 iteration limit reached. The step adds alpha p to x every second
+// iteration (two directions at once); pend = 1 while x still lacks the last
+// iteration's alpha p (cg_finish / cgm_finish apply it).
 struct CgState {
     double rr, alpha, beta, bb, stop, pAp, alpha_p;
     int iter, done, max_iter, pend;
@@ -41,6 +41,9 @@ void cgm_start(const double *b, const double *Ax, double *r, double *p, const un
                hipStream_t st);
 void cgm_iterate(double *x, double *r, double *p, const double *Ap, const unsigned char *fr,
                  const CgMulti &cm, const double *part_pap, double *part, hipStream_t st);
+// After the iterations: the pending last direction of every mesh whose step
+// left one (x += alpha p in that mesh's chunks).
+void cgm_finish(double *x, const double *p, const CgMulti &cm, hipStream_t st);
 // out[m] = ||b_m - (Ax)_m||^2 over free DOFs
 void cgm_resid(const double *b, const double *Ax, const unsigned char *fr, const CgMulti &cm,
                double *part, double *out, hipStream_t st);

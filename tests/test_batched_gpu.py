@@ -269,7 +269,17 @@ def test_each_mesh_runs_its_own_cg(torch_cuda):
         xh = xg.cpu().numpy()
         for k, xk in enumerate(xs):
             assert np.linalg.norm(g.h1_slice(xh, k) - xk) < 1e-9 * np.linalg.norm(xk), k
-        xg.zero_()
-        rc, it, rr = fe.fe_mass_cg(g.ctx, g.h1(bs), xg, None, rel_tol=1e-12, max_iter=3,
-                                   check=False)
-        assert rc == fe.FE_ENOTCONV and it == 3
+        # stopped by the iteration limit after an odd and an even count: every
+        # mesh's x is its own k-th CG iterate (the last direction may have been
+        # left pending by the step and is added after the loop)
+        for k_it in (3, 2):
+            xg.zero_()
+            rc, it, rr = fe.fe_mass_cg(g.ctx, g.h1(bs), xg, None, rel_tol=1e-12, max_iter=k_it,
+                                       check=False)
+            assert rc == fe.FE_ENOTCONV and it == k_it
+            xh = xg.cpu().numpy()
+            for k, (c, b) in enumerate(zip(cases, bs)):
+                xo, ito, _, ok = O.mass_cg(c.mesh.elem_nodes, c.p, c.Q, c.N, oracle_qdata(c)["mq"], b,
+                                           rel_tol=1e-12, max_iter=k_it)
+                assert not ok and ito == k_it
+                assert np.linalg.norm(g.h1_slice(xh, k) - xo) <= 1e-11 * np.linalg.norm(xo), (k, k_it)
