@@ -52,10 +52,10 @@ HBM_PEAK_GBS = 8000.0
 # profiles/c4_step.md).
 TRAFFIC = {
     ("c2", "fp64"): {"action": "pair", "kernel": "k_force_pair<3,4,ONE,double,2>", "bytes": 614.9e6,
-                     "src": {"kern_fp64.hip": "5c1f7413bda2bcdc", "kern_common.hpp": "243f1c42df2ea2ef",
+                     "src": {"kern_fp64.hip": "2817bcc2e6223854", "kern_common.hpp": "243f1c42df2ea2ef",
                              "tune_table.inc": "57afa8d182eb45ab"}},
-    ("c4", "fp64"): {"action": "pair", "kernel": "k_force_pair<4,5,ONE,double,4>", "bytes": 3350.6e6,
-                     "src": {"kern_fp64.hip": "5c1f7413bda2bcdc", "kern_common.hpp": "243f1c42df2ea2ef",
+    ("c4", "fp64"): {"action": "pair", "kernel": "k_force_pair<4,5,ONE,double,4>", "bytes": 3348.6e6,
+                     "src": {"kern_fp64.hip": "2817bcc2e6223854", "kern_common.hpp": "243f1c42df2ea2ef",
                              "tune_table.inc": "57afa8d182eb45ab"}},
 }
 

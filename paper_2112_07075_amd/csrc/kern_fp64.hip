@@ -436,6 +436,8 @@ k_force_t(const RS *__restrict__ S, const double *__restrict__ v,
             cLy[j] = qy < DL ? tab[T::BL + j * DL + qy] : (R)0;
         }
     }
+    // idle lanes (spare element row NE) read slots from the spare row: keep it valid
+    for (int i = tid; i < D3; i += blockDim.x) sSl[NE][i] = 0;
 
     __syncthreads();
 
@@ -681,6 +683,8 @@ k_force_pair(const RS *__restrict__ S, const double *__restrict__ e, const doubl
         rBy[i] = tab[T::B + qy * D + i];
         rGy[i] = tab[T::G + qy * D + i];
     }
+    // idle lanes (spare element row NE) read slots from the spare row: keep it valid
+    for (int i = tid; i < D3; i += blockDim.x) sSl[NE][i] = 0;
     __syncthreads();
 
     // S by component: sv holds component c of this pass while sn loads the next
@@ -1025,6 +1029,8 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
             acc[3 * u + c] = (R)0;
         }
     }
+    // idle lanes (spare element row NE) read slots from the spare row: keep it valid
+    for (int i = tid; i < D3; i += blockDim.x) sSl[NE][i] = 0;
     __syncthreads();
 #pragma unroll 1
     for (int base = 0; base < pr.cnt; base += NE) {
