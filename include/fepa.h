@@ -83,10 +83,13 @@ extern "C" {
 #define FE_OPT_TIMERS   0x1  /* record HIP events around the main kernels     */
 #define FE_OPT_BATCHED  0x2  /* multi-mesh: one launch per (order, Q) class of
                                 meshes per action, over their joined patches */
-#define FE_OPT_GRAPH    0x4  /* actions and groups of CG iterations replayed
+#define FE_OPT_GRAPH    0x4  /* groups of CG iterations, and the actions of
+                                a context with several launch units, replayed
                                 from hipGraphs captured at first use (per
-                                argument set); class launches run as parallel
-                                branches                                    */
+                                argument set), the units as parallel
+                                branches; a one-unit action (two or three
+                                kernels) is launched directly, which starts
+                                sooner than a graph replay                  */
 
 /* kernels timed under FE_OPT_TIMERS */
 #define FE_TIMER_QDATA   0
