@@ -54,7 +54,7 @@ TRAFFIC = {
     ("c2", "fp64"): {"action": "pair", "kernel": "k_force_pair<3,4,ONE,double,2>", "bytes": 614.9e6,
                      "src": {"kern_fp64.hip": "2817bcc2e6223854", "kern_common.hpp": "243f1c42df2ea2ef",
                              "tune_table.inc": "57afa8d182eb45ab"}},
-    ("c4", "fp64"): {"action": "pair", "kernel": "k_force_pair<4,5,ONE,double,4>", "bytes": 3348.6e6,
+    ("c4", "fp64"): {"action": "pair", "kernel": "k_force_pair<4,5,ONE,double,4>", "bytes": 3348.0e6,
                      "src": {"kern_fp64.hip": "2817bcc2e6223854", "kern_common.hpp": "243f1c42df2ea2ef",
                              "tune_table.inc": "57afa8d182eb45ab"}},
 }
