@@ -177,7 +177,10 @@ int fe_mesh_offsets(const fe_ctx_t *ctx, int64_t *node_offset, int64_t *elem_off
                     int64_t *l2_offset);
 
 /*
- * Quadrature-data update (the qdata step of the Lagrange phase): from the
+ * Quadrature-data update (the qdata step of the Lagrange phase; Sec. 2.1's
+ * total stress of ideal-gas pressure plus artificial viscosity, Sec. 3.3's
+ * rho |J| = rho0 |J0|, Sec. 6's quadrature-point data and viscosity
+ * coefficients): from the
  * current positions x, velocities v ([3][N_tot], device) and specific internal
  * energy e ([E_tot][Dl^3], device), compute J, detJ, J^{-1}, rho = m_q/(w detJ),
  * e_q, the ideal-gas pressure, the viscosity and S_q = w detJ sigma J^{-T}
@@ -214,11 +217,14 @@ int fe_force_mult_T(fe_ctx_t *ctx, const double *v, double *z);
  */
 int fe_force_mult_pair(fe_ctx_t *ctx, const double *e, double *y, const double *v, double *z);
 
-/* Mass action y = M_v x ([3][N_tot] device in and out; y overwritten). Asynchronous. */
+/* Mass action y = M_v x (the kinematic mass matrix of Sec. 3.3's momentum
+ * equation, applied as Sec. 3.2's element mass matrices by sum factorisation;
+ * [3][N_tot] device in and out; y overwritten). Asynchronous. */
 int fe_mass_mult(fe_ctx_t *ctx, const double *x, double *y);
 
 /*
- * Solve M_v x = b by unpreconditioned conjugate gradients on the free DOFs,
+ * Solve M_v x = b (Sec. 3.3's momentum equation; Sec. 6's inversion of the
+ * global CG mass matrix) by unpreconditioned conjugate gradients on the free DOFs,
  * with x = 0 on the essential DOFs ess_dofs (device int32 indices into
  * [3][N_tot], sorted or not, no duplicates; NULL/n_ess = 0 for none).
  * x (device [3][N_tot]) holds the initial guess on entry and the solution on

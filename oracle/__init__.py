@@ -48,7 +48,8 @@ def lib():
         L.or_lagrange.restype = None
         L.or_qdata.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _ip, _dp, _dp, _vp, _vp,
                                C.c_double, C.c_double, C.c_double, C.c_double, _vp, C.c_int,
-                               _vp, _vp, _vp]
+                               _vp, _vp, _vp, _vp]
+        L.or_l2_mass.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp]
         L.or_force_elem_matrix.argtypes = [C.c_int, C.c_int, _dp, _dp]
         L.or_mass_elem_matrix.argtypes = [C.c_int, C.c_int, _dp, _dp]
         for fn in (L.or_force_mult, L.or_force_mult_T, L.or_mass_mult):
@@ -102,7 +103,8 @@ class OracleError(RuntimeError):
 
 def qdata(mesh_map, p, Q, N, x0, x, v, e, rho0=1.0, gamma=5.0 / 3.0, q1=0.5, q2=2.0,
           elems=None, want=("S", "mq", "detJ"), allow_bad=False):
-    """Quadrature data: dict with S [E][3][3][Q^3], mq [E][Q^3], detJ [E][Q^3]."""
+    """Quadrature data: dict with S [E][3][3][Q^3], mq, detJ and dt (the per-point
+    stable time step) [E][Q^3], as asked for in want."""
     mesh_map = _i32(mesh_map)
     E = mesh_map.shape[0]
     Q3 = Q ** 3
@@ -111,7 +113,8 @@ def qdata(mesh_map, p, Q, N, x0, x, v, e, rho0=1.0, gamma=5.0 / 3.0, q1=0.5, q2=
     el = _i32(elems)
     rc = lib().or_qdata(E, p, Q, N, mesh_map, x0, x, _ptr(v), _ptr(e), rho0, gamma, q1, q2,
                         _ptr(el), 0 if el is None else len(el),
-                        _ptr(out.get("S")), _ptr(out.get("mq")), _ptr(out.get("detJ")))
+                        _ptr(out.get("S")), _ptr(out.get("mq")), _ptr(out.get("detJ")),
+                        _ptr(out.get("dt")))
     if rc == -2 and not allow_bad:
         raise OracleError("non-positive Jacobian determinant")
     if rc not in (0, -2):
@@ -186,3 +189,63 @@ def mass_cg(mesh_map, p, Q, N, mq, b, x0=None, ess=None, rel_tol=1e-12, max_iter
     if rc < 0:
         raise OracleError(f"or_mass_cg failed: {rc}")
     return x.reshape(3, N), it.value, rr.value, rc == 0
+
+
+# ------------------------------------------------------------ Lagrange step
+def l2_mass(mesh_map, p, Q, mq):
+    """Element L2 mass matrices M_E [E][p^3][p^3] from m_q (the energy equation's M_E)."""
+    E = _i32(mesh_map).shape[0]
+    Dl3 = p ** 3
+    ME = np.zeros(E * Dl3 * Dl3)
+    if lib().or_l2_mass(E, p, Q, _f64(mq).ravel(), ME):
+        raise OracleError("or_l2_mass failed")
+    return ME.reshape(E, Dl3, Dl3)
+
+
+def total_energy(mesh_map, p, Q, N, mq, v, e):
+    """Kinetic + internal energy: 1/2 v^T M_v v + sum_E 1^T M_E e_E (= int rho e)."""
+    kin = 0.5 * float((_f64(v).reshape(3, N) * mass_mult(mesh_map, p, Q, N, mq, v)).sum())
+    ME = l2_mass(mesh_map, p, Q, mq)
+    inner = float(np.einsum("ejk,ek->", ME, _f64(e).reshape(ME.shape[0], -1)))
+    return kin, inner
+
+
+def lagrange_rhs(mesh_map, p, Q, N, x0, x, v, e, ess, rho0, gamma, q1, q2, cg_tol, vbar=None):
+    """Right-hand sides of the semi-discrete system (Sec. 3.3) at one state:
+    S from the state, a = M_v^-1 (-F 1) on the free DOFs (0 on ess), and
+    de = M_E^-1 F^T w with w = v (or the given vbar). Returns (a, de, dt_min, S)."""
+    qd = qdata(mesh_map, p, Q, N, x0, x, v, e, rho0, gamma, q1, q2, want=("S", "mq", "dt"))
+    rhs = -force_mult(mesh_map, p, Q, N, qd["S"])
+    a, _, _, ok = mass_cg(mesh_map, p, Q, N, qd["mq"], rhs, ess=ess, rel_tol=cg_tol, max_iter=20000)
+    if not ok:
+        raise OracleError("mass CG did not converge")
+    z = force_mult_T(mesh_map, p, Q, N, qd["S"], v if vbar is None else vbar)
+    de = np.linalg.solve(l2_mass(mesh_map, p, Q, qd["mq"]), z[:, :, None])[:, :, 0]
+    return a, de, float(qd["dt"].min()), qd
+
+
+def lagrange_step(mesh_map, p, Q, N, x0, x, v, e, ess=None, cfl=0.5, dt_max=np.inf,
+                  rho0=1.0, gamma=5.0 / 3.0, q1=0.5, q2=2.0, cg_tol=1e-14):
+    """One two-stage step of the semi-discrete Lagrange system (Sec. 3.3):
+      M_v dv/dt = -F 1,  M_E de/dt = F^T v,  dx/dt = v.
+    The step size is dt = min(dt_max, cfl * min_q dt_q) at the start of the step.
+    Stage 1 (midpoint predictor from the state n):
+      v_h = v + dt/2 a(n),  e_h = e + dt/2 M_E^-1 F(n)^T v,  x_h = x + dt/2 v.
+    Stage 2 (from the midpoint forces):
+      v' = v + dt a(h),  vbar = (v + v')/2,  e' = e + dt M_E^-1 F(h)^T vbar,  x' = x + dt vbar.
+    Using vbar in both the energy and the position updates makes the change of
+    kinetic energy, vbar^T M_v (v' - v) = -dt vbar^T F(h) 1, cancel the change
+    of internal energy, dt 1^T F(h)^T vbar, exactly (up to the CG residual).
+    Returns (x', v', e', dt)."""
+    x, v, e = (_f64(a).copy() for a in (x, v, e))
+    a0, de0, dtq, _ = lagrange_rhs(mesh_map, p, Q, N, x0, x, v, e, ess, rho0, gamma, q1, q2, cg_tol)
+    dt = min(dt_max, cfl * dtq)
+    vh = v + 0.5 * dt * a0
+    eh = e + 0.5 * dt * de0
+    xh = x + 0.5 * dt * v
+    a1, _, _, qd = lagrange_rhs(mesh_map, p, Q, N, x0, xh, vh, eh, ess, rho0, gamma, q1, q2, cg_tol)
+    v1 = v + dt * a1
+    vbar = 0.5 * (v + v1)
+    z = force_mult_T(mesh_map, p, Q, N, qd["S"], vbar)
+    de1 = np.linalg.solve(l2_mass(mesh_map, p, Q, qd["mq"]), z[:, :, None])[:, :, 0]
+    return x + dt * vbar, v1, e + dt * de1, dt

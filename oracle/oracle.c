@@ -216,6 +216,11 @@ static void inv3(const double A[3][3], double det, double inv[3][3])
  *   S[e][c][d][q] = w_q detJ_q sum_k sigma_q[c][k] Jinv_q[d][k]  (w detJ sigma J^-T)
  *   mq[e][q]      = rho0 detJ0_q w_q                             (rho |J| = rho0 |J0|)
  *   detJ[e][q]    (optional)
+ *   dt[e][q]      (optional) the stable explicit time step of the point: the
+ *                 time a signal of speed c_s + mu/(rho l) needs to cross the
+ *                 length l = detJ^(1/3)/p, i.e. l / ((1+q1) c_s + q2 l max(0, -tr eps))
+ *                 (+inf where both speeds vanish); a reading, the paper names
+ *                 no time-step rule
  * Inputs: x0, x, v as [3][N]; e as [E][p^3]. Any output pointer may be NULL.
  * Returns 0, or -1 on bad arguments, or -2 when some detJ <= 0 (values still
  * written).
@@ -224,7 +229,7 @@ int or_qdata(int n_elem, int p, int Q, int N, const int32_t *map,
              const double *x0, const double *x, const double *v, const double *e,
              double rho0, double gamma, double q1, double q2,
              const int32_t *elems, int n_sel,
-             double *S, double *mq, double *detJ_out)
+             double *S, double *mq, double *detJ_out, double *dt_out)
 {
     or_basis bs;
     if (make_basis(p, Q, &bs)) return -1;
@@ -255,7 +260,7 @@ int or_qdata(int n_elem, int p, int Q, int N, const int32_t *map,
             const double m = rho0 * dJ0 * w;
             if (mq) mq[(size_t)el * Q3 + q] = m;
             if (detJ_out) detJ_out[(size_t)el * Q3 + q] = dJ;
-            if (!S) continue;
+            if (!S && !dt_out) continue;
             double Ji[3][3];
             inv3(J, dJ, Ji);
             const double rho = m / (w * dJ);
@@ -279,6 +284,11 @@ int or_qdata(int n_elem, int p, int Q, int N, const int32_t *map,
             const double tr = eps[0][0] + eps[1][1] + eps[2][2];
             const double ell = cbrt(dJ) / p;
             const double mu = rho * ell * (q1 * cs + q2 * ell * (tr < 0.0 ? -tr : 0.0));
+            if (dt_out) {
+                const double speed = cs + mu / (rho * ell);
+                dt_out[(size_t)el * Q3 + q] = speed > 0.0 ? ell / speed : INFINITY;
+            }
+            if (!S) continue;
             double sig[3][3];
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b) sig[a][b] = mu * eps[a][b] - (a == b ? pres : 0.0);
@@ -370,6 +380,34 @@ static void mass_elem(const or_tab3 *tb, const double *mq_el, int absmode, doubl
             }
         }
     }
+}
+
+/*
+ * Thermodynamic (L2) mass matrix of every element, the M_E of the energy
+ * equation M_E de/dt = F^T v (Sec. 3.3): ME[e][j][k] = sum_q rho_q detJ_q w_q
+ * phi_j(q) phi_k(q), and rho detJ w = m_q by rho |J| = rho0 |J0|, so M_E does
+ * not change while the mesh moves. phi are evaluated directly at each point.
+ */
+int or_l2_mass(int n_elem, int p, int Q, const double *mq, double *ME)
+{
+    or_basis bs;
+    if (make_basis(p, Q, &bs)) return -1;
+    const int Dl3 = p * p * p, Q3 = Q * Q * Q;
+    for (int el = 0; el < n_elem; ++el) {
+        double *M = ME + (size_t)el * Dl3 * Dl3;
+        memset(M, 0, sizeof(double) * Dl3 * Dl3);
+        for (int qz = 0; qz < Q; ++qz)
+        for (int qy = 0; qy < Q; ++qy)
+        for (int qx = 0; qx < Q; ++qx) {
+            const int q = qx + Q * (qy + Q * qz);
+            const double m = mq[(size_t)el * Q3 + q];
+            for (int j = 0; j < Dl3; ++j) {
+                const double pj = l2_at(&bs, j, qx, qy, qz);
+                for (int k = 0; k < Dl3; ++k) M[j * Dl3 + k] += m * pj * l2_at(&bs, k, qx, qy, qz);
+            }
+        }
+    }
+    return 0;
 }
 
 /* Export the dense element matrices (for tests that assemble or inspect them). */

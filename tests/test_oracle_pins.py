@@ -418,3 +418,94 @@ def test_pa_storage_example():
     ME = O.mass_elem_matrix(p, Q, mq[0])
     assert g["elements"] * ME.size == g["full_assembly_values"]
     assert g["elements"] * mq[0].size == g["partial_assembly_values"]
+
+
+# -------------------------------------------------- moved configurations (x != x0)
+# Sec. 3.3's pointwise mass conservation rho |J| = rho0 |J0| makes the density
+# on a moved mesh rho0 detJ0 / detJ, and the stress acts through the current
+# Jacobian J (S = w detJ sigma J^-T). The pins below move the mesh away from x0
+# and compare with closed forms that a J0-for-J swap, or rho = rho0, would miss.
+def still_gas(mesh, p, Q, x, e0=3.0, q1=0.5, q2=2.0):
+    E, N = mesh.n_elem, mesh.n_nodes
+    e = np.full((E, p ** 3), e0)
+    return O.qdata(mesh.elem_nodes, p, Q, N, mesh.x0, x, np.zeros((3, N)), e, q1=q1, q2=q2)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_affine_motion_transforms_s(p):
+    # x = A x0 + b, v = 0, e = e0: J = A J0, detJ = det(A) detJ0, rho = rho0/det(A),
+    # p = p0/det(A), so S(x) = -p w detJ J^-T = A^-T S(x0) entry by entry.
+    Q = p + 2
+    m = W.cube_mesh(2, p, amp=W.default_amp(p), seed=13)
+    A = np.array([[1.3, 0.2, -0.1], [0.05, 0.9, 0.15], [-0.2, 0.1, 1.1]])
+    x = A @ m.x0 + np.array([[0.3], [-0.2], [0.7]])
+    q0 = still_gas(m, p, Q, m.x0)
+    q1 = still_gas(m, p, Q, x)
+    np.testing.assert_allclose(q1["detJ"], np.linalg.det(A) * q0["detJ"], rtol=1e-13)
+    np.testing.assert_allclose(q1["mq"], q0["mq"], rtol=0, atol=0)   # m_q depends on x0 only
+    expect = np.einsum("kc,ekdq->ecdq", np.linalg.inv(A), q0["S"])  # (A^-T S0)[c][d]
+    scale = np.abs(q0["S"]).max()
+    assert np.abs(q1["S"] - expect).max() < 1e-14 * scale
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("s", [0.8, 1.3])
+def test_dilated_free_stream_faces(p, s):
+    # x = s x0: the gas keeps its mass, so rho = rho0/s^3 and p = p0/s^3 on faces of
+    # area s^2: interior nodes feel nothing and each face x_c = s carries -p0/s
+    # (+p0/s on x_c = 0).
+    Q = p + 2
+    m = W.cube_mesh(3, p, amp=W.default_amp(p), seed=14)
+    p0 = (GAMMA - 1.0) * 3.0
+    y = O.force_mult(m.elem_nodes, p, Q, m.n_nodes, still_gas(m, p, Q, s * m.x0)["S"])
+    for c in range(3):
+        inner = (m.ref[c] > 0) & (m.ref[c] < 1)
+        assert np.abs(y[c, inner]).max() < 1e-13
+        assert abs(y[c, m.ref[c] == 1.0].sum() + p0 / s) < 1e-13
+        assert abs(y[c, m.ref[c] == 0.0].sum() - p0 / s) < 1e-13
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_moved_mesh_virial_is_mass_times_energy(p):
+    # On any valid moved mesh the coordinate functions lie in the H1 space, so
+    # sum_g x_{g,c'} (F 1)_{g,c} = int sigma_{cc'} dx = -(gamma-1) e0 delta_{cc'} int rho dx,
+    # and int rho dx = sum_q rho_q w_q detJ_q = rho0 vol(x0) = 1 whatever x is.
+    Q = p + 2
+    m = W.cube_mesh(3, p, amp=W.default_amp(p), seed=15)
+    rng = np.random.default_rng(p)
+    x = m.x0 + 0.3 * W.default_amp(p) / 3 * (2 * rng.random(m.x0.shape) - 1)   # boundary moves too
+    qd = still_gas(m, p, Q, x)
+    assert qd["detJ"].min() > 0
+    vol = (qd["detJ"] * weights3(Q)[None, :]).sum()
+    assert abs(vol - 1.0) > 1e-6          # the moved volume differs from the initial one
+    y = O.force_mult(m.elem_nodes, p, Q, m.n_nodes, qd["S"])
+    p0 = (GAMMA - 1.0) * 3.0
+    for c in range(3):
+        for cp in range(3):
+            assert abs(np.dot(x[cp], y[c]) - (-p0 if c == cp else 0.0)) < 1e-13
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_linear_velocity_on_dilated_mesh(p):
+    # x = s x0 on an axis-aligned mesh with v = A x: grad v = A, rho = 1/s^3,
+    # l = s h / p, so sigma is constant and (F^T v)_{E,j} = (sigma : A) (s h)^3 W_j.
+    Q, n, s = p + 2, 2, 1.25
+    h = 1.0 / n
+    m = W.cube_mesh(n, p, amp=0.0, permute_seed=6)
+    x = s * m.x0
+    A = np.array([[-0.4, 0.2, 0.1], [0.3, -0.5, -0.2], [0.05, 0.15, 0.25]])
+    v = A @ x
+    e0 = 3.0
+    e = np.full((m.n_elem, p ** 3), e0)
+    S = O.qdata(m.elem_nodes, p, Q, m.n_nodes, m.x0, x, v, e)["S"]
+    z = O.force_mult_T(m.elem_nodes, p, Q, m.n_nodes, S, v)
+    rho = 1.0 / s ** 3
+    eps = 0.5 * (A + A.T)
+    cs = math.sqrt(GAMMA * (GAMMA - 1.0) * e0)
+    ell = s * h / p
+    mu = rho * ell * (0.5 * cs + 2.0 * ell * max(0.0, -np.trace(eps)))
+    sigma = -(GAMMA - 1.0) * rho * e0 * np.eye(3) + mu * eps
+    _, wl = np.polynomial.legendre.leggauss(p)
+    W3 = np.einsum("i,j,k->kji", 0.5 * wl, 0.5 * wl, 0.5 * wl).ravel()
+    expect = np.sum(sigma * A) * (s * h) ** 3 * W3
+    np.testing.assert_allclose(z, np.tile(expect, (m.n_elem, 1)), rtol=0, atol=1e-14)

@@ -13,8 +13,9 @@ from helpers import elems_touching, make_case, oracle_qdata, rel_cw, rel_elem
 
 pytestmark = pytest.mark.gpu
 
-# FP32 unit roundoff is 6e-8; the actions sum 100-1000 terms per output.
-FP32_BOUND = 2e-6
+# FP32 unit roundoff is 6e-8; the actions sum 100-1000 terms per output
+# (measured: at most 1.1e-7 of the term-magnitude scale).
+FP32_BOUND = 1e-6
 # BF16 keeps 8 significant bits (unit roundoff 2^-9): S and the gradient table
 # are each rounded once, products accumulate in FP32.
 BF16_BOUND = 2e-2
