@@ -90,6 +90,10 @@ extern "C" {
                                 branches; a one-unit action (two or three
                                 kernels) is launched directly, which starts
                                 sooner than a graph replay                  */
+#define FE_OPT_STEP     0x8  /* also set up the full Lagrange step
+                                (fe_lagrange_step): every element's inverse
+                                thermodynamic mass M_E^-1 and the step's
+                                workspace, allocated at setup              */
 
 /* kernels timed under FE_OPT_TIMERS */
 #define FE_TIMER_QDATA   0
@@ -150,7 +154,20 @@ typedef struct fe_diag {
     int32_t nonfinite;         /* 1 if the last qdata produced a NaN/Inf    */
     int32_t cg_iters;          /* iterations of the last fe_mass_cg         */
     double cg_rel_res;         /* its final true relative residual          */
+    double dt_est;             /* smallest stable point step of the last
+                                  fe_qdata_update: min over the points of
+                                  l / (c_s + mu / (rho l)), l = detJ^(1/3)/p
+                                  (+inf where no signal moves)             */
 } fe_diag_t;
+
+/* What one fe_lagrange_step did. */
+typedef struct fe_step_info {
+    double dt;                 /* step taken: min(dt_max, cfl * dt_est)     */
+    double dt_est;             /* smallest stable point step of the state at
+                                  the start of the step                    */
+    int32_t cg_iters[2];       /* mass-CG iterations of the two stages      */
+    double cg_rel_res[2];      /* and their true relative residuals         */
+} fe_step_info_t;
 
 /*
  * Build a context: validate the meshes, build the 1-D basis tables, upload the
@@ -242,6 +259,44 @@ int fe_mass_mult(fe_ctx_t *ctx, const double *x, double *y);
 int fe_mass_cg(fe_ctx_t *ctx, const double *b, double *x, const int32_t *ess_dofs,
                int32_t n_ess, double rel_tol, int32_t max_iter, int32_t *iters,
                double *rel_res);
+
+/*
+ * One step of the full Lagrange phase: the semi-discrete system of Sec. 3.3,
+ *     M_v dv/dt = -F 1,   M_E de/dt = F^T v,   dx/dt = v,
+ * (the right sides are Sec. 6's four computations: quadrature data and
+ * viscosity, force actions, CG mass inversion) advanced by a two-stage scheme
+ * from the state (x, v, e) at t to t + dt, in place:
+ *   dt   = min(dt_max, cfl * dt_est), dt_est the smallest stable point step of
+ *          the state at t (see fe_diag_t);
+ *   stage 1, forces of the state at t:
+ *          v_h = v + dt/2 a,  e_h = e + dt/2 M_E^-1 F^T v,  x_h = x + dt/2 v;
+ *   stage 2, forces of the midpoint state:
+ *          v' = v + dt a_h,  vbar = (v + v')/2,
+ *          e' = e + dt M_E^-1 F_h^T vbar,  x' = x + dt vbar,
+ * with a = M_v^-1 (-F 1) solved by fe_mass_cg on the free DOFs (a = 0 on
+ * ess_dofs, rel_tol cg_tol, at most cg_max_iter iterations; the previous
+ * stage's acceleration is the first guess). Averaging the velocity in both
+ * the energy and the position update makes the kinetic energy lost,
+ * vbar^T M_v (v' - v), equal the internal energy gained, 1^T M_E (e' - e),
+ * up to the CG residual. M_E = sum_q m_q phi_j phi_k does not change while
+ * the mesh moves (rho |J| = rho0 |J0|); its element inverses are built at
+ * setup. x, v ([3][N_tot]) and e ([E_tot][Dl^3]) are device memory, updated
+ * in place; v should be 0 on ess_dofs. One dt serves every mesh of the
+ * context. Needs a context set up with FE_OPT_STEP (FE_EINVAL otherwise).
+ * Synchronises the stream; FE_ENOTCONV if a CG solve hit cg_max_iter,
+ * FE_EINVAL if no finite positive dt results (a still, pressureless state
+ * with dt_max = +inf). info may be NULL.
+ */
+int fe_lagrange_step(fe_ctx_t *ctx, double *x, double *v, double *e, const int32_t *ess_dofs,
+                     int32_t n_ess, double cfl, double dt_max, double cg_tol, int32_t cg_max_iter,
+                     fe_step_info_t *info);
+
+/*
+ * Copy the element inverses M_E^-1 of an FE_OPT_STEP context to out (device,
+ * FP64): for each mesh in order, [E][Dl^3][Dl^3] in caller element order.
+ * Synchronises the stream. For tests.
+ */
+int fe_export_l2_mass_inv(fe_ctx_t *ctx, double *out);
 
 /* Diagnostics of the last qdata update and CG solve. Synchronises the stream. */
 int fe_get_diag(fe_ctx_t *ctx, fe_diag_t *diag);

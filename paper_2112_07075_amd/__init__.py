@@ -21,13 +21,13 @@ LIB_PATH = os.path.join(HERE, "libfepa.so")
 FE_OK, FE_EINVAL, FE_ENOMEM, FE_EDEVICE, FE_EUNSUPPORTED, FE_EBADMESH, FE_ENOTCONV = \
     0, -1, -2, -3, -4, -5, -6
 FE_PREC_FP64, FE_PREC_FP32, FE_PREC_BF16 = 0, 1, 2
-FE_OPT_TIMERS, FE_OPT_BATCHED, FE_OPT_GRAPH = 0x1, 0x2, 0x4
+FE_OPT_TIMERS, FE_OPT_BATCHED, FE_OPT_GRAPH, FE_OPT_STEP = 0x1, 0x2, 0x4, 0x8
 FE_TIMER_QDATA, FE_TIMER_FORCE, FE_TIMER_FORCE_T, FE_TIMER_MASS, FE_TIMER_PAIR = 0, 1, 2, 3, 4
 
 ABI_FUNCTIONS = ("fe_pa_setup", "fe_destroy", "fe_query", "fe_mesh_offsets", "fe_qdata_update",
                  "fe_force_mult", "fe_force_mult_T", "fe_force_mult_pair", "fe_mass_mult", "fe_mass_cg",
                  "fe_get_diag", "fe_export_qdata", "fe_timer_read", "fe_timer_reset",
-                 "fe_status_str", "fe_last_error")
+                 "fe_status_str", "fe_last_error", "fe_lagrange_step", "fe_export_l2_mass_inv")
 
 
 class FepaError(RuntimeError):
@@ -59,7 +59,12 @@ class _Info(C.Structure):
 
 class _Diag(C.Structure):
     _fields_ = [("min_detj", C.c_double), ("nonfinite", C.c_int32), ("cg_iters", C.c_int32),
-                ("cg_rel_res", C.c_double)]
+                ("cg_rel_res", C.c_double), ("dt_est", C.c_double)]
+
+
+class _StepInfo(C.Structure):
+    _fields_ = [("dt", C.c_double), ("dt_est", C.c_double), ("cg_iters", C.c_int32 * 2),
+                ("cg_rel_res", C.c_double * 2)]
 
 
 _lib = None
@@ -94,6 +99,9 @@ def lib() -> C.CDLL:
     L.fe_status_str.restype = C.c_char_p
     L.fe_last_error.argtypes = [vp]
     L.fe_last_error.restype = C.c_char_p
+    L.fe_lagrange_step.argtypes = [vp, vp, vp, vp, vp, i32, dbl, dbl, dbl, i32,
+                                   C.POINTER(_StepInfo)]
+    L.fe_export_l2_mass_inv.argtypes = [vp, vp]
     _lib = L
     return L
 
@@ -260,3 +268,20 @@ def fe_timer_reset(ctx: Ctx) -> None:
 
 def fe_status_str(status: int) -> str:
     return lib().fe_status_str(status).decode()
+
+
+def fe_lagrange_step(ctx: Ctx, x, v, e, ess_dofs=None, cfl=0.5, dt_max=float("inf"),
+                     cg_tol=1e-12, cg_max_iter=2000) -> dict:
+    """One step of the full Lagrange phase, x, v, e updated in place; returns
+    {dt, dt_est, cg_iters: [2], cg_rel_res: [2]}."""
+    info = _StepInfo()
+    n_ess = 0 if ess_dofs is None else int(ess_dofs.numel())
+    _check(lib().fe_lagrange_step(ctx.handle, _ptr(x), _ptr(v), _ptr(e), _ptr(ess_dofs), n_ess,
+                                  float(cfl), float(dt_max), float(cg_tol), int(cg_max_iter),
+                                  C.byref(info)), ctx.handle)
+    return {"dt": info.dt, "dt_est": info.dt_est, "cg_iters": list(info.cg_iters),
+            "cg_rel_res": list(info.cg_rel_res)}
+
+
+def fe_export_l2_mass_inv(ctx: Ctx, out) -> None:
+    _check(lib().fe_export_l2_mass_inv(ctx.handle, _ptr(out)), ctx.handle)

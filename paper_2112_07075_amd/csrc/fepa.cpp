@@ -20,6 +20,7 @@
 #include "kern_cg.hpp"
 #include "kern_common.hpp"
 #include "kern_fp64.hpp"
+#include "kern_step.hpp"
 #include "patch.hpp"
 
 using namespace fepa;
@@ -32,6 +33,7 @@ struct MeshRec {
     int E = 0, p = 0, Q = 0, N = 0;
     long long node_off = 0, elem_off = 0, l2_off = 0, S_off = 0, mq_off = 0;
     long long part_off = 0;  // into the CG dot-partial array (one per patch)
+    long long minv_off = 0;  // FE_OPT_STEP: first entry of the mesh's M_E^-1 blocks
     int tab_slot = 0;        // into the table buffer (doubles)
     const KernelSet *ks = nullptr;   // FP64 kernels
     KernelSet kl{};                  // kernels of the context's precision
@@ -125,6 +127,13 @@ struct fe_ctx {
     CgState *cgm = nullptr;
     CgGlobal *glob = nullptr;
     double *part3 = nullptr, *mres = nullptr;
+    // FE_OPT_STEP: element inverses of the L2 mass, the saved state of the
+    // step (xs, vs, es), the stage acceleration (solution of M_v acc = F 1,
+    // kept as the next solve's first guess), F 1, F^T w, the averaged
+    // velocity and the device step size (dtv[0] = dt, dtv[1] = estimate)
+    double *minv = nullptr, *xs = nullptr, *vs = nullptr, *es = nullptr, *acc = nullptr;
+    double *sy = nullptr, *sz = nullptr, *vbar = nullptr, *dtv = nullptr, *h_dt = nullptr;
+    long long minv_len = 0;
     CgState *h_cgm = nullptr;
     CgGlobal *h_glob = nullptr;
     double *h_mres = nullptr;
@@ -185,12 +194,14 @@ void free_all(fe_ctx *c)
     if (c->st) (void)hipStreamSynchronize(c->st);
     void *dptrs[] = {c->S, c->mq, c->tabs, c->mq32, c->tabs32, c->tabsb, c->ref_r, c->ref_d, c->min_key,
                      c->nonfinite, c->r, c->p, c->Ap, c->part, c->part2, c->scal, c->fr, c->cg,
-                     c->bad, c->cgm, c->glob, c->part3, c->mres};
+                     c->bad, c->cgm, c->glob, c->part3, c->mres, c->minv, c->xs, c->vs, c->es,
+                     c->acc, c->sy, c->sz, c->vbar, c->dtv};
     for (void *d : dptrs)
         if (d) (void)hipFree(d);
     for (void *d : c->plan_bufs)
         if (d) (void)hipFree(d);
-    void *hptrs[] = {c->h_cg, c->h_scal, c->h_key, c->h_flag, c->h_cgm, c->h_glob, c->h_mres};
+    void *hptrs[] = {c->h_cg, c->h_scal, c->h_key, c->h_flag, c->h_cgm, c->h_glob, c->h_mres,
+                     c->h_dt};
     for (void *h : hptrs)
         if (h) (void)hipHostFree(h);
     for (auto &tp : c->timers)
@@ -415,7 +426,7 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         return fail(nullptr, FE_EINVAL, "gamma must be > 1 and q1, q2 >= 0%s");
     if (o.precision != FE_PREC_FP64 && o.precision != FE_PREC_FP32 && o.precision != FE_PREC_BF16)
         return fail(nullptr, FE_EUNSUPPORTED, "precision not provided by this build%s");
-    if (o.flags & ~(FE_OPT_TIMERS | FE_OPT_BATCHED | FE_OPT_GRAPH))
+    if (o.flags & ~(FE_OPT_TIMERS | FE_OPT_BATCHED | FE_OPT_GRAPH | FE_OPT_STEP))
         return fail(nullptr, FE_EINVAL, "unknown option flags%s");
     for (int v : {o.tune_nw_force, o.tune_nw_force_t, o.tune_nw_mass})
         if (v != 0 && v != 2 && v != 4 && v != 8)
@@ -592,7 +603,7 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
     }
     if ((rc = dev_alloc(ctx, &ctx->mq, ctx->mq_len, &qb)) ||
         (rc = dev_alloc(ctx, &ctx->tabs, (long long)tab_host.size(), &wb)) ||
-        (rc = dev_alloc(ctx, &ctx->min_key, 1, &wb)) || (rc = dev_alloc(ctx, &ctx->nonfinite, 1, &wb)) ||
+        (rc = dev_alloc(ctx, &ctx->min_key, 2, &wb)) || (rc = dev_alloc(ctx, &ctx->nonfinite, 1, &wb)) ||
         (rc = dev_alloc(ctx, &ctx->r, 3 * ctx->N_tot, &wb)) || (rc = dev_alloc(ctx, &ctx->p, 3 * ctx->N_tot, &wb)) ||
         (rc = dev_alloc(ctx, &ctx->Ap, 3 * ctx->N_tot, &wb)) ||
         (rc = dev_alloc(ctx, &ctx->part2, kVecBlocks, &wb)) || (rc = dev_alloc(ctx, &ctx->scal, 8, &wb)) ||
@@ -614,9 +625,27 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
             return bail(FE_EDEVICE);
         }
     }
+    if (o.flags & FE_OPT_STEP) {
+        for (MeshRec &r : ctx->mesh) {
+            r.minv_off = ctx->minv_len;
+            ctx->minv_len += (long long)r.E * r.p * r.p * r.p * r.p * r.p * r.p;
+        }
+        const long long n3 = 3 * ctx->N_tot;
+        if ((rc = dev_alloc(ctx, &ctx->minv, ctx->minv_len, &wb)) || (rc = dev_alloc(ctx, &ctx->xs, n3, &wb)) ||
+            (rc = dev_alloc(ctx, &ctx->vs, n3, &wb)) || (rc = dev_alloc(ctx, &ctx->es, ctx->L2_tot, &wb)) ||
+            (rc = dev_alloc(ctx, &ctx->acc, n3, &wb)) || (rc = dev_alloc(ctx, &ctx->sy, n3, &wb)) ||
+            (rc = dev_alloc(ctx, &ctx->sz, ctx->L2_tot, &wb)) || (rc = dev_alloc(ctx, &ctx->vbar, n3, &wb)) ||
+            (rc = dev_alloc(ctx, &ctx->dtv, 2, &wb)))
+            return bail(rc);
+        launch_fill(ctx->acc, n3, 0.0, ctx->st);
+        if (hipHostMalloc((void **)&ctx->h_dt, 2 * sizeof(double)) != hipSuccess) {
+            ctx->err = "pinned host allocation failed";
+            return bail(FE_ENOMEM);
+        }
+    }
     if (hipHostMalloc((void **)&ctx->h_cg, sizeof(CgState)) != hipSuccess ||
         hipHostMalloc((void **)&ctx->h_scal, 8 * sizeof(double)) != hipSuccess ||
-        hipHostMalloc((void **)&ctx->h_key, sizeof(long long)) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->h_key, 2 * sizeof(long long)) != hipSuccess ||
         hipHostMalloc((void **)&ctx->h_flag, sizeof(int)) != hipSuccess) {
         ctx->err = "pinned host allocation failed";
         return bail(FE_ENOMEM);
@@ -852,6 +881,18 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         std::snprintf(buf, sizeof(buf), "initial mesh has min detJ = %.3e", min0);
         ctx->err = buf;
         return bail(FE_EBADMESH);
+    }
+    if (o.flags & FE_OPT_STEP) {
+        // M_E^-1 of every element from m_q (fixed while the mesh moves)
+        for (const MeshRec &r : ctx->mesh) {
+            const int perm_base = ctx->batched ? (int)(r.l2_off / ((long long)r.p * r.p * r.p)) : 0;
+            launch_l2_mass_inv(r.p, r.Q, ctx->mq + r.mq_off, r.pd.perm, perm_base, r.E,
+                               ctx->tabs + r.tab_slot, ctx->minv + r.minv_off, ctx->st);
+        }
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->st) != hipSuccess) {
+            ctx->err = "set-up kernels failed";
+            return bail(FE_EDEVICE);
+        }
     }
     *out = ctx;
     return FE_OK;
@@ -1200,13 +1241,79 @@ int fe_mass_cg(fe_ctx_t *ctx, const double *b, double *x, const int32_t *ess_dof
     return FE_OK;
 }
 
+int fe_lagrange_step(fe_ctx_t *ctx, double *x, double *v, double *e, const int32_t *ess_dofs,
+                     int32_t n_ess, double cfl, double dt_max, double cg_tol, int32_t cg_max_iter,
+                     fe_step_info_t *info)
+{
+    if (!ctx) return FE_EINVAL;
+    if (!(ctx->opts.flags & FE_OPT_STEP)) return fail(ctx, FE_EINVAL, "context set up without FE_OPT_STEP%s");
+    if (!x || !v || !e) return fail(ctx, FE_EINVAL, "NULL state vector%s");
+    if ((const void *)x == (const void *)v) return fail(ctx, FE_EINVAL, "x aliases v%s");
+    if (!(cfl > 0.0) || !(dt_max > 0.0)) return fail(ctx, FE_EINVAL, "cfl and dt_max must be > 0%s");
+    const long long n3 = 3 * ctx->N_tot;
+    hipStream_t st = ctx->st;
+    fe_step_info_t out{};
+    // the state at the start of the step
+    HIP_OK(hipMemcpyAsync(ctx->xs, x, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipMemcpyAsync(ctx->vs, v, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipMemcpyAsync(ctx->es, e, ctx->L2_tot * sizeof(double), hipMemcpyDeviceToDevice, st));
+    auto l2_update = [&](double frac) {
+        for (const MeshRec &r : ctx->mesh) {
+            const int N = r.p * r.p * r.p;
+            launch_rk_l2(ctx->es + r.l2_off, ctx->minv + r.minv_off, ctx->sz + r.l2_off, e + r.l2_off,
+                         (long long)r.E * N, N, ctx->dtv, frac, st);
+        }
+    };
+    // stage 1: forces of the state n; dt from its smallest stable point step
+    int rc = fe_qdata_update(ctx, ctx->xs, ctx->vs, ctx->es);
+    if (rc) return rc;
+    launch_step_dt(ctx->min_key, cfl, dt_max, ctx->dtv, st);
+    HIP_OK(hipMemcpyAsync(ctx->h_dt, ctx->dtv, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    if ((rc = fe_force_mult_pair(ctx, nullptr, ctx->sy, ctx->vs, ctx->sz))) return rc;
+    int it = 0;
+    double res = 0.0;
+    rc = fe_mass_cg(ctx, ctx->sy, ctx->acc, ess_dofs, n_ess, cg_tol, cg_max_iter, &it, &res);
+    out.cg_iters[0] = it;
+    out.cg_rel_res[0] = res;
+    if (rc) return rc;  // fe_mass_cg synchronised: h_dt is valid below
+    out.dt = ctx->h_dt[0];
+    out.dt_est = ctx->h_dt[1];
+    if (!(out.dt > 0.0) || !std::isfinite(out.dt))
+        return fail(ctx, FE_EINVAL, "no finite positive step (set dt_max)%s");
+    launch_rk_h1(ctx->vs, ctx->xs, ctx->acc, v, x, nullptr, n3, ctx->dtv, 0.5, st);
+    l2_update(0.5);
+    // stage 2: forces of the midpoint state; v' and vbar, then e' and x' with vbar
+    if ((rc = fe_qdata_update(ctx, x, v, e))) return rc;
+    if ((rc = fe_force_mult(ctx, nullptr, ctx->sy))) return rc;
+    rc = fe_mass_cg(ctx, ctx->sy, ctx->acc, ess_dofs, n_ess, cg_tol, cg_max_iter, &it, &res);
+    out.cg_iters[1] = it;
+    out.cg_rel_res[1] = res;
+    if (rc) return rc;
+    launch_rk_h1(ctx->vs, ctx->xs, ctx->acc, v, x, ctx->vbar, n3, ctx->dtv, 1.0, st);
+    if ((rc = fe_force_mult_T(ctx, ctx->vbar, ctx->sz))) return rc;
+    l2_update(1.0);
+    HIP_OK(hipGetLastError());
+    if (info) *info = out;
+    return FE_OK;
+}
+
+int fe_export_l2_mass_inv(fe_ctx_t *ctx, double *out)
+{
+    if (!ctx || !out) return FE_EINVAL;
+    if (!(ctx->opts.flags & FE_OPT_STEP)) return fail(ctx, FE_EINVAL, "context set up without FE_OPT_STEP%s");
+    HIP_OK(hipMemcpyAsync(out, ctx->minv, ctx->minv_len * sizeof(double), hipMemcpyDeviceToDevice, ctx->st));
+    HIP_OK(hipStreamSynchronize(ctx->st));
+    return FE_OK;
+}
+
 int fe_get_diag(fe_ctx_t *ctx, fe_diag_t *diag)
 {
     if (!ctx || !diag) return FE_EINVAL;
-    HIP_OK(hipMemcpyAsync(ctx->h_key, ctx->min_key, sizeof(long long), hipMemcpyDeviceToHost, ctx->st));
+    HIP_OK(hipMemcpyAsync(ctx->h_key, ctx->min_key, 2 * sizeof(long long), hipMemcpyDeviceToHost, ctx->st));
     HIP_OK(hipMemcpyAsync(ctx->h_flag, ctx->nonfinite, sizeof(int), hipMemcpyDeviceToHost, ctx->st));
     HIP_OK(hipStreamSynchronize(ctx->st));
-    diag->min_detj = key_to_double(*ctx->h_key);
+    diag->min_detj = key_to_double(ctx->h_key[0]);
+    diag->dt_est = key_to_double(ctx->h_key[1]);
     diag->nonfinite = *ctx->h_flag;
     diag->cg_iters = ctx->last_iters;
     diag->cg_rel_res = ctx->last_res;

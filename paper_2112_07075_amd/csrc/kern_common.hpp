@@ -5,6 +5,11 @@
 
 namespace fepa {
 
+// The (order, points per direction) pairs the library instantiates: p = 1..4
+// with Q = p+1 .. p+3.
+#define FEPA_PQ_LIST(X) \
+    X(1, 2) X(1, 3) X(1, 4) X(2, 3) X(2, 4) X(2, 5) X(3, 4) X(3, 5) X(3, 6) X(4, 5) X(4, 6) X(4, 7)
+
 // Layout of one (p, Q) basis table block in device memory (FP64):
 //   B [Q][D]  H1 Lagrange values at the Gauss-Legendre points
 //   G [Q][D]  their derivatives
@@ -62,11 +67,15 @@ __host__ __device__ constexpr MfmaLayout mfma_layout(int D, int Q)
     return MfmaLayout{q3, q3p, ns, d3, nt, tabf, nfrag, tabf * 4 + nfrag * 16};
 }
 
-// Order-preserving map of a double onto int64 (for atomicMin of detJ).
+// Order-preserving map of a double onto int64 (for atomicMin of detJ), and back.
 __device__ __forceinline__ long long ordered_key(double d)
 {
     long long b = __double_as_longlong(d);
     return b >= 0 ? b : (b ^ 0x7fffffffffffffffLL);
+}
+__device__ __forceinline__ double key_value(long long k)
+{
+    return __longlong_as_double(k >= 0 ? k : (k ^ 0x7fffffffffffffffLL));
 }
 
 // ---------------------------------------------------------------- patches

@@ -1321,7 +1321,10 @@ __global__ void k_unpermute_rows(const R *__restrict__ in, const int32_t *__rest
 //   grad v = (grad_xi v) J^-1; eps = sym grad v; l = detJ^(1/3)/p;
 //   mu = rho l (q1 c_s + q2 l max(0, -tr eps)); sigma = -p I + mu eps;
 //   S = w detJ sigma J^-T.
-// INIT mode writes m_q = rho0 detJ0 w instead of S.
+// min_key[0] receives the smallest detJ and min_key[1] the smallest stable
+// explicit step of a point, l / (c_s + mu / (rho l)): the time a signal at
+// the sound speed plus the viscous speed needs to cross the point's length l.
+// INIT mode writes m_q = rho0 detJ0 w instead of S (and no step).
 template <int D, int Q, bool INIT, typename RS>
 __global__ void __launch_bounds__(pt_ne(Q) * Q * Q * Q)
 k_qdata(const double *__restrict__ x, const double *__restrict__ v,
@@ -1340,7 +1343,7 @@ k_qdata(const double *__restrict__ x, const double *__restrict__ v,
     __shared__ double sX[NE][NF][2][D * D * Q];
     __shared__ double sY[NE][NF][3][D * QQ];
     __shared__ double sE[NE][DL3 > 0 ? DL3 : 1];
-    __shared__ long long sMin;
+    __shared__ long long sMin, sDt;
     __shared__ int sBad;
 
     const int tid = threadIdx.x, le = tid / Q3, q = tid % Q3;
@@ -1350,7 +1353,7 @@ k_qdata(const double *__restrict__ x, const double *__restrict__ v,
 
     for (int k = tid; k < T::SIZE; k += blockDim.x) sTab[k] = tab[k];
     if (tid == 0) {
-        sMin = 0x7fffffffffffffffLL;
+        sMin = sDt = 0x7fffffffffffffffLL;
         sBad = 0;
     }
     for (int k = q; k < NF * D3; k += Q3) {
@@ -1459,6 +1462,8 @@ k_qdata(const double *__restrict__ x, const double *__restrict__ v,
         const double tr = eps[0][0] + eps[1][1] + eps[2][2];
         const double ell = cbrt(detJ) * prm.inv_order;
         const double mu = rho * ell * (prm.q1 * cs + prm.q2 * ell * fmax(-tr, 0.0));
+        const double speed = cs + mu / (rho * ell);
+        atomicMin(&sDt, ordered_key(speed > 0.0 ? ell / speed : INFINITY));
         const double wd = w * detJ;
         constexpr int SQ = s_stride<RS>(Q);
         RS *__restrict__ Se = S + el * 9 * SQ;
@@ -1484,6 +1489,7 @@ k_qdata(const double *__restrict__ x, const double *__restrict__ v,
     __syncthreads();
     if (tid == 0) {
         atomicMin(min_key, sMin);
+        if (!INIT) atomicMin(min_key + 1, sDt);
         if (sBad) atomicOr(nonfinite, 1);
     }
 }
@@ -1658,9 +1664,6 @@ struct Launch {
     }
 };
 
-#define FEPA_PQ_LIST(X) \
-    X(1, 2) X(1, 3) X(1, 4) X(2, 3) X(2, 4) X(2, 5) X(3, 4) X(3, 5) X(3, 6) X(4, 5) X(4, 6) X(4, 7)
-
 template <typename R>
 static const KernelSet *kernels_for(int p, int Q)
 {
@@ -1798,7 +1801,7 @@ void launch_unpermute_rows(const void *in, bool in_f32, const int32_t *perm, lon
 __global__ void k_reset_diag(long long *__restrict__ key, int *__restrict__ flag)
 {
     if (threadIdx.x == 0) {
-        if (key) *key = 0x7fffffffffffffffLL;
+        if (key) key[0] = key[1] = 0x7fffffffffffffffLL;
         if (flag) *flag = 0;
     }
 }

@@ -95,7 +95,8 @@ void launch_zero_nodes(const int32_t *nodes, int n, double *y, long long ncomp, 
 void launch_unpermute_rows(const void *in, bool in_f32, const int32_t *perm, long long rows,
                            int len, double *out, hipStream_t st);
 void launch_fill(double *y, long long n, double val, hipStream_t st);
-// *key = INT64_MAX (empty min of ordered detJ keys), *flag = 0; either may be NULL.
+// key[0] = key[1] = INT64_MAX (empty minima of ordered detJ and time-step
+// keys), *flag = 0; either pointer may be NULL.
 void launch_reset_diag(long long *key, int *flag, hipStream_t st);
 
 }  // namespace fepa
