@@ -55,6 +55,9 @@ def lib():
         for fn in (L.or_force_mult, L.or_force_mult_T, L.or_mass_mult):
             fn.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _ip, _dp, _vp, _vp, C.c_int,
                            C.c_int, _dp]
+        L.or_stiff_elem_matrix.argtypes = [C.c_int, C.c_int, C.c_int, _ip, _dp, _vp, _dp]
+        L.or_stiff_mult.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _ip, _dp, _vp, _dp, _vp,
+                                    C.c_int, C.c_int, _dp]
         L.or_mass_cg.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _ip, _dp, _dp, _dp, _vp,
                                  C.c_int, C.c_double, C.c_int, C.POINTER(C.c_int),
                                  C.POINTER(C.c_double)]
@@ -174,6 +177,33 @@ def mass_mult(mesh_map, p, Q, N, mq, x, elems=None, absmode=False):
                             int(absmode), y)
     if rc:
         raise OracleError(f"or_mass_mult failed: {rc}")
+    return y.reshape(3, N)
+
+
+def stiff_elem_matrix(p, Q, nodes, x, kappa_el=None):
+    """Dense element stiffness K_E [D^3][D^3] of the element with node ids `nodes` on positions x."""
+    D3 = (p + 1) ** 3
+    x = _f64(x)
+    KE = np.zeros(D3 * D3)
+    rc = lib().or_stiff_elem_matrix(p, Q, x.shape[-1], _i32(nodes), x.ravel(),
+                                    _ptr(_f64(kappa_el)), KE)
+    if rc:
+        raise OracleError(f"or_stiff_elem_matrix failed: {rc}")
+    return KE.reshape(D3, D3)
+
+
+def stiff_mult(mesh_map, p, Q, N, x, u, kappa=None, elems=None, absmode=False):
+    """y = K u ([3][N]): the stiffness (diffusion) operator int kappa grad w_i . grad w_j
+    on the mesh x, per component; kappa [E][Q^3] or None for 1."""
+    mesh_map = _i32(mesh_map)
+    y = np.zeros(3 * N)
+    el = _i32(elems)
+    kap = _f64(kappa)
+    rc = lib().or_stiff_mult(mesh_map.shape[0], p, Q, N, mesh_map, _f64(x).ravel(),
+                             _ptr(None if kap is None else kap.ravel()), _f64(u).ravel(),
+                             _ptr(el), 0 if el is None else len(el), int(absmode), y)
+    if rc:
+        raise OracleError(f"or_stiff_mult failed: {rc}")
     return y.reshape(3, N)
 
 

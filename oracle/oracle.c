@@ -525,6 +525,105 @@ int or_mass_mult(int n_elem, int p, int Q, int N, const int32_t *map, const doub
     return 0;
 }
 
+/* ------------------------------------------------- stiffness (diffusion) */
+
+/*
+ * Stiffness (diffusion) operator of the hyper-viscosity term (Sec. 2.1 names
+ * the "stiffness matrix" operator the shock-capturing hyper-viscosity needs;
+ * Sec. 6 the diffusion integrator used in the artificial-viscosity
+ * calculations), on the kinematic H1 space, one block per velocity component
+ * like M_v:
+ *     K[i][j] = int kappa grad w_i . grad w_j dx
+ *             = sum_q w_q kappa_q detJ_q (J_q^-T grad_xi w_i) . (J_q^-T grad_xi w_j)
+ * on the current mesh x. kappa is given per quadrature point ([E][Q^3]) or
+ * NULL for kappa = 1. The physical gradients are formed at each point
+ * directly from the definition, the element matrix is dense, and
+ * y_c = sum_E R_E^T K_E R_E u_c. With absmode the same loops run on
+ * magnitudes (the scale of the rounding error).
+ */
+static void stiff_elem(const or_basis *bs, const or_tab3 *tb, const int32_t *nodes, int N,
+                       const double *x, const double *kap_el, int absmode, double *KE)
+{
+    const int Q = bs->Q, D3 = tb->D3;
+    memset(KE, 0, sizeof(double) * D3 * D3);
+    double *gphys = (double *)malloc(sizeof(double) * 3 * D3);
+    for (int qz = 0; qz < Q; ++qz)
+    for (int qy = 0; qy < Q; ++qy)
+    for (int qx = 0; qx < Q; ++qx) {
+        const int q = qx + Q * (qy + Q * qz);
+        const double w = bs->wq[qx] * bs->wq[qy] * bs->wq[qz];
+        double J[3][3] = {{0}};
+        for (int i = 0; i < D3; ++i) {
+            const double *g = &tb->hg3[(q * D3 + i) * 3];
+            for (int c = 0; c < 3; ++c)
+                for (int d = 0; d < 3; ++d) J[c][d] += x[(size_t)c * N + nodes[i]] * g[d];
+        }
+        const double dJ = det3(J);
+        double Ji[3][3];
+        inv3(J, dJ, Ji);
+        /* grad w_i = J^-T grad_xi w_i: component k = sum_d Ji[d][k] g[d] */
+        for (int i = 0; i < D3; ++i) {
+            const double *g = &tb->hg3[(q * D3 + i) * 3];
+            for (int k = 0; k < 3; ++k)
+                gphys[3 * i + k] = Ji[0][k] * g[0] + Ji[1][k] * g[1] + Ji[2][k] * g[2];
+        }
+        const double kap = kap_el ? kap_el[q] : 1.0;
+        const double f = w * kap * dJ;
+        for (int i = 0; i < D3; ++i)
+            for (int j = 0; j < D3; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < 3; ++k)
+                    s += absmode ? fabs(gphys[3 * i + k]) * fabs(gphys[3 * j + k])
+                                 : gphys[3 * i + k] * gphys[3 * j + k];
+                KE[i * D3 + j] += absmode ? fabs(f) * s : f * s;
+            }
+    }
+    free(gphys);
+}
+
+int or_stiff_elem_matrix(int p, int Q, int N, const int32_t *nodes, const double *x,
+                         const double *kap_el, double *KE)
+{
+    or_basis bs;
+    or_tab3 tb = {0};
+    if (make_basis(p, Q, &bs)) return -1;
+    if (make_tab3(&bs, &tb)) { free_tab3(&tb); return -3; }
+    stiff_elem(&bs, &tb, nodes, N, x, kap_el, 0, KE);
+    free_tab3(&tb);
+    return 0;
+}
+
+/* y = K u for the three components of u ([3][N]); y overwritten. */
+int or_stiff_mult(int n_elem, int p, int Q, int N, const int32_t *map, const double *x,
+                  const double *kappa, const double *u, const int32_t *elems, int n_sel,
+                  int absmode, double *y)
+{
+    or_basis bs;
+    if (make_basis(p, Q, &bs)) return -1;
+    const int D = bs.D, D3 = D * D * D, Q3 = Q * Q * Q;
+    or_tab3 tb = {0};
+    double *KE = (double *)malloc(sizeof(double) * D3 * D3);
+    if (!KE || make_tab3(&bs, &tb)) { free(KE); free_tab3(&tb); return -3; }
+    memset(y, 0, sizeof(double) * 3 * (size_t)N);
+    for (int k = 0; k < NLOOP; ++k) {
+        const int el = ELEM(k);
+        const int32_t *nodes = map + (size_t)el * D3;
+        stiff_elem(&bs, &tb, nodes, N, x, kappa ? kappa + (size_t)el * Q3 : NULL, absmode, KE);
+        for (int c = 0; c < 3; ++c)
+            for (int i = 0; i < D3; ++i) {
+                double acc = 0.0;
+                for (int j = 0; j < D3; ++j) {
+                    const double uj = u[(size_t)c * N + nodes[j]];
+                    acc += KE[i * D3 + j] * (absmode ? fabs(uj) : uj);
+                }
+                y[(size_t)c * N + nodes[i]] += acc;
+            }
+    }
+    free(KE);
+    free_tab3(&tb);
+    return 0;
+}
+
 /* ------------------------------------------------------------- mass CG */
 
 static double dot(const double *a, const double *b, size_t n)
