@@ -55,6 +55,8 @@ def lib():
         for fn in (L.or_force_mult, L.or_force_mult_T, L.or_mass_mult):
             fn.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _ip, _dp, _vp, _vp, C.c_int,
                            C.c_int, _dp]
+        L.or_qdata_mm.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _ip, C.c_int, _dp, _dp, _dp,
+                                  _dp, _dp, _dp, _dp, C.c_double, C.c_double, _dp, _vp]
         L.or_stiff_elem_matrix.argtypes = [C.c_int, C.c_int, C.c_int, _ip, _dp, _vp, _dp]
         L.or_stiff_mult.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _ip, _dp, _vp, _dp, _vp,
                                     C.c_int, C.c_int, _dp]
@@ -125,6 +127,27 @@ def qdata(mesh_map, p, Q, N, x0, x, v, e, rho0=1.0, gamma=5.0 / 3.0, q1=0.5, q2=
     if "S" in out:
         out["S"] = out["S"].reshape(E, 3, 3, Q3)
     return out
+
+
+def qdata_mm(mesh_map, p, Q, N, x0, x, v, e, eta0, gamma, rho0, q1=0.5, q2=2.0, want_mq=False):
+    """Multi-material quadrature data: S [K][E][3][3][Q^3] of F_k (eta_k sigma_k),
+    from e, eta0 [K][E][p^3] and per-material gamma, rho0 ([K]); with want_mq
+    also the material masses per point mqk [K][E][Q^3]. Returns S or (S, mqk)."""
+    mesh_map = _i32(mesh_map)
+    E = mesh_map.shape[0]
+    gamma, rho0 = _f64(np.atleast_1d(gamma)), _f64(np.atleast_1d(rho0))
+    K = len(gamma)
+    Q3 = Q ** 3
+    S = np.zeros(K * E * 9 * Q3)
+    mq = np.zeros(K * E * Q3) if want_mq else None
+    rc = lib().or_qdata_mm(E, p, Q, N, mesh_map, K, _f64(x0), _f64(x), _f64(v),
+                           _f64(e).ravel(), _f64(eta0).ravel(), gamma, rho0, q1, q2, S, _ptr(mq))
+    if rc == -2:
+        raise OracleError("non-positive Jacobian determinant")
+    if rc:
+        raise OracleError(f"or_qdata_mm failed: {rc}")
+    S = S.reshape(K, E, 3, 3, Q3)
+    return (S, mq.reshape(K, E, Q3)) if want_mq else S
 
 
 def force_elem_matrix(p, Q, S_el):

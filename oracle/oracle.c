@@ -303,6 +303,97 @@ int or_qdata(int n_elem, int p, int Q, int N, const int32_t *map,
     return bad ? -2 : 0;
 }
 
+/* ------------------------------------------------------- multi-material */
+
+/*
+ * Quadrature data of the multi-material force operators F_k (Sec. 2.1's
+ * multi-material momentum and energy equations, rho dv/dt = div sum_k eta_k
+ * sigma_k and eta_k rho_k de_k/dt = eta_k sigma_k : grad v; Sec. 3.3's
+ * semi-discrete M_v dv/dt = -sum_k F_k 1, M_E,k de_k/dt = F_k^T v - c_k,
+ * eta_k rho_k |J| = eta_k0 rho_k0 |J0|), for K materials:
+ *   F_k[(i,c), j] = int eta_k sigma_k : grad(w_i e_c) phi_j dx
+ *   S_k[e][c][d][q] = w_q detJ_q sum_m (eta_k sigma_k)[c][m] Jinv[d][m]
+ * Readings: no closure model (alpha_k = 0, c_k = 0), so eta_k = eta_k0 along
+ * the motion and rho_k = rho_k0 detJ0/detJ; eta_k0 is an L2 field (the
+ * thermodynamic space, like e_k) with coefficients eta0[k][e][j];
+ * sigma_k = -p_k I + mu_k eps with p_k = (gamma_k - 1) rho_k e_k and the
+ * scalar viscosity mu_k = rho_k l (q1 c_s,k + q2 l max(0, -tr eps)),
+ * c_s,k = sqrt(gamma_k (gamma_k - 1) max(e_k, 0)), l = detJ^(1/3)/p.
+ * Also mqk[k][e][q] = eta_k0 rho_k0 detJ0 w (the material's mass per point)
+ * when mqk != NULL. Inputs e[k][e][j], eta0[k][e][j] ([K][E][p^3]),
+ * gamma[k], rho0[k]. Returns 0, -1 on bad arguments, -2 if some detJ <= 0.
+ */
+int or_qdata_mm(int n_elem, int p, int Q, int N, const int32_t *map, int K,
+                const double *x0, const double *x, const double *v, const double *e,
+                const double *eta0, const double *gamma, const double *rho0, double q1, double q2,
+                double *S, double *mqk)
+{
+    or_basis bs;
+    if (make_basis(p, Q, &bs) || K < 1) return -1;
+    const int D = bs.D, D3 = D * D * D, Dl3 = p * p * p, Q3 = Q * Q * Q;
+    const size_t Sk = (size_t)n_elem * 9 * Q3, Mk = (size_t)n_elem * Q3, Lk = (size_t)n_elem * Dl3;
+    int bad = 0;
+    for (int el = 0; el < n_elem; ++el) {
+        const int32_t *nodes = map + (size_t)el * D3;
+        for (int qz = 0; qz < Q; ++qz)
+        for (int qy = 0; qy < Q; ++qy)
+        for (int qx = 0; qx < Q; ++qx) {
+            const int q = qx + Q * (qy + Q * qz);
+            const double w = bs.wq[qx] * bs.wq[qy] * bs.wq[qz];
+            double J[3][3] = {{0}}, J0[3][3] = {{0}}, Gv[3][3] = {{0}};
+            for (int i = 0; i < D3; ++i) {
+                double val, g[3];
+                h1_at(&bs, i, qx, qy, qz, &val, g);
+                for (int c = 0; c < 3; ++c)
+                    for (int d = 0; d < 3; ++d) {
+                        J[c][d] += x[(size_t)c * N + nodes[i]] * g[d];
+                        J0[c][d] += x0[(size_t)c * N + nodes[i]] * g[d];
+                        Gv[c][d] += v[(size_t)c * N + nodes[i]] * g[d];
+                    }
+            }
+            const double dJ = det3(J), dJ0 = det3(J0);
+            if (!(dJ > 0.0)) bad = 1;
+            double Ji[3][3];
+            inv3(J, dJ, Ji);
+            double L[3][3];
+            for (int c = 0; c < 3; ++c)
+                for (int m = 0; m < 3; ++m) {
+                    double s = 0.0;
+                    for (int d = 0; d < 3; ++d) s += Gv[c][d] * Ji[d][m];
+                    L[c][m] = s;
+                }
+            double eps[3][3];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) eps[a][b] = 0.5 * (L[a][b] + L[b][a]);
+            const double tr = eps[0][0] + eps[1][1] + eps[2][2];
+            const double ell = cbrt(dJ) / p;
+            for (int k = 0; k < K; ++k) {
+                double eta = 0.0, ek = 0.0;
+                for (int j = 0; j < Dl3; ++j) {
+                    const double phi = l2_at(&bs, j, qx, qy, qz);
+                    eta += eta0[k * Lk + (size_t)el * Dl3 + j] * phi;
+                    ek += e[k * Lk + (size_t)el * Dl3 + j] * phi;
+                }
+                const double rho = rho0[k] * dJ0 / dJ;  /* eta_k rho_k |J| = eta_k0 rho_k0 |J0| */
+                const double pk = (gamma[k] - 1.0) * rho * ek;
+                const double cs = sqrt(gamma[k] * (gamma[k] - 1.0) * (ek > 0.0 ? ek : 0.0));
+                const double mu = rho * ell * (q1 * cs + q2 * ell * (tr < 0.0 ? -tr : 0.0));
+                if (mqk) mqk[k * Mk + (size_t)el * Q3 + q] = eta * rho0[k] * dJ0 * w;
+                for (int c = 0; c < 3; ++c)
+                    for (int d = 0; d < 3; ++d) {
+                        double s = 0.0;
+                        for (int m = 0; m < 3; ++m) {
+                            const double sig = mu * eps[c][m] - (c == m ? pk : 0.0);
+                            s += eta * sig * Ji[d][m];
+                        }
+                        S[k * Sk + (((size_t)el * 3 + c) * 3 + d) * Q3 + q] = w * dJ * s;
+                    }
+            }
+        }
+    }
+    return bad ? -2 : 0;
+}
+
 /* -------------------------------------------------------- element matrices */
 
 /* 3-D basis tables at every quadrature point, evaluated directly as products of
