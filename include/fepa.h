@@ -234,6 +234,25 @@ int fe_force_mult_T(fe_ctx_t *ctx, const double *v, double *z);
  */
 int fe_force_mult_pair(fe_ctx_t *ctx, const double *e, double *y, const double *v, double *z);
 
+/*
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): fe_force_mult_pair with
+ * the shared-node partials of the patch kernels held in a static device
+ * array of this library (32 MiB per GPU, kept until the process ends)
+ * instead of the context's own buffer. Same arguments, layouts, results and
+ * errors as fe_force_mult_pair; the call allocates nothing and never builds
+ * or replays a graph (its kernels are launched directly on the context
+ * stream). Every partial it reads is written by the same call, so nothing
+ * must start at zero. FE_EINVAL (with fe_last_error naming the size) when
+ * one launch unit's partials (3 doubles per shared-node entry) exceed
+ * 32 MiB; FE_EDEVICE if the array's device address could not be looked up
+ * at set-up. All calls on one GPU share the array: calls that overlap in
+ * time on one GPU (other streams, other contexts, other host threads) race
+ * and must be ordered by the caller. Asynchronous.
+ */
+int fe_force_mult_pair_noalloc(fe_ctx_t *ctx, const double *e, double *y, const double *v,
+                               double *z);
+
 /* Mass action y = M_v x (the kinematic mass matrix of Sec. 3.3's momentum
  * equation, applied as Sec. 3.2's element mass matrices by sum factorisation;
  * [3][N_tot] device in and out; y overwritten). Asynchronous. */

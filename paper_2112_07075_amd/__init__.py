@@ -27,7 +27,8 @@ FE_TIMER_QDATA, FE_TIMER_FORCE, FE_TIMER_FORCE_T, FE_TIMER_MASS, FE_TIMER_PAIR =
 ABI_FUNCTIONS = ("fe_pa_setup", "fe_destroy", "fe_query", "fe_mesh_offsets", "fe_qdata_update",
                  "fe_force_mult", "fe_force_mult_T", "fe_force_mult_pair", "fe_mass_mult", "fe_mass_cg",
                  "fe_get_diag", "fe_export_qdata", "fe_timer_read", "fe_timer_reset",
-                 "fe_status_str", "fe_last_error", "fe_lagrange_step", "fe_export_l2_mass_inv")
+                 "fe_status_str", "fe_last_error", "fe_lagrange_step", "fe_export_l2_mass_inv",
+                 "fe_force_mult_pair_noalloc")
 
 
 class FepaError(RuntimeError):
@@ -89,6 +90,7 @@ def lib() -> C.CDLL:
     L.fe_force_mult.argtypes = [vp, vp, vp]
     L.fe_force_mult_T.argtypes = [vp, vp, vp]
     L.fe_force_mult_pair.argtypes = [vp, vp, vp, vp, vp]
+    L.fe_force_mult_pair_noalloc.argtypes = [vp, vp, vp, vp, vp]
     L.fe_mass_mult.argtypes = [vp, vp, vp]
     L.fe_mass_cg.argtypes = [vp, vp, vp, vp, i32, dbl, i32, C.POINTER(i32), C.POINTER(dbl)]
     L.fe_get_diag.argtypes = [vp, C.POINTER(_Diag)]
@@ -228,6 +230,11 @@ def fe_force_mult_T(ctx: Ctx, v, z) -> None:
 
 def fe_force_mult_pair(ctx: Ctx, e, y, v, z) -> None:
     _check(lib().fe_force_mult_pair(ctx.handle, _ptr(e), _ptr(y), _ptr(v), _ptr(z)), ctx.handle)
+
+
+def fe_force_mult_pair_noalloc(ctx: Ctx, e, y, v, z) -> None:
+    _check(lib().fe_force_mult_pair_noalloc(ctx.handle, _ptr(e), _ptr(y), _ptr(v), _ptr(z)),
+           ctx.handle)
 
 
 def fe_mass_mult(ctx: Ctx, x, y) -> None:

@@ -21,6 +21,7 @@
 #include "kern_common.hpp"
 #include "kern_fp64.hpp"
 #include "kern_step.hpp"
+#include "noalloc.hpp"
 #include "patch.hpp"
 
 using namespace fepa;
@@ -469,6 +470,9 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         ctx->err = "no HIP device";
         return bail(FE_EDEVICE);
     }
+    // device address of this GPU's static scratch (allocation-free entry
+    // points), looked up once per device; a failure only disables those calls
+    (void)static_scratch_init(ctx->device);
 
     // layout of the concatenated vectors and context arrays
     const std::vector<TuneEntry> tune = read_tune_table();
@@ -714,6 +718,7 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         if (!urc && (urc = upload(pl.sh_ptr.data(), pl.sh_ptr.size() * 4, &dp)) == FE_OK) r.pd.sh_ptr = (const int32_t *)dp;
         if (!urc && (urc = upload(pl.sh_idx.data(), pl.sh_idx.size() * 4, &dp)) == FE_OK) r.pd.sh_idx = (const int32_t *)dp;
         if (!urc && (urc = upload(nullptr, (size_t)pl.n_entries * 3 * sizeof(double), &dp)) == FE_OK) r.pd.part = (double *)dp;
+        r.pd.n_entries = pl.n_entries;
         if (!urc && (urc = upload(pl.orphans.data(), pl.orphans.size() * 4, &dp)) == FE_OK) r.orphans = (const int32_t *)dp;
         static_assert(sizeof(PatchRec) == 6 * sizeof(int32_t), "patch table rows are 6 int32");
         r.pd.n_patch = (int)pl.patch.size();
@@ -1007,6 +1012,51 @@ int fe_force_mult_pair(fe_ctx_t *ctx, const double *e, double *y, const double *
             launch_zero_nodes(r.orphans, r.n_orphans, y, ctx->N_tot, nullptr, su);
         });
     });
+}
+
+int fe_force_mult_pair_noalloc(fe_ctx_t *ctx, const double *e, double *y, const double *v,
+                               double *z)
+{
+    if (!ctx) return FE_EINVAL;
+    if (!y || !v || !z) return fail(ctx, FE_EINVAL, "NULL argument%s");
+    const void *in[] = {e, v}, *out[] = {y, z};
+    if (out[0] == out[1]) return fail(ctx, FE_EINVAL, "outputs alias%s");
+    for (const void *i : in)
+        for (const void *o : out)
+            if (i && i == o) return fail(ctx, FE_EINVAL, "input aliases output%s");
+    double *scr = static_scratch(ctx->device);
+    if (!scr) return fail(ctx, FE_EDEVICE, "static scratch of this device is not available%s");
+    // the units run one after another on the context stream, so each reuses
+    // the scratch from its start
+    for (const MeshRec &r : ctx->units()) {
+        const long long need = r.pd.n_entries * 3 * (long long)sizeof(double);
+        if (need > kStaticScratchBytes) {
+            char buf[160];
+            std::snprintf(buf, sizeof(buf),
+                          "shared-node partials need %lld bytes, above the %lld-byte static scratch",
+                          need, kStaticScratchBytes);
+            ctx->err = buf;
+            return FE_EINVAL;
+        }
+    }
+    hipStream_t su = ctx->st;
+    for (const MeshRec &r : ctx->units()) {
+        PatchDev pd = r.pd;
+        pd.part = scr;
+        if (r.pair_split) {
+            r.kl.force(S_of(ctx, r), e ? e + r.l2_off : nullptr, pd, y, ctx->N_tot, tab_of(ctx, r),
+                       r.nw_force, su);
+            r.kl.force_t(S_of(ctx, r), v, pd, r.E, z + r.l2_off, ctx->N_tot, tab_of(ctx, r),
+                         r.nw_force_t, su);
+        } else {
+            r.kl.force_pair(S_of(ctx, r), e ? e + r.l2_off : nullptr, v, pd, y, z + r.l2_off,
+                            ctx->N_tot, tab_of(ctx, r), r.nw_pair, su);
+        }
+        launch_gather_shared(pd, y, ctx->N_tot, nullptr, su);
+        launch_zero_nodes(r.orphans, r.n_orphans, y, ctx->N_tot, nullptr, su);
+    }
+    HIP_OK(hipGetLastError());
+    return FE_OK;
 }
 
 // lo: the FP32 operator (precision form); otherwise the FP64 operator.

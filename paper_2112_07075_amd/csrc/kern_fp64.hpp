@@ -26,6 +26,7 @@ struct PatchDev {
     const int32_t *sh_node = nullptr, *sh_ptr = nullptr, *sh_idx = nullptr;
     int n_shared = 0;
     double *part = nullptr;          // [entries][3] shared-node partials
+    long long n_entries = 0;         // rows of part (host-side size, not a kernel argument)
 };
 
 // CG extras of a mass launch: part_dot receives per-workgroup partials of

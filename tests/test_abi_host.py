@@ -97,6 +97,7 @@ def test_null_context_calls():
     assert L.fe_force_mult(None, None, None) == fe.FE_EINVAL
     assert L.fe_force_mult_T(None, None, None) == fe.FE_EINVAL
     assert L.fe_force_mult_pair(None, None, None, None, None) == fe.FE_EINVAL
+    assert L.fe_force_mult_pair_noalloc(None, None, None, None, None) == fe.FE_EINVAL
     assert L.fe_mass_mult(None, None, None) == fe.FE_EINVAL
     assert L.fe_mass_cg(None, None, None, None, 0, 1e-12, 10, None, None) == fe.FE_EINVAL
     assert L.fe_get_diag(None, None) == fe.FE_EINVAL
