@@ -35,12 +35,19 @@ sys.path.insert(0, HERE)
 
 CONFIGS = {
     # name: (n, p, Q, label)
-    "c2": (48, 2, 4, "48^3 hex, H1 Q2 / L2 Q1, 4^3 Gauss points, Taylor-Green, seed 0"),
-    "c3": (24, 4, 6, "24^3 hex, H1 Q4 / L2 Q3, 6^3 Gauss points, Taylor-Green, seed 0"),
-    "c4": (64, 3, 5, "64^3 hex, H1 Q3 / L2 Q2, 5^3 Gauss points, Taylor-Green, seed 0"),
-    "c5": (None, None, None, "256 perturbed cubes, 4^3..24^3 elements, H1 Q1..Q4, Q = p+2, "
-                             "Taylor-Green, seeds 1000..1255"),
+    "c2": (48, 2, 4, "48^3 hex, H1 Q2 / L2 Q1, 4^3 Gauss points, every node +-0.1h (seeded "
+                     "uniform), Taylor-Green, seed 0"),
+    "c3": (24, 4, 6, "24^3 hex, H1 Q4 / L2 Q3, 6^3 Gauss points, vertices +-0.05h (seeded uniform), "
+                     "other nodes on the trilinear map plus +-0.025h, Taylor-Green, seed 0"),
+    "c4": (64, 3, 5, "64^3 hex, H1 Q3 / L2 Q2, 5^3 Gauss points, every node +-0.05h (seeded "
+                     "uniform), Taylor-Green, seed 0"),
+    "c5": (None, None, None, "256 perturbed cubes, 4^3..24^3 elements, H1 Q1..Q4, Q = p+2, every "
+                             "node +-0.1h (p <= 2), 0.05h (p = 3), 0.025h (p = 4), Taylor-Green, "
+                             "seeds 1000..1255"),
 }
+# vertex perturbation (in h) of the workloads that perturb vertices and
+# high-order nodes separately
+VERTEX_AMP = {"c3": 0.05}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 N_PAIRS = 50
 HBM_PEAK_GBS = 8000.0
@@ -86,6 +93,59 @@ def algorithmic_bytes(E, N, p, Q):
         "mass": Q3 * E * 8 + 2 * 3 * N * 8 + D3 * E * 4,
         "qdata": 2 * 3 * N * 8 + Dl3 * E * 8 + Q3 * E * 8 + D3 * E * 4 + S,
     }
+
+
+def host_cpu():
+    """CPU model name and logical core count of the host the bench runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
+def cpu_baseline_allcore(meshes, qs, fields, threads, budget_s=10.0):
+    """The same oracle calls on every thread at once: each thread applies F.1 and
+    F^T.v over its own slice of an element sample into a private output (the
+    oracle releases the GIL inside its C calls); the slices' outputs would be
+    summed, which is not timed. Scaled per element to the whole workload."""
+    import oracle as O
+    from concurrent.futures import ThreadPoolExecutor
+    classes = {}
+    for m, Q, f in zip(meshes, qs, fields):
+        classes.setdefault((m.p, Q), (m, f))
+    per_elem, notes = {}, []
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        for (p, Q), (mesh, (v, e)) in classes.items():
+            E, N = mesh.n_elem, mesh.n_nodes
+            k = min(64 * threads, E)
+            while True:
+                el = np.arange(k, dtype=np.int32)
+                S = O.qdata(mesh.elem_nodes, p, Q, N, mesh.x0, mesh.x0, v, e, elems=el,
+                            want=("S",))["S"]
+                parts = np.array_split(el, threads)
+
+                def work(part, S=S, v=v, p=p, Q=Q, N=N, mesh=mesh):
+                    O.force_mult(mesh.elem_nodes, p, Q, N, S, None, elems=part)
+                    O.force_mult_T(mesh.elem_nodes, p, Q, N, S, v, elems=part)
+
+                t1 = time.perf_counter()
+                list(ex.map(work, parts))
+                t2 = time.perf_counter()
+                if (t2 - t1) > budget_s / (4 * len(classes)) or k * 2 > E:
+                    break
+                k *= 2
+            per_elem[(p, Q)] = (t2 - t1) / k
+            notes.append(f"p={p},Q={Q}: first {k} of {E} elements in {threads} slices, {t2 - t1:.2f} s")
+    pair_s = sum(per_elem[(m.p, Q)] * m.n_elem for m, Q in zip(meshes, qs))
+    dofs = sum(3 * m.n_nodes for m in meshes)
+    return {"value": dofs * 2 / pair_s / 1e9, "unit": "GDOF/s", "cores": threads, "kind": "oracle",
+            "sample": "F.1 + F^T.v on " + "; ".join(notes) + ", scaled per element to the workload"}
 
 
 def cpu_baseline(meshes, qs, fields, budget_s=12.0):
@@ -155,6 +215,114 @@ def precision_errors(torch, fe, run, meshes, qs, fields, W):
     return {k: float(f"{v:.3e}") for k, v in err.items()}
 
 
+def mf_flops(p, Q):
+    """FP64 operations per element of the matrix-free pair kernel as written:
+    forward x, y, z stages of six fields, the per-point algebra (counted from
+    the kernel: cofactors, inverse, velocity gradient, strain, viscosity,
+    S = w detJ sigma J^-T, the F^T v integrand), the transposed stages of three
+    components and the L2 stages of F^T v (multiply-add = 2)."""
+    D, Dl = p + 1, p
+    fwd = 2 * (2 * D ** 3 * Q + 3 * D ** 2 * Q ** 2 + 3 * D * Q ** 3)
+    point = 27 + 9 + 5 + 45 + 18 + 4 + 8 + 9 * 8 + 3 + 18 + 9 * 3 * 2
+    trans = 2 * (3 * D * Q ** 3 + 3 * D ** 2 * Q ** 2 // 1 + 2 * D ** 3 * Q)
+    l2 = 2 * (Dl * Q ** 3 + Dl ** 2 * Q ** 2 + Dl ** 3 * Q)
+    einterp = 2 * (Dl ** 3 * Q * Q + Dl * Q ** 3)
+    return 6 * fwd + point * Q ** 3 + 3 * trans + l2 + einterp
+
+
+def time_calls(torch, fn, reps=20, warm=3):
+    """Mean milliseconds of fn() over reps calls on the current stream (HIP events)."""
+    for _ in range(warm):
+        fn()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / reps
+
+
+def extra_rows(torch, fe, W, mesh, Q, fields):
+    """The operators beyond the force pair, timed on the same single-mesh
+    workload: the stiffness (diffusion) action of the hyper-viscosity term, the
+    fully matrix-free force pair (against stored-S qdata + pair), two materials
+    (their qdata and every material's F_k^T v) and the full Lagrange step."""
+    dev = torch.device("cuda:0")
+    p, E, N = mesh.p, mesh.n_elem, mesh.n_nodes
+    Q3, D3, Dl3 = Q ** 3, (p + 1) ** 3, p ** 3
+    v = torch.from_numpy(fields[0]).to(dev)
+    e = torch.from_numpy(fields[1].ravel()).to(dev)
+    x0 = torch.from_numpy(mesh.x0).to(dev)
+    x = x0 + (0.05 / mesh.n) * v
+    y = torch.empty((3, N), dtype=torch.float64, device=dev)
+    z = torch.empty(E * Dl3, dtype=torch.float64, device=dev)
+    desc = fe.MeshDesc(mesh.elem_nodes, x0, p, Q)
+    rows = {}
+
+    def rate(bytes_, ms):
+        gbs = bytes_ / (ms * 1e-3) / 1e9
+        return {"us": round(ms * 1e3, 2), "algorithmic_MB": round(bytes_ / 1e6, 1),
+                "GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+
+    # stiffness: Dk (6 Q^3 per element) + u in + y out + map
+    ctx = fe.fe_pa_setup(desc, fe.Opts(flags=fe.FE_OPT_STIFF))
+    ms_q = time_calls(torch, lambda: fe.fe_stiffness_update(ctx, x))
+    ms_k = time_calls(torch, lambda: fe.fe_stiffness_mult(ctx, v, y))
+    rows["stiffness"] = {"action": rate(6 * Q3 * E * 8 + 2 * 3 * N * 8 + D3 * E * 4, ms_k),
+                         "qdata": rate(3 * N * 8 + 6 * Q3 * E * 8 + D3 * E * 4, ms_q),
+                         "gdof_s": round(3 * N / (ms_k * 1e-3) / 1e9, 2)}
+    del ctx
+    # matrix-free pair vs qdata + stored-S pair
+    ctx = fe.fe_pa_setup(desc, fe.Opts())
+    try:
+        ms_mf = time_calls(torch, lambda: fe.fe_force_mult_pair_mf(ctx, x, v, e, y, z))
+        ms_pa = time_calls(torch, lambda: (fe.fe_qdata_update(ctx, x, v, e),
+                                           fe.fe_force_mult_pair(ctx, None, y, v, z)))
+        b = 2 * 3 * N * 8 + Dl3 * E * 8 + Q3 * E * 8 + 3 * N * 8 + Dl3 * E * 8 + D3 * E * 4
+        fl = mf_flops(p, Q) * E
+        r = rate(b, ms_mf)
+        r.update(gflops=round(fl / (ms_mf * 1e-3) / 1e9, 1), flop_per_elem=mf_flops(p, Q),
+                 frac_fp64=round(fl / (ms_mf * 1e-3) / 78.6e12, 4),
+                 pa_qdata_plus_pair_us=round(ms_pa * 1e3, 2),
+                 speedup_vs_pa=round(ms_pa / ms_mf, 3),
+                 gdof_s=round(3 * N * 2 / (ms_mf * 1e-3) / 1e9, 2))
+        rows["matrix_free_pair"] = r
+    except fe.FepaError as err:
+        rows["matrix_free_pair"] = {"unsupported": str(err)}
+    del ctx
+    # two materials: fractions 0.3 / 0.7, energies e and 1.5 e
+    eta = torch.cat([torch.full_like(e, 0.3), torch.full_like(e, 0.7)]).contiguous()
+    ctx = fe.fe_pa_setup(desc, fe.Opts(materials=fe.Materials([5.0 / 3.0, 1.4], [1.0, 4.0], eta)))
+    e2 = torch.cat([e, 1.5 * e]).contiguous()
+    z2 = torch.empty(2 * E * Dl3, dtype=torch.float64, device=dev)
+    ms_qm = time_calls(torch, lambda: fe.fe_qdata_update_mm(ctx, x, v, e2), reps=5)
+    ms_zm = time_calls(torch, lambda: fe.fe_force_mult_T_mm(ctx, v, z2))
+    ms_y = time_calls(torch, lambda: fe.fe_force_mult(ctx, None, y))
+    S = 9 * Q3 * E * 8
+    rows["multimaterial_2"] = {
+        "qdata_mm": rate(2 * (2 * 3 * N * 8 + Dl3 * E * 8 + Q3 * E * 8 + D3 * E * 4 + S) + 3 * S, ms_qm),
+        "force_T_mm": rate(2 * (S + 3 * N * 8 + Dl3 * E * 8 + D3 * E * 4), ms_zm),
+        "force_1_sum": rate(S + 3 * N * 8 + D3 * E * 4, ms_y)}
+    del ctx
+    # the full Lagrange step (two stages: 2 qdata, pair + F 1 + F^T vbar, 2 CG)
+    ctx = fe.fe_pa_setup(desc, fe.Opts(flags=fe.FE_OPT_STEP | fe.FE_OPT_GRAPH))
+    ess = torch.from_numpy(W.boundary_normal_dofs(mesh).astype(np.int32)).to(dev)
+    xs, vs, es = x0.clone(), v.clone(), e.clone()
+    info = fe.fe_lagrange_step(ctx, xs, vs, es, ess, cfl=0.5, cg_tol=1e-12)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nstep = 3
+    for _ in range(nstep):
+        info = fe.fe_lagrange_step(ctx, xs, vs, es, ess, cfl=0.5, cg_tol=1e-12)
+    ms_step = (time.perf_counter() - t0) * 1e3 / nstep
+    rows["lagrange_step"] = {"ms": round(ms_step, 3), "dt": info["dt"], "cg_iters": list(info["cg_iters"]),
+                             "gdof_s": round(3 * N / (ms_step * 1e-3) / 1e9, 3)}
+    del ctx
+    return rows
+
+
 def finite(obj):
     """NaN (a timer with no launches, e.g. inside replayed graphs) -> null."""
     if isinstance(obj, dict):
@@ -174,7 +342,8 @@ def build_workload(config, W):
         qs = [b.q1d for b in items]
     else:
         n, p, Q, _ = CONFIGS[config]
-        meshes, qs = [W.cube_mesh(n, p, W.default_amp(p), seed=0)], [Q]
+        meshes = [W.cube_mesh(n, p, W.default_amp(p), seed=0, vertex_amp=VERTEX_AMP.get(config))]
+        qs = [Q]
     fields = [W.taylor_green_fields(m) for m in meshes]
     return meshes, qs, fields, CONFIGS[config][3]
 
@@ -228,10 +397,13 @@ class Runner:
         fe.fe_timer_reset(self.ctx)
         t.cuda.synchronize()
         t0 = time.perf_counter()
+        marks = []
         for _ in range(steps):
-            self.step()
+            self.step()  # ends in the CG solve, which synchronises the stream
+            marks.append(time.perf_counter())
         t.cuda.synchronize()
         step_s = (time.perf_counter() - t0) / steps
+        self.step_times = np.diff(np.concatenate([[t0], marks]))
         per = {}
         for name, which in (("qdata", fe.FE_TIMER_QDATA), ("pair", fe.FE_TIMER_PAIR)):
             ms, cnt = fe.fe_timer_read(self.ctx, which)
@@ -248,6 +420,20 @@ class Runner:
                             ("mass", fe.FE_TIMER_MASS)):
             ms, cnt = fe.fe_timer_read(self.ctx, which)
             per[name] = (ms / cnt if cnt else float("nan"), ms)
+        # the CG solve of the step on its own (synchronous call): time per iteration
+        rhs = -self.y
+        fe.fe_force_mult(self.ctx, None, self.y)
+        t.neg(self.y, out=rhs)
+        solves = []
+        for _ in range(3):
+            self.a.zero_()
+            t.cuda.synchronize()
+            c0 = time.perf_counter()
+            _, it, _ = fe.fe_mass_cg(self.ctx, rhs, self.a, self.ess, rel_tol=1e-12, max_iter=5000)
+            solves.append(((time.perf_counter() - c0) * 1e3, it))
+        ms_solve = float(np.median([a for a, _ in solves]))
+        self.cg.update(ms_per_solve=round(ms_solve, 3),
+                       us_per_iter=round(ms_solve * 1e3 / max(1, solves[0][1]), 2))
         return step_s, per
 
 
@@ -259,6 +445,8 @@ def main():
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--precision", default="fp64", choices=sorted(PRECISIONS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip the timing of the stiffness, matrix-free, multi-material and step operators")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -352,12 +540,16 @@ def main():
             "launch": ("batched, actions and CG groups replayed from hipGraphs" if args.config == "c5"
                        else "direct action launches, CG groups replayed from hipGraphs"),
         },
+        "ms_per_step_median": round(float(np.median(run.step_times)) * 1e3, 3),
+        "ms_per_step_min_max": [round(float(run.step_times.min()) * 1e3, 3),
+                                round(float(run.step_times.max()) * 1e3, 3)],
         "kernels_us": {k: round(vv[0] * 1e3, 2) for k, vv in per.items()},
         "kernels_gbs": {k: round(ab[k] / (per[k][0] * 1e-3) / 1e9, 1) for k in per},
         "force_pair_gdof_s": 3 * N * 2 / (per["pair"][0] * 1e-3) / 1e9,
         "single_actions_gdof_s": 3 * N * 2 / ((per["force_1"][0] + per["force_T"][0]) * 1e-3) / 1e9,
         "cg": {"iters": run.cg.get("iters"), "true_rel_res": run.cg.get("rel_res"),
-               "mass_us": round(per["mass"][0] * 1e3, 2)},
+               "mass_us": round(per["mass"][0] * 1e3, 2), "ms_per_solve": run.cg.get("ms_per_solve"),
+               "us_per_iter": run.cg.get("us_per_iter")},
         "min_detj": diag["min_detj"],
         "roofline": {"bound": "hbm", "kernel": dom,
                      "timed": "whole action: k_force_pair (or k_force + k_force_t) + k_gather_shared, "
@@ -382,8 +574,18 @@ def main():
                                  "kernels_us": {k: round(vv[0] * 1e3, 2) for k, vv in p_per.items()}}
         out["batched_speedup"] = round(p_step / step_s, 3)
         del plain
+    if len(meshes) == 1 and args.precision == "fp64" and not args.no_rows:
+        del run
+        torch.cuda.empty_cache()
+        out["rows"] = extra_rows(torch, fe, W, meshes[0], qs[0], fields[0])
     if not args.no_cpu_baseline:
+        model, ncpu = host_cpu()
         out["cpu_baseline"] = cpu_baseline(meshes, qs, fields)
+        out["cpu_baseline"].update(host_cpu=model, host_logical_cores=ncpu)
+        # all host cores (at most 16: the CPU share of one GPU on the GPU machines)
+        threads = max(1, min(16, ncpu))
+        out["cpu_baseline_allcore"] = cpu_baseline_allcore(meshes, qs, fields, threads)
+        out["cpu_baseline_allcore"].update(host_cpu=model, host_logical_cores=ncpu)
     print(json.dumps(finite(out)))
 
 

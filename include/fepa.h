@@ -95,13 +95,20 @@ extern "C" {
                                 thermodynamic mass M_E^-1 and the step's
                                 workspace, allocated at setup              */
 
+#define FE_OPT_STIFF    0x10 /* also set up the stiffness (diffusion) operator
+                                of the hyper-viscosity term
+                                (fe_stiffness_update / fe_stiffness_mult):
+                                its quadrature data, 6 Q^3 FP64 values per
+                                element, allocated at setup                */
+
 /* kernels timed under FE_OPT_TIMERS */
 #define FE_TIMER_QDATA   0
 #define FE_TIMER_FORCE   1
 #define FE_TIMER_FORCE_T 2
 #define FE_TIMER_MASS    3
 #define FE_TIMER_PAIR    4  /* fe_force_mult_pair                          */
-#define FE_TIMER_COUNT   5
+#define FE_TIMER_MF      5  /* fe_force_mult_pair_mf                       */
+#define FE_TIMER_COUNT   6
 
 typedef struct fe_ctx fe_ctx_t;
 
@@ -118,6 +125,26 @@ typedef struct fe_mesh_desc {
     double rho0;               /* initial density (> 0), uniform            */
 } fe_mesh_desc_t;
 
+/* Several materials in one context (Sec. 2.1's multi-material equations,
+ * Sec. 3.3's semi-discrete system with sum_k F_k): material k has the
+ * ideal-gas ratio gamma[k] (> 1), the initial density rho0[k] (> 0) and the
+ * initial volume fraction eta0_k, an L2 field with the layout of e (for
+ * every material a full L2 vector of l2_size_total entries, materials
+ * concatenated: device [n_mat][L2_tot], read during fe_pa_setup only; for a
+ * context of several meshes each mesh's block starts at a multiple of its
+ * p^3, see fe_mesh_offsets). Without a closure model (volume-fraction
+ * exchange and the energy exchange c_k are not modelled) eta_k stays eta0_k
+ * along the motion, and eta_k rho_k |J| = eta_k0 rho_k0 |J0| fixes the
+ * material's mass per point m_qk = eta0_k rho0[k] detJ0 w. gamma and rho0
+ * are host arrays of n_mat entries, read during setup. */
+#define FE_MAX_MATERIALS 8
+typedef struct fe_materials {
+    int32_t n_mat;             /* 1 .. FE_MAX_MATERIALS                     */
+    const double *gamma;       /* host [n_mat]                              */
+    const double *rho0;        /* host [n_mat]                              */
+    const double *eta0;        /* device [n_mat][L2_tot]                    */
+} fe_materials_t;
+
 /* Tile shapes of the patch kernels. 0 selects, in order of precedence, the
  * matching line of the tuning table named by the environment variable
  * FEPA_TUNE_TABLE (text lines "order q1d precision nw_force nw_force_t nw_mass
@@ -132,6 +159,12 @@ typedef struct fe_opts {
     int32_t tune_nw_force_t;   /* waves per workgroup of F^T v              */
     int32_t tune_nw_mass;      /* waves per workgroup of M x                */
     int32_t tune_patch;        /* elements per patch, 1..4096 (0: default)  */
+    /* NULL: one material (rho0 of the meshes, gamma above). Otherwise the
+     * materials of a multi-material context (FE_PREC_FP64 only, not with
+     * FE_OPT_STEP): the context's m_q (mass action and CG) becomes the
+     * mixture's, sum_k m_qk, and fe_qdata_update_mm / fe_force_mult_T_mm
+     * apply the material operators. */
+    const fe_materials_t *materials;
 } fe_opts_t;
 
 typedef struct fe_info {
@@ -235,6 +268,71 @@ int fe_force_mult_T(fe_ctx_t *ctx, const double *v, double *z);
 int fe_force_mult_pair(fe_ctx_t *ctx, const double *e, double *y, const double *v, double *z);
 
 /*
+ * Quadrature data of the stiffness (diffusion) operator of the hyper-viscosity
+ * term (Sec. 2.1: the stiffness-matrix operator that shock capturing by
+ * hyper-viscosity needs; Sec. 6: the diffusion integrator of the
+ * artificial-viscosity calculations),
+ *     K[i][j] = int kappa grad w_i . grad w_j dx,
+ * on the current mesh: from the positions x ([3][N_tot], device) and the
+ * coefficient kappa at the quadrature points (device [E_tot][Q^3] in caller
+ * element order, q = qx + Q*(qy + Q*qz); NULL for kappa = 1; only for
+ * contexts whose meshes share one (order, q1d), FE_EINVAL otherwise), store
+ * Dk_q = w_q kappa_q detJ_q J_q^-1 J_q^-T (symmetric, 6 values per point) in
+ * the context, always in FP64. Needs FE_OPT_STIFF (FE_EINVAL otherwise).
+ * Asynchronous.
+ */
+int fe_stiffness_update(fe_ctx_t *ctx, const double *x, const double *kappa);
+
+/*
+ * Stiffness action y = K u for each of the three components of u ([3][N_tot]
+ * device in and out; y overwritten), block diagonal like M_v, with the data of
+ * the last fe_stiffness_update. Constants are in its null space. FP64 in
+ * every precision form. Needs FE_OPT_STIFF. Asynchronous.
+ */
+int fe_stiffness_mult(fe_ctx_t *ctx, const double *u, double *y);
+
+/*
+ * Quadrature data of a multi-material context (Sec. 3.3: F_k connects the
+ * kinematic space to material k's energy; the momentum equation takes
+ * sum_k F_k 1): from x, v ([3][N_tot]) and the material energies e
+ * (device [n_mat][L2_tot], each material an L2 vector like e of
+ * fe_qdata_update), for every material
+ *     S_k = w detJ eta_k sigma_k J^-T,  sigma_k = -p_k I + mu_k eps(v),
+ *     eta_k rho_k = m_qk / (w detJ),  p_k = (gamma_k - 1) rho_k e_k,
+ *     mu_k = rho_k l (q1 c_s,k + q2 l max(0, -tr eps)),
+ * and the context's S = sum_k S_k, so that fe_force_mult (e = NULL) and
+ * fe_force_mult_pair then give sum_k F_k 1 (and sum_k F_k^T v). fe_get_diag
+ * reports min detJ and the smallest stable point step over all materials.
+ * FE_EINVAL without materials. Asynchronous.
+ */
+int fe_qdata_update_mm(fe_ctx_t *ctx, const double *x, const double *v, const double *e);
+
+/*
+ * Energy right sides of every material, z_k = F_k^T v (the M_E,k de_k/dt
+ * equations of Sec. 3.3 without the closure term c_k): v [3][N_tot], z device
+ * [n_mat][L2_tot] (overwritten), from the S_k of the last
+ * fe_qdata_update_mm. FE_EINVAL without materials. Asynchronous.
+ */
+int fe_force_mult_T_mm(fe_ctx_t *ctx, const double *v, double *z);
+
+/*
+ * Fully matrix-free force pair: y = F 1 ([3][N_tot], as fe_force_mult with
+ * e = NULL) and z = F^T v ([E_tot][Dl^3], as fe_force_mult_T) of the state
+ * x, v ([3][N_tot]) and e ([E_tot][Dl^3]), with the quadrature data formed at
+ * each point inside the kernel and never stored: what fe_qdata_update
+ * followed by fe_force_mult_pair computes, without writing and reading S
+ * (the on-the-fly quadrature-data style of the paper's mesh-optimisation
+ * kernels, Sec. 3.4, applied to the force operator of Sec. 3.3). Also
+ * records min detJ, the smallest stable point step and the non-finite flag
+ * like fe_qdata_update (fe_get_diag); the context's stored S is not
+ * touched. Built for p = 1, 2 (every Q) and p = 3 at Q = 4, where every
+ * value stays in registers; FE_EUNSUPPORTED for other (order, q1d) and for
+ * multi-material contexts. FP64 in every precision form. Asynchronous.
+ */
+int fe_force_mult_pair_mf(fe_ctx_t *ctx, const double *x, const double *v, const double *e,
+                          double *y, double *z);
+
+/*
  * For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): fe_force_mult_pair with
  * the shared-node partials of the patch kernels held in a static device
@@ -272,6 +370,8 @@ int fe_mass_mult(fe_ctx_t *ctx, const double *x, double *y);
  * A context of several meshes solves every mesh's (independent) system with
  * its own CG scalars and stopping test; *iters is then the largest iteration
  * count and *rel_res the largest relative residual over the meshes.
+ * A (mesh's) zero right side b_free = 0 gives its exact solution x = 0 with
+ * no iteration, whatever the first guess.
  * Synchronises the stream. Returns FE_ENOTCONV when max_iter iterations did
  * not reach rel_tol (x then holds the last iterate).
  */

@@ -21,14 +21,16 @@ LIB_PATH = os.path.join(HERE, "libfepa.so")
 FE_OK, FE_EINVAL, FE_ENOMEM, FE_EDEVICE, FE_EUNSUPPORTED, FE_EBADMESH, FE_ENOTCONV = \
     0, -1, -2, -3, -4, -5, -6
 FE_PREC_FP64, FE_PREC_FP32, FE_PREC_BF16 = 0, 1, 2
-FE_OPT_TIMERS, FE_OPT_BATCHED, FE_OPT_GRAPH, FE_OPT_STEP = 0x1, 0x2, 0x4, 0x8
-FE_TIMER_QDATA, FE_TIMER_FORCE, FE_TIMER_FORCE_T, FE_TIMER_MASS, FE_TIMER_PAIR = 0, 1, 2, 3, 4
+FE_OPT_TIMERS, FE_OPT_BATCHED, FE_OPT_GRAPH, FE_OPT_STEP, FE_OPT_STIFF = 0x1, 0x2, 0x4, 0x8, 0x10
+FE_TIMER_QDATA, FE_TIMER_FORCE, FE_TIMER_FORCE_T, FE_TIMER_MASS, FE_TIMER_PAIR, FE_TIMER_MF = \
+    0, 1, 2, 3, 4, 5
 
 ABI_FUNCTIONS = ("fe_pa_setup", "fe_destroy", "fe_query", "fe_mesh_offsets", "fe_qdata_update",
                  "fe_force_mult", "fe_force_mult_T", "fe_force_mult_pair", "fe_mass_mult", "fe_mass_cg",
                  "fe_get_diag", "fe_export_qdata", "fe_timer_read", "fe_timer_reset",
                  "fe_status_str", "fe_last_error", "fe_lagrange_step", "fe_export_l2_mass_inv",
-                 "fe_force_mult_pair_noalloc")
+                 "fe_force_mult_pair_noalloc", "fe_stiffness_update", "fe_stiffness_mult",
+                 "fe_qdata_update_mm", "fe_force_mult_T_mm", "fe_force_mult_pair_mf")
 
 
 class FepaError(RuntimeError):
@@ -43,11 +45,16 @@ class _MeshDesc(C.Structure):
                 ("rho0", C.c_double)]
 
 
+class _Materials(C.Structure):
+    _fields_ = [("n_mat", C.c_int32), ("gamma", C.c_void_p), ("rho0", C.c_void_p),
+                ("eta0", C.c_void_p)]
+
+
 class _Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("flags", C.c_int32), ("gamma", C.c_double),
                 ("q1", C.c_double), ("q2", C.c_double), ("tune_nw_force", C.c_int32),
                 ("tune_nw_force_t", C.c_int32), ("tune_nw_mass", C.c_int32),
-                ("tune_patch", C.c_int32)]
+                ("tune_patch", C.c_int32), ("materials", C.POINTER(_Materials))]
 
 
 class _Info(C.Structure):
@@ -91,6 +98,11 @@ def lib() -> C.CDLL:
     L.fe_force_mult_T.argtypes = [vp, vp, vp]
     L.fe_force_mult_pair.argtypes = [vp, vp, vp, vp, vp]
     L.fe_force_mult_pair_noalloc.argtypes = [vp, vp, vp, vp, vp]
+    L.fe_stiffness_update.argtypes = [vp, vp, vp]
+    L.fe_qdata_update_mm.argtypes = [vp, vp, vp, vp]
+    L.fe_force_mult_pair_mf.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.fe_force_mult_T_mm.argtypes = [vp, vp, vp]
+    L.fe_stiffness_mult.argtypes = [vp, vp, vp]
     L.fe_mass_mult.argtypes = [vp, vp, vp]
     L.fe_mass_cg.argtypes = [vp, vp, vp, vp, i32, dbl, i32, C.POINTER(i32), C.POINTER(dbl)]
     L.fe_get_diag.argtypes = [vp, C.POINTER(_Diag)]
@@ -154,6 +166,15 @@ class Opts:
     tune_nw_force_t: int = 0
     tune_nw_mass: int = 0
     tune_patch: int = 0
+    materials: "Materials | None" = None
+
+
+@dataclass
+class Materials:
+    """Several materials: host gamma[K], rho0[K] (sequences), device eta0 [K][L2_tot] (torch)."""
+    gamma: object
+    rho0: object
+    eta0: object
 
 
 class Ctx:
@@ -190,6 +211,16 @@ def fe_pa_setup(meshes, opts: Opts | None = None, stream=None) -> Ctx:
     o = opts or Opts()
     co = _Opts(o.precision, o.flags, o.gamma, o.q1, o.q2, o.tune_nw_force, o.tune_nw_force_t,
                o.tune_nw_mass, o.tune_patch)
+    if o.materials is not None:
+        mt = o.materials
+        g = np.ascontiguousarray(mt.gamma, dtype=np.float64)
+        r = np.ascontiguousarray(mt.rho0, dtype=np.float64)
+        if g.shape != r.shape or g.ndim != 1:
+            raise FepaError(FE_EINVAL, "materials: gamma and rho0 need one entry per material")
+        keep += [g, r]
+        cm = _Materials(len(g), g.ctypes.data, r.ctypes.data, _ptr(mt.eta0).value)
+        keep.append(cm)
+        co.materials = C.pointer(cm)
     h = C.c_void_p()
     _check(L.fe_pa_setup(descs, len(meshes), C.byref(co), _stream(stream), C.byref(h)))
     return Ctx(h, keep)
@@ -234,6 +265,27 @@ def fe_force_mult_pair(ctx: Ctx, e, y, v, z) -> None:
 
 def fe_force_mult_pair_noalloc(ctx: Ctx, e, y, v, z) -> None:
     _check(lib().fe_force_mult_pair_noalloc(ctx.handle, _ptr(e), _ptr(y), _ptr(v), _ptr(z)),
+           ctx.handle)
+
+
+def fe_stiffness_update(ctx: Ctx, x, kappa=None) -> None:
+    _check(lib().fe_stiffness_update(ctx.handle, _ptr(x), _ptr(kappa)), ctx.handle)
+
+
+def fe_stiffness_mult(ctx: Ctx, u, y) -> None:
+    _check(lib().fe_stiffness_mult(ctx.handle, _ptr(u), _ptr(y)), ctx.handle)
+
+
+def fe_qdata_update_mm(ctx: Ctx, x, v, e) -> None:
+    _check(lib().fe_qdata_update_mm(ctx.handle, _ptr(x), _ptr(v), _ptr(e)), ctx.handle)
+
+
+def fe_force_mult_T_mm(ctx: Ctx, v, z) -> None:
+    _check(lib().fe_force_mult_T_mm(ctx.handle, _ptr(v), _ptr(z)), ctx.handle)
+
+
+def fe_force_mult_pair_mf(ctx: Ctx, x, v, e, y, z) -> None:
+    _check(lib().fe_force_mult_pair_mf(ctx.handle, _ptr(x), _ptr(v), _ptr(e), _ptr(y), _ptr(z)),
            ctx.handle)
 
 

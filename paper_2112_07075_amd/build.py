@@ -19,7 +19,9 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfepa.so")
 
 SOURCES = ["fepa.cpp", "basis.cpp", "patch.cpp", "kern_fp64.hip", "kern_bf16.hip", "kern_cg.hip",
-           "kern_step.hip", "noalloc.hip"]
+           "kern_step.hip", "noalloc.hip",
+           "kern_stiff.hip", "kern_mm.hip",
+           "kern_mf.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -21,6 +21,9 @@
 #include "kern_common.hpp"
 #include "kern_fp64.hpp"
 #include "kern_step.hpp"
+#include "kern_stiff.hpp"
+#include "kern_mm.hpp"
+#include "kern_mf.hpp"
 #include "noalloc.hpp"
 #include "patch.hpp"
 
@@ -35,12 +38,17 @@ struct MeshRec {
     long long node_off = 0, elem_off = 0, l2_off = 0, S_off = 0, mq_off = 0;
     long long part_off = 0;  // into the CG dot-partial array (one per patch)
     long long minv_off = 0;  // FE_OPT_STEP: first entry of the mesh's M_E^-1 blocks
+    long long Dk_off = 0;    // FE_OPT_STIFF: first entry of the mesh's stiffness data
+    StiffSet sk{};           // stiffness kernels of (p, Q)
+    MfFn mf = nullptr;       // matrix-free force pair of (p, Q), if built
     int tab_slot = 0;        // into the table buffer (doubles)
     const KernelSet *ks = nullptr;   // FP64 kernels
     KernelSet kl{};                  // kernels of the context's precision
     long long Sb_off = 0;            // offset of the mesh's S in the stored type
     int nw_force = 4, nw_force_t = 4, nw_mass = 4;  // waves per workgroup
     int nw_pair = 4;                                 // of the fused F e + F^T v kernel
+    int nw_stiff = 4;                                // of the stiffness action
+    int nw_mf = 4;                                   // of the matrix-free force pair
     bool pair_split = false;                         // the pair runs as the two actions
     int patch = 0;                                   // elements per patch (0: default)
     long long tabb_off = 0;          // BF16 form: byte offset of its operand buffer
@@ -70,10 +78,11 @@ struct GraphKey {
     int action = 0;
     const void *a = nullptr, *b = nullptr, *c = nullptr;
     int extra = 0;
-    const void *d = nullptr;
+    const void *d = nullptr, *f = nullptr;
     bool operator==(const GraphKey &o) const
     {
-        return action == o.action && a == o.a && b == o.b && c == o.c && extra == o.extra && d == o.d;
+        return action == o.action && a == o.a && b == o.b && c == o.c && extra == o.extra && d == o.d &&
+               f == o.f;
     }
 };
 struct GraphRec {
@@ -83,7 +92,7 @@ struct GraphRec {
 constexpr int kAuxStreams = 3;     // side streams of the unit branches in a graph
 constexpr size_t kMaxGraphs = 32;  // cached graphs per context (oldest dropped)
 constexpr int kGraphCgIters = 8;   // CG iterations per captured graph
-enum { kActQdata = 1, kActForce, kActForceT, kActMass, kActCg, kActPair };
+enum { kActQdata = 1, kActForce, kActForceT, kActMass, kActCg, kActPair, kActStiffQ, kActStiff, kActQdataMm, kActForceTMm, kActPairMf };
 
 }  // namespace
 
@@ -135,6 +144,14 @@ struct fe_ctx {
     double *minv = nullptr, *xs = nullptr, *vs = nullptr, *es = nullptr, *acc = nullptr;
     double *sy = nullptr, *sz = nullptr, *vbar = nullptr, *dtv = nullptr, *h_dt = nullptr;
     long long minv_len = 0;
+    // several materials (fe_opts_t.materials): per-material mass per point
+    // [K][mq_len] and quadrature data [K][S_len] (patch order, FP64)
+    int n_mat = 0;
+    std::vector<double> mat_gamma;
+    double *mqk = nullptr, *Sk = nullptr;
+    // FE_OPT_STIFF: stiffness quadrature data w kappa detJ J^-1 J^-T, [E][6][Q^3]
+    double *Dk = nullptr;
+    long long Dk_len = 0;
     CgState *h_cgm = nullptr;
     CgGlobal *h_glob = nullptr;
     double *h_mres = nullptr;
@@ -196,7 +213,7 @@ void free_all(fe_ctx *c)
     void *dptrs[] = {c->S, c->mq, c->tabs, c->mq32, c->tabs32, c->tabsb, c->ref_r, c->ref_d, c->min_key,
                      c->nonfinite, c->r, c->p, c->Ap, c->part, c->part2, c->scal, c->fr, c->cg,
                      c->bad, c->cgm, c->glob, c->part3, c->mres, c->minv, c->xs, c->vs, c->es,
-                     c->acc, c->sy, c->sz, c->vbar, c->dtv};
+                     c->acc, c->sy, c->sz, c->vbar, c->dtv, c->Dk, c->mqk, c->Sk};
     for (void *d : dptrs)
         if (d) (void)hipFree(d);
     for (void *d : c->plan_bufs)
@@ -427,8 +444,20 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         return fail(nullptr, FE_EINVAL, "gamma must be > 1 and q1, q2 >= 0%s");
     if (o.precision != FE_PREC_FP64 && o.precision != FE_PREC_FP32 && o.precision != FE_PREC_BF16)
         return fail(nullptr, FE_EUNSUPPORTED, "precision not provided by this build%s");
-    if (o.flags & ~(FE_OPT_TIMERS | FE_OPT_BATCHED | FE_OPT_GRAPH | FE_OPT_STEP))
+    if (o.flags & ~(FE_OPT_TIMERS | FE_OPT_BATCHED | FE_OPT_GRAPH | FE_OPT_STEP | FE_OPT_STIFF))
         return fail(nullptr, FE_EINVAL, "unknown option flags%s");
+    if (o.materials) {
+        const fe_materials_t &mt = *o.materials;
+        if (mt.n_mat < 1 || mt.n_mat > FE_MAX_MATERIALS || !mt.gamma || !mt.rho0 || !mt.eta0)
+            return fail(nullptr, FE_EINVAL, "materials: n_mat in [1, 8] and non-NULL arrays%s");
+        for (int k = 0; k < mt.n_mat; ++k)
+            if (!(mt.gamma[k] > 1.0) || !(mt.rho0[k] > 0.0))
+                return fail(nullptr, FE_EINVAL, "materials: gamma must be > 1 and rho0 > 0%s");
+        if (o.precision != FE_PREC_FP64)
+            return fail(nullptr, FE_EUNSUPPORTED, "materials need FE_PREC_FP64%s");
+        if (o.flags & FE_OPT_STEP)
+            return fail(nullptr, FE_EUNSUPPORTED, "the Lagrange step is single-material%s");
+    }
     for (int v : {o.tune_nw_force, o.tune_nw_force_t, o.tune_nw_mass})
         if (v != 0 && v != 2 && v != 4 && v != 8)
             return fail(nullptr, FE_EINVAL, "waves per workgroup must be 2, 4 or 8%s");
@@ -517,6 +546,11 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
             if (o.tune_nw_force || !r.nw_pair) r.nw_pair = r.nw_force;  // explicit shapes: one for both
             r.nw_pair = std::min(r.nw_pair, kc.max_nw(3));
         }
+        r.mf = mf_kernel(r.p, r.Q);
+        if (!stiff_kernels(r.p, r.Q, &r.sk)) {
+            ctx->err = "no stiffness kernels for this (order, q1d)";
+            return bail(FE_EUNSUPPORTED);
+        }
         if (ctx->bf) {
             r.kl.force = bf16_force(r.p, r.Q);
             bf16_parts(r.p, r.Q, &r.kl);
@@ -558,6 +592,8 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         r.S_off = ctx->S_len;
         r.Sb_off = ctx->Sb_len;
         r.mq_off = ctx->mq_len;
+        r.Dk_off = ctx->Dk_len;
+        ctx->Dk_len += 6 * Q3 * r.E;
         ctx->S_len += 9 * Q3 * r.E;
         ctx->Sb_len += 9 * (ctx->bf ? (Q3 + 31) / 32 * 32 : Q3) * r.E;
         ctx->mq_len += Q3 * r.E;
@@ -628,6 +664,14 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
             ctx->err = "stream or event creation failed";
             return bail(FE_EDEVICE);
         }
+    }
+    if ((o.flags & FE_OPT_STIFF) && (rc = dev_alloc(ctx, &ctx->Dk, ctx->Dk_len, &qb))) return bail(rc);
+    if (o.materials) {
+        ctx->n_mat = o.materials->n_mat;
+        ctx->mat_gamma.assign(o.materials->gamma, o.materials->gamma + ctx->n_mat);
+        if ((rc = dev_alloc(ctx, &ctx->mqk, ctx->n_mat * ctx->mq_len, &qb)) ||
+            (rc = dev_alloc(ctx, &ctx->Sk, ctx->n_mat * ctx->S_len, &qb)))
+            return bail(rc);
     }
     if (o.flags & FE_OPT_STEP) {
         for (MeshRec &r : ctx->mesh) {
@@ -873,6 +917,23 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         ctx->err = "set-up kernels failed";
         return bail(FE_EDEVICE);
     }
+    if (ctx->n_mat) {
+        // m_qk = rho0_k eta0_k(q) detJ0 w = (rho0_k / rho0) eta0_k(q) m_q, then
+        // the context's m_q becomes the mixture's, sum_k m_qk
+        const fe_materials_t &mt = *o.materials;
+        for (int k = 0; k < ctx->n_mat; ++k)
+            for (const MeshRec &r : ctx->mesh) {
+                const double *eta = mt.eta0 + k * ctx->L2_tot + (ctx->batched ? 0 : r.l2_off);
+                launch_mat_mass(r.p, r.Q, ctx->mq + r.mq_off, eta, r.pd.perm, mt.rho0[k] / r.rho0,
+                                ctx->mqk + k * ctx->mq_len + r.mq_off, r.E, ctx->tabs + r.tab_slot,
+                                ctx->st);
+            }
+        launch_sum_blocks(ctx->mqk, ctx->n_mat, ctx->mq_len, ctx->mq, ctx->mq_len, ctx->st);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->st) != hipSuccess) {
+            ctx->err = "set-up kernels failed";
+            return bail(FE_EDEVICE);
+        }
+    }
     if (ctx->lo) {
         launch_f64_to_f32(ctx->mq, ctx->mq32, ctx->mq_len, ctx->st);
         if (hipStreamSynchronize(ctx->st) != hipSuccess) {
@@ -1059,6 +1120,105 @@ int fe_force_mult_pair_noalloc(fe_ctx_t *ctx, const double *e, double *y, const 
     return FE_OK;
 }
 
+int fe_stiffness_update(fe_ctx_t *ctx, const double *x, const double *kappa)
+{
+    if (!ctx) return FE_EINVAL;
+    if (!(ctx->opts.flags & FE_OPT_STIFF)) return fail(ctx, FE_EINVAL, "context set up without FE_OPT_STIFF%s");
+    if (!x) return fail(ctx, FE_EINVAL, "NULL positions%s");
+    if (kappa && !ctx->uniform_pq)
+        return fail(ctx, FE_EINVAL, "a point coefficient needs one (order, q1d) for all meshes%s");
+    return run_graph(ctx, GraphKey{kActStiffQ, x, kappa}, [&](hipStream_t s, bool branch) {
+        enqueue_units(ctx, s, branch, [&](const MeshRec &r, hipStream_t su) {
+            const long long Q3 = (long long)r.Q * r.Q * r.Q;
+            r.sk.qdata(x, r.pd, r.E, ctx->N_tot, kappa ? kappa + r.elem_off * Q3 : nullptr, 0,
+                       ctx->Dk + r.Dk_off, ctx->tabs + r.tab_slot, su);
+        });
+    });
+}
+
+int fe_stiffness_mult(fe_ctx_t *ctx, const double *u, double *y)
+{
+    if (!ctx) return FE_EINVAL;
+    if (!(ctx->opts.flags & FE_OPT_STIFF)) return fail(ctx, FE_EINVAL, "context set up without FE_OPT_STIFF%s");
+    if (!u || !y) return fail(ctx, FE_EINVAL, "NULL argument%s");
+    if ((const void *)u == (const void *)y) return fail(ctx, FE_EINVAL, "input aliases output%s");
+    return run_graph(ctx, GraphKey{kActStiff, u, y}, [&](hipStream_t s, bool branch) {
+        enqueue_units(ctx, s, branch, [&](const MeshRec &r, hipStream_t su) {
+            r.sk.mult(ctx->Dk + r.Dk_off, u, r.pd, y, ctx->N_tot, ctx->tabs + r.tab_slot,
+                      r.nw_stiff, su);
+            launch_gather_shared(r.pd, y, ctx->N_tot, nullptr, su);
+            launch_zero_nodes(r.orphans, r.n_orphans, y, ctx->N_tot, nullptr, su);
+        });
+    });
+}
+
+int fe_qdata_update_mm(fe_ctx_t *ctx, const double *x, const double *v, const double *e)
+{
+    if (!ctx) return FE_EINVAL;
+    if (!ctx->n_mat) return fail(ctx, FE_EINVAL, "context set up without materials%s");
+    if (!x || !v || !e) return fail(ctx, FE_EINVAL, "NULL input%s");
+    ScopedTimer tm(ctx, FE_TIMER_QDATA);
+    return run_graph(ctx, GraphKey{kActQdataMm, x, v, e}, [&](hipStream_t s, bool branch) {
+        launch_reset_diag(ctx->min_key, ctx->nonfinite, s);
+        enqueue_units(ctx, s, branch, [&](const MeshRec &r, hipStream_t su) {
+            for (int k = 0; k < ctx->n_mat; ++k) {
+                const double g = ctx->mat_gamma[k];
+                QParams prm{r.rho0, g, g - 1.0, ctx->opts.q1, ctx->opts.q2, 1.0 / r.p};
+                r.kl.qdata(x, v, e + k * ctx->L2_tot + r.l2_off, r.pd, r.E, ctx->N_tot, 0,
+                           ctx->mqk + k * ctx->mq_len + r.mq_off, ctx->Sk + k * ctx->S_len + r.S_off,
+                           ctx->tabs + r.tab_slot, prm, ctx->min_key, ctx->nonfinite, false, su);
+            }
+            const long long Q3 = (long long)r.Q * r.Q * r.Q;
+            launch_sum_blocks(ctx->Sk + r.S_off, ctx->n_mat, ctx->S_len, (double *)ctx->S + r.S_off,
+                              9 * Q3 * r.E, su);
+        });
+    });
+}
+
+int fe_force_mult_T_mm(fe_ctx_t *ctx, const double *v, double *z)
+{
+    if (!ctx) return FE_EINVAL;
+    if (!ctx->n_mat) return fail(ctx, FE_EINVAL, "context set up without materials%s");
+    if (!v || !z) return fail(ctx, FE_EINVAL, "NULL argument%s");
+    if ((const void *)v == (const void *)z) return fail(ctx, FE_EINVAL, "input aliases output%s");
+    ScopedTimer tm(ctx, FE_TIMER_FORCE_T);
+    return run_graph(ctx, GraphKey{kActForceTMm, v, z}, [&](hipStream_t s, bool branch) {
+        enqueue_units(ctx, s, branch, [&](const MeshRec &r, hipStream_t su) {
+            for (int k = 0; k < ctx->n_mat; ++k)
+                r.kl.force_t(ctx->Sk + k * ctx->S_len + r.S_off, v, r.pd, r.E,
+                             z + k * ctx->L2_tot + r.l2_off, ctx->N_tot, tab_of(ctx, r),
+                             r.nw_force_t, su);
+        });
+    });
+}
+
+int fe_force_mult_pair_mf(fe_ctx_t *ctx, const double *x, const double *v, const double *e,
+                          double *y, double *z)
+{
+    if (!ctx) return FE_EINVAL;
+    if (!x || !v || !e || !y || !z) return fail(ctx, FE_EINVAL, "NULL argument%s");
+    const void *in[] = {x, v, e}, *out[] = {y, z};
+    if (out[0] == out[1]) return fail(ctx, FE_EINVAL, "outputs alias%s");
+    for (const void *i : in)
+        for (const void *o : out)
+            if (i == o) return fail(ctx, FE_EINVAL, "input aliases output%s");
+    if (ctx->n_mat) return fail(ctx, FE_EUNSUPPORTED, "the matrix-free pair is single-material%s");
+    for (const MeshRec &r : ctx->units())
+        if (!r.mf) return fail(ctx, FE_EUNSUPPORTED, "no matrix-free kernel for this (order, q1d)%s");
+    ScopedTimer tm(ctx, FE_TIMER_MF);
+    return run_graph(ctx, GraphKey{kActPairMf, x, v, e, 0, y, z}, [&](hipStream_t s, bool branch) {
+        launch_reset_diag(ctx->min_key, ctx->nonfinite, s);
+        enqueue_units(ctx, s, branch, [&](const MeshRec &r, hipStream_t su) {
+            QParams prm{r.rho0, ctx->opts.gamma, ctx->opts.gamma - 1.0, ctx->opts.q1, ctx->opts.q2,
+                        1.0 / r.p};
+            r.mf(x, v, e + r.l2_off, ctx->mq + r.mq_off, r.pd, y, z + r.l2_off, ctx->N_tot,
+                 ctx->tabs + r.tab_slot, prm, ctx->min_key, ctx->nonfinite, r.nw_mf, su);
+            launch_gather_shared(r.pd, y, ctx->N_tot, nullptr, su);
+            launch_zero_nodes(r.orphans, r.n_orphans, y, ctx->N_tot, nullptr, su);
+        });
+    });
+}
+
 // lo: the FP32 operator (precision form); otherwise the FP64 operator.
 // With x2 set, the launch is a CG iteration's: the operand is x + beta x2
 // (x = r, x2 = p; beta and the done flag from the device CG state) and the
@@ -1122,10 +1282,10 @@ static int cg_run(fe_ctx *ctx, const double *b, double *x, double rel_tol, int m
     const long long n = 3 * ctx->N_tot;
     mass_launch(ctx, x, ctx->Ap, lo);
     if (ctx->multi)
-        cgm_start(b, ctx->Ap, ctx->r, ctx->p, ctx->fr, ctx->cm, ctx->part2, ctx->part3, rel_tol,
+        cgm_start(x, b, ctx->Ap, ctx->r, ctx->p, ctx->fr, ctx->cm, ctx->part2, ctx->part3, rel_tol,
                   max_iter, ctx->st);
     else
-        cg_start(b, ctx->Ap, ctx->r, ctx->p, ctx->fr, n, ctx->part, ctx->part2, ctx->cg, rel_tol,
+        cg_start(x, b, ctx->Ap, ctx->r, ctx->p, ctx->fr, n, ctx->part, ctx->part2, ctx->cg, rel_tol,
                  max_iter, ctx->st);
     HIP_OK(hipGetLastError());
     // one iteration: Ap = M (r + beta p) with partials of its M-norm, then the
@@ -1320,16 +1480,19 @@ int fe_lagrange_step(fe_ctx_t *ctx, double *x, double *v, double *e, const int32
     launch_step_dt(ctx->min_key, cfl, dt_max, ctx->dtv, st);
     HIP_OK(hipMemcpyAsync(ctx->h_dt, ctx->dtv, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     if ((rc = fe_force_mult_pair(ctx, nullptr, ctx->sy, ctx->vs, ctx->sz))) return rc;
+    // the step size is known before any solve: a state with no finite step
+    // (still and pressureless, no dt_max) is refused before the CG runs
+    HIP_OK(hipStreamSynchronize(st));
+    out.dt = ctx->h_dt[0];
+    out.dt_est = ctx->h_dt[1];
+    if (!(out.dt > 0.0) || !std::isfinite(out.dt))
+        return fail(ctx, FE_EINVAL, "no finite positive step (set dt_max)%s");
     int it = 0;
     double res = 0.0;
     rc = fe_mass_cg(ctx, ctx->sy, ctx->acc, ess_dofs, n_ess, cg_tol, cg_max_iter, &it, &res);
     out.cg_iters[0] = it;
     out.cg_rel_res[0] = res;
-    if (rc) return rc;  // fe_mass_cg synchronised: h_dt is valid below
-    out.dt = ctx->h_dt[0];
-    out.dt_est = ctx->h_dt[1];
-    if (!(out.dt > 0.0) || !std::isfinite(out.dt))
-        return fail(ctx, FE_EINVAL, "no finite positive step (set dt_max)%s");
+    if (rc) return rc;
     launch_rk_h1(ctx->vs, ctx->xs, ctx->acc, v, x, nullptr, n3, ctx->dtv, 0.5, st);
     l2_update(0.5);
     // stage 2: forces of the midpoint state; v' and vbar, then e' and x' with vbar

@@ -97,9 +97,22 @@ __global__ void k_cg_start_final(const double *__restrict__ part_rr,
         st->iter = 0;
         st->max_iter = max_iter;
         st->done = (rr <= st->stop) ? 1 : (max_iter <= 0 ? 2 : 0);
+        if (bb == 0.0) {  // b_free = 0: x = 0 is the solution (k_cg_zero_rhs sets it)
+            st->rr = 0.0;
+            st->done = 1;
+        }
         st->alpha = st->beta = st->pAp = st->alpha_p = 0.0;
         st->pend = 0;
     }
+}
+
+// b_free = 0: the solution is x = 0 whatever the first guess (a relative
+// stopping test could never be met from a non-zero guess)
+__global__ void k_cg_zero_rhs(double *__restrict__ x, long long n, const CgState *__restrict__ st)
+{
+    if (st->bb != 0.0) return;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = 0.0;
 }
 
 // One step of a one-mesh solve, after Ap = M p' with p' = r + beta p (the
@@ -255,6 +268,10 @@ __global__ void k_cgm_start_final(const double *__restrict__ part_rr,
         st.iter = 0;
         st.max_iter = max_iter;
         st.done = (rr <= st.stop) ? 1 : (max_iter <= 0 ? 2 : 0);
+        if (bb == 0.0) {  // b_free = 0 on this mesh: x = 0 (k_cgm_zero_rhs sets it)
+            st.rr = 0.0;
+            st.done = 1;
+        }
         st.alpha = st.beta = st.pAp = st.alpha_p = 0.0;
         st.pend = 0;
         if (!st.done) atomicAdd(&glob->running, 1);
@@ -456,14 +473,15 @@ void cg_mask_apply(double *x, const unsigned char *fr, long long n, hipStream_t 
     hipLaunchKernelGGL(k_mask_apply, dim3(kVecBlocks), dim3(256), 0, st, x, fr, n);
 }
 
-void cg_start(const double *b, const double *Ax, double *r, double *p, const unsigned char *fr,
-              long long n, double *part_a, double *part_b, CgState *state, double rel_tol,
-              int max_iter, hipStream_t st)
+void cg_start(double *x, const double *b, const double *Ax, double *r, double *p,
+              const unsigned char *fr, long long n, double *part_a, double *part_b,
+              CgState *state, double rel_tol, int max_iter, hipStream_t st)
 {
     hipLaunchKernelGGL(k_cg_start, dim3(kVecBlocks), dim3(256), 0, st, b, Ax, r, p, fr, n, part_a,
                        part_b);
     hipLaunchKernelGGL(k_cg_start_final, dim3(1), dim3(1024), 0, st, part_a, part_b, kVecBlocks,
                        state, rel_tol, max_iter);
+    hipLaunchKernelGGL(k_cg_zero_rhs, dim3(kVecBlocks), dim3(256), 0, st, x, n, state);
 }
 
 void cg_step_shared(double *x, double *r, double *p, const double *Ap, const unsigned char *fr,
@@ -488,15 +506,25 @@ void resid_norm2(const double *b, const double *Ax, const unsigned char *fr, lon
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(1024), 0, st, part, kVecBlocks, out);
 }
 
-void cgm_start(const double *b, const double *Ax, double *r, double *p, const unsigned char *fr,
-               const CgMulti &cm, double *part_a, double *part_b, double rel_tol, int max_iter,
-               hipStream_t st)
+// a mesh with b_free = 0: its chunks of x are set to the solution 0
+__global__ void k_cgm_zero_rhs(double *__restrict__ x, const CgChunk *__restrict__ chunk,
+                               const CgState *__restrict__ state)
+{
+    const CgChunk ck = chunk[blockIdx.x];
+    if (state[ck.mesh].bb != 0.0) return;
+    for (int k = threadIdx.x; k < ck.len; k += blockDim.x) x[(long long)ck.start + k] = 0.0;
+}
+
+void cgm_start(double *x, const double *b, const double *Ax, double *r, double *p,
+               const unsigned char *fr, const CgMulti &cm, double *part_a, double *part_b,
+               double rel_tol, int max_iter, hipStream_t st)
 {
     hipLaunchKernelGGL(k_cgm_start, dim3(cm.n_chunk), dim3(256), 0, st, b, Ax, r, p, fr, cm.chunk,
                        part_a, part_b, cm.glob);
     hipLaunchKernelGGL(k_cgm_start_final, dim3(cm.n_mesh), dim3(256), 0, st, part_a, part_b, cm.cbeg,
                        cm.state, cm.glob, rel_tol, max_iter);
     hipLaunchKernelGGL(k_cgm_glob, dim3(1), dim3(64), 0, st, cm.glob);
+    hipLaunchKernelGGL(k_cgm_zero_rhs, dim3(cm.n_chunk), dim3(256), 0, st, x, cm.chunk, cm.state);
 }
 
 void cgm_finish(double *x, const double *p, const CgMulti &cm, hipStream_t st)

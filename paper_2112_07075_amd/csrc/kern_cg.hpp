@@ -36,9 +36,10 @@ struct CgMulti {
     CgState *state = nullptr;    // [n_mesh]
     CgGlobal *glob = nullptr;
 };
-void cgm_start(const double *b, const double *Ax, double *r, double *p, const unsigned char *fr,
-               const CgMulti &cm, double *part_a, double *part_b, double rel_tol, int max_iter,
-               hipStream_t st);
+// (x: the first guess; a mesh whose b_free is 0 gets x = 0 and counts as converged)
+void cgm_start(double *x, const double *b, const double *Ax, double *r, double *p,
+               const unsigned char *fr, const CgMulti &cm, double *part_a, double *part_b,
+               double rel_tol, int max_iter, hipStream_t st);
 void cgm_iterate(double *x, double *r, double *p, const double *Ap, const unsigned char *fr,
                  const CgMulti &cm, const double *part_pap, double *part, hipStream_t st);
 // After the iterations: the pending last direction of every mesh whose step
@@ -51,9 +52,10 @@ void cgm_resid(const double *b, const double *Ax, const unsigned char *fr, const
 void cg_mask(unsigned char *fr, long long n, const int32_t *ess, int n_ess, int *bad,
              hipStream_t st);
 void cg_mask_apply(double *x, const unsigned char *fr, long long n, hipStream_t st);
-void cg_start(const double *b, const double *Ax, double *r, double *p, const unsigned char *fr,
-              long long n, double *part_a, double *part_b, CgState *state, double rel_tol,
-              int max_iter, hipStream_t st);
+// r = b - Ax, p = r and the start-up sums; b_free = 0 gives x = 0, converged
+void cg_start(double *x, const double *b, const double *Ax, double *r, double *p,
+              const unsigned char *fr, long long n, double *part_a, double *part_b,
+              CgState *state, double rel_tol, int max_iter, hipStream_t st);
 // One CG step of a one-mesh solve after Ap = M p' with p' = r + beta p (the
 // mass kernel forms p' during its gather, leaves partials of p'.Ap in part_pap
 // and skips the shared-node gather): p = p', alpha = rr / (p.Ap), r -= alpha

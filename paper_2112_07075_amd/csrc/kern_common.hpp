@@ -78,6 +78,17 @@ __device__ __forceinline__ double key_value(long long k)
     return __longlong_as_double(k >= 0 ? k : (k ^ 0x7fffffffffffffffLL));
 }
 
+// Smallest of a 64-bit key over the wavefront (every lane receives it).
+__device__ __forceinline__ long long wave_min_key(long long k)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const long long o = __shfl_xor(k, off);
+        k = o < k ? o : k;
+    }
+    return k;
+}
+
 // ---------------------------------------------------------------- patches
 // Distinct-node slots per patch (UMAX) and the elements a workgroup handles
 // per pass (NE) are chosen so that the static LDS of a workgroup stays below

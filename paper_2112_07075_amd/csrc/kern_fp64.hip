@@ -1343,7 +1343,7 @@ k_qdata(const double *__restrict__ x, const double *__restrict__ v,
     __shared__ double sX[NE][NF][2][D * D * Q];
     __shared__ double sY[NE][NF][3][D * QQ];
     __shared__ double sE[NE][DL3 > 0 ? DL3 : 1];
-    __shared__ long long sMin, sDt;
+    __shared__ long long sKey[2][pt_ne(Q) * Q * Q * Q];
     __shared__ int sBad;
 
     const int tid = threadIdx.x, le = tid / Q3, q = tid % Q3;
@@ -1352,10 +1352,7 @@ k_qdata(const double *__restrict__ x, const double *__restrict__ v,
     const bool act = el < E;
 
     for (int k = tid; k < T::SIZE; k += blockDim.x) sTab[k] = tab[k];
-    if (tid == 0) {
-        sMin = sDt = 0x7fffffffffffffffLL;
-        sBad = 0;
-    }
+    if (tid == 0) sBad = 0;
     for (int k = q; k < NF * D3; k += Q3) {
         const int f = k / D3, i = k % D3;
         double val = 0.0;
@@ -1429,6 +1426,7 @@ k_qdata(const double *__restrict__ x, const double *__restrict__ v,
     const double A20 = J10 * J21 - J11 * J20, A21 = J01 * J20 - J00 * J21, A22 = J00 * J11 - J01 * J10;
     const double detJ = J00 * A00 + J01 * A10 + J02 * A20;
     bool nf = !isfinite(detJ);
+    long long kDt = 0x7fffffffffffffffLL;  // this point's stable-step key (none: largest)
 
     if (INIT) {
         if (act) mq[el * Q3 + q] = prm.rho0 * detJ * w;
@@ -1463,7 +1461,7 @@ k_qdata(const double *__restrict__ x, const double *__restrict__ v,
         const double ell = cbrt(detJ) * prm.inv_order;
         const double mu = rho * ell * (prm.q1 * cs + prm.q2 * ell * fmax(-tr, 0.0));
         const double speed = cs + mu / (rho * ell);
-        atomicMin(&sDt, ordered_key(speed > 0.0 ? ell / speed : INFINITY));
+        kDt = ordered_key(speed > 0.0 ? ell / speed : INFINITY);
         const double wd = w * detJ;
         constexpr int SQ = s_stride<RS>(Q);
         RS *__restrict__ Se = S + el * 9 * SQ;
@@ -1482,15 +1480,26 @@ k_qdata(const double *__restrict__ x, const double *__restrict__ v,
                 Se[(c * 3 + d) * SQ + q] = cvt<RS>(sv);
             }
     }
-    if (act) {
-        atomicMin(&sMin, ordered_key(detJ));
-        if (nf) atomicOr(&sBad, 1);
-    }
+    // minima over the workgroup without a per-point atomic: every point
+    // leaves its keys in LDS, the first wave (always a full one) takes the
+    // minima of a strided share each, then across its lanes
+    sKey[0][tid] = act ? ordered_key(detJ) : 0x7fffffffffffffffLL;
+    sKey[1][tid] = kDt;
+    if (act && nf) sBad = 1;
     __syncthreads();
-    if (tid == 0) {
-        atomicMin(min_key, sMin);
-        if (!INIT) atomicMin(min_key + 1, sDt);
-        if (sBad) atomicOr(nonfinite, 1);
+    if (tid < 64) {
+        long long a = 0x7fffffffffffffffLL, b = 0x7fffffffffffffffLL;
+        for (int k = tid; k < (int)blockDim.x; k += 64) {
+            a = sKey[0][k] < a ? sKey[0][k] : a;
+            b = sKey[1][k] < b ? sKey[1][k] : b;
+        }
+        a = wave_min_key(a);
+        b = wave_min_key(b);
+        if (tid == 0) {
+            atomicMin(min_key, a);
+            if (!INIT) atomicMin(min_key + 1, b);
+            if (sBad) atomicOr(nonfinite, 1);
+        }
     }
 }
 
@@ -1626,13 +1635,23 @@ struct Launch {
                 return force_lds(D, Q, rs, NW) <= kLdsMax && no_spill(k_force<D, Q, true, R, NW>) &&
                        no_spill(k_force<D, Q, false, R, NW>);
         }
-        if (kind == 1)
-            return force_t_lds(D, Q, rs, NW) <= kLdsMax && no_spill(k_force_t<D, Q, R, R, NW>);
+        // the FP32 set's shapes also serve the BF16 form, whose F^T v and pair
+        // kernels read BF16 S: their instances must not spill either
+        if (kind == 1) {
+            bool ok = force_t_lds(D, Q, rs, NW) <= kLdsMax && no_spill(k_force_t<D, Q, R, R, NW>);
+            if constexpr (sizeof(R) == 4) ok = ok && no_spill(k_force_t<D, Q, R, __bf16, NW>);
+            return ok;
+        }
         if (kind == 3) {
-            if constexpr (force_pair_lds(D, Q, rs, NW) <= kLdsMax)
-                return no_spill(k_force_pair<D, Q, true, R, NW>) && no_spill(k_force_pair<D, Q, false, R, NW>);
-            else
+            if constexpr (force_pair_lds(D, Q, rs, NW) <= kLdsMax) {
+                bool ok = no_spill(k_force_pair<D, Q, true, R, NW>) && no_spill(k_force_pair<D, Q, false, R, NW>);
+                if constexpr (sizeof(R) == 4)
+                    ok = ok && no_spill(k_force_pair<D, Q, true, R, NW, __bf16>) &&
+                         no_spill(k_force_pair<D, Q, false, R, NW, __bf16>);
+                return ok;
+            } else {
                 return false;
+            }
         }
         if constexpr (Q == 4)
             return mass_lds(D, Q, rs, NW) <= kLdsMax && no_spill(k_mass_q4<D, true, R, NW>) &&

@@ -86,8 +86,16 @@ class Mesh:
 
 
 def cube_mesh(n: int, p: int, amp: float = 0.1, seed: int = 0,
-              permute_seed: int | None = None) -> Mesh:
-    """Structured n^3 hex mesh of [0,1]^3 with order-p nodes, seeded perturbation."""
+              permute_seed: int | None = None, vertex_amp: float | None = None) -> Mesh:
+    """Structured n^3 hex mesh of [0,1]^3 with order-p nodes, seeded perturbation.
+
+    Every node component moves by amp*h*(2u-1) (u uniform in [0,1) from
+    splitmix64 of (seed, 3g+c)) unless the node lies on that component's
+    boundary plane. With vertex_amp, the element vertices instead move by
+    vertex_amp*h*(2u-1), every other node follows the trilinear map of its
+    element's moved vertices and then moves by amp*h*(2u-1) of its own (so the
+    elements stay curved): vertex noise of a larger amplitude than independent
+    high-order node noise allows without inverting elements."""
     if n < 1 or p < 1:
         raise ValueError("n and p must be >= 1")
     D = p + 1
@@ -103,12 +111,35 @@ def cube_mesh(n: int, p: int, amp: float = 0.1, seed: int = 0,
     ref = np.stack([coords[gx], coords[gy], coords[gz]])
     x0 = ref.copy()
     h = 1.0 / n
-    if amp != 0.0:
+    if amp != 0.0 or vertex_amp:
         gidx = np.arange(N, dtype=np.int64)
+        if vertex_amp:
+            # vertex displacements on the (n+1)^3 vertex grid, then their
+            # trilinear interpolation at every node of the element holding it
+            vert = (gx % p == 0) & (gy % p == 0) & (gz % p == 0)
+            V = n + 1
+            dv = np.zeros((3, V, V, V))
+            vg = gidx[vert]
+            vx, vy, vz = gx[vert] // p, gy[vert] // p, gz[vert] // p
+            for c, gc in enumerate((gx, gy, gz)):
+                u = uniform01(seed, 3 * vg + c)
+                inner = (gc[vert] > 0) & (gc[vert] < M - 1)
+                dv[c, vz, vy, vx] = np.where(inner, vertex_amp * h * (2.0 * u - 1.0), 0.0)
+            ex_, ey_, ez_ = (np.minimum(gq // p, n - 1) for gq in (gx, gy, gz))
+            tx, ty, tz = (t[gq - p * eq] for gq, eq in ((gx, ex_), (gy, ey_), (gz, ez_)))
+            disp = np.zeros((3, N))
+            for a in (0, 1):
+                for b in (0, 1):
+                    for d in (0, 1):
+                        wgt = ((tx if a else 1 - tx) * (ty if b else 1 - ty) * (tz if d else 1 - tz))
+                        disp += wgt * dv[:, ez_ + d, ey_ + b, ex_ + a]
         for c, gc in enumerate((gx, gy, gz)):
             u = uniform01(seed, 3 * gidx + c)
             inner = (gc > 0) & (gc < M - 1)
-            x0[c] = np.where(inner, ref[c] + amp * h * (2.0 * u - 1.0), ref[c])
+            own = amp * h * (2.0 * u - 1.0)
+            if vertex_amp:
+                own = np.where(vert, 0.0, own) + disp[c]
+            x0[c] = np.where(inner, ref[c] + own, ref[c])
     # element -> node map, local lexicographic (x fastest)
     ez, ey, ex = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
     ex, ey, ez = ex.ravel(), ey.ravel(), ez.ravel()
