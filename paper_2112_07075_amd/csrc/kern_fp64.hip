@@ -1503,6 +1503,221 @@ k_qdata(const double *__restrict__ x, const double *__restrict__ v,
     }
 }
 
+// Quadrature data at Q = 4 in the column layout of the force kernels: one
+// patch per workgroup (its node values of x and v read once into LDS), an
+// element's 16 point columns on one 16-lane row (point row qy fastest), qz in
+// registers. Per field (x_c, then v_c) the x stage runs on the lane's column
+// from LDS and the y stage over the quad's node rows by quad broadcasts; the z
+// stage and the point algebra (that of k_qdata) run per qz, and each (c, d) row
+// of S is written by the row's 16 lanes as 128 contiguous bytes. Minima of
+// detJ and of the stable step go over the wave, then one atomic per workgroup.
+constexpr int kQdataQ4Waves = 4;  // waves per workgroup of k_qdata_q4
+template <int D, typename RS, int NW>
+__global__ void __launch_bounds__(NW * 64)
+k_qdata_q4(const double *__restrict__ x, const double *__restrict__ v,
+           const double *__restrict__ e, const int32_t *__restrict__ perm,
+           const uint16_t *__restrict__ slot, const int32_t *__restrict__ pn,
+           const int32_t *__restrict__ ptab, long long ncomp, const double *__restrict__ mq,
+           RS *__restrict__ S, const double *__restrict__ tab, QParams prm,
+           long long *__restrict__ min_key, int *__restrict__ nonfinite)
+{
+    constexpr int Q = 4, NE = NW * 4, UMAX = patch_umax(D);
+    constexpr int DL = D - 1, QQ = 16, Q3 = 64, D3 = D * D * D, DL3 = DL * DL * DL;
+    constexpr int SQ = s_stride<RS>(Q);
+    using T = Tab<D, Q>;
+    __shared__ double xs[3 * UMAX];
+    __shared__ double vs[3 * UMAX];
+    __shared__ int sSl[NE][D3];
+    __shared__ long long sKey[2][NW];
+    __shared__ int sBad;
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int le = wv * 4 + (lane >> 4);
+    const int r = lane & 15, qy = r & 3, qx = r >> 2, t = qx + Q * qy;
+    const PatchRow pr = load_patch(ptab, xcd_block(blockIdx.x, gridDim.x));
+    for (int u = tid; u < pr.U; u += blockDim.x) {
+        const long long g = pn[pr.pno + u];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            xs[3 * u + c] = x[c * ncomp + g];
+            vs[3 * u + c] = v[c * ncomp + g];
+        }
+    }
+    if (tid == 0) sBad = 0;
+    double rBx[D], rGx[D], rBy[D], rGy[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        rBx[i] = tab[T::B + qx * D + i];
+        rGx[i] = tab[T::G + qx * D + i];
+        rBy[i] = tab[T::B + qy * D + i];
+        rGy[i] = tab[T::G + qy * D + i];
+    }
+    const double wxy = tab[T::W + qx] * tab[T::W + qy];
+    const int qyc = qy < D ? qy : D - 1;
+    long long kMin = 0x7fffffffffffffffLL, kDt = 0x7fffffffffffffffLL;
+    bool bad = false;
+    __syncthreads();
+
+#pragma unroll 1
+    for (int base = 0; base < pr.cnt; base += NE) {
+        const int idx = base + le;
+        const bool act = idx < pr.cnt;
+        const long long el = pr.eb + (act ? idx : 0);
+        for (int i = r; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
+        double mqv[Q], eq[Q];
+#pragma unroll
+        for (int qz = 0; qz < Q; ++qz) mqv[qz] = mq[el * Q3 + qz * QQ + t];
+        {
+            const double *__restrict__ ee = e + (long long)perm[el] * DL3;
+            double tz[DL];
+#pragma unroll
+            for (int jz = 0; jz < DL; ++jz) {
+                double s = 0.0;
+#pragma unroll
+                for (int jy = 0; jy < DL; ++jy) {
+                    double u = 0.0;
+#pragma unroll
+                    for (int jx = 0; jx < DL; ++jx) u += tab[T::BL + qx * DL + jx] * ee[(jz * DL + jy) * DL + jx];
+                    s += tab[T::BL + qy * DL + jy] * u;
+                }
+                tz[jz] = s;
+            }
+#pragma unroll
+            for (int qz = 0; qz < Q; ++qz) {
+                double s = 0.0;
+#pragma unroll
+                for (int jz = 0; jz < DL; ++jz) s += tab[T::BL + qz * DL + jz] * tz[jz];
+                eq[qz] = s;
+            }
+        }
+        wave_sync();
+        int sl[D][D];  // slots of the nodes (iz, qyc, ix) this lane's x stage reads
+#pragma unroll
+        for (int iz = 0; iz < D; ++iz)
+#pragma unroll
+            for (int ix = 0; ix < D; ++ix) sl[iz][ix] = sSl[le][(iz * D + qyc) * D + ix];
+        // x and y stages of the six fields: yf[f][0] = B_y G_x, [1] = G_y B_x, [2] = B_y B_x
+        double yf[6][3][D];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            const double *__restrict__ src = f < 3 ? xs : vs;
+            const int c = f % 3;
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) {
+                double ub = 0.0, ug = 0.0;
+#pragma unroll
+                for (int ix = 0; ix < D; ++ix) {
+                    const double u = src[3 * sl[iz][ix] + c];
+                    ub += rBx[ix] * u;
+                    ug += rGx[ix] * u;
+                }
+                const double bb[Q] = {dpp_r<kQuadBcast0>(ub), dpp_r<kQuadBcast1>(ub),
+                                      dpp_r<kQuadBcast2>(ub), dpp_r<kQuadBcast3>(ub)};
+                const double bg[Q] = {dpp_r<kQuadBcast0>(ug), dpp_r<kQuadBcast1>(ug),
+                                      dpp_r<kQuadBcast2>(ug), dpp_r<kQuadBcast3>(ug)};
+                double a = 0.0, b = 0.0, cc = 0.0;
+#pragma unroll
+                for (int iy = 0; iy < D; ++iy) {
+                    a += rBy[iy] * bg[iy];
+                    b += rGy[iy] * bb[iy];
+                    cc += rBy[iy] * bb[iy];
+                }
+                yf[f][0][iz] = a;
+                yf[f][1][iz] = b;
+                yf[f][2][iz] = cc;
+            }
+        }
+        RS *__restrict__ Se = S + el * 9 * SQ + t;
+#pragma unroll
+        for (int qz = 0; qz < Q; ++qz) {
+            double g[6][3];
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                double a = 0.0, b = 0.0, cc = 0.0;
+#pragma unroll
+                for (int iz = 0; iz < D; ++iz) {
+                    const double bz = tab[T::B + qz * D + iz], gz = tab[T::G + qz * D + iz];
+                    a += bz * yf[f][0][iz];
+                    b += bz * yf[f][1][iz];
+                    cc += gz * yf[f][2][iz];
+                }
+                g[f][0] = a;
+                g[f][1] = b;
+                g[f][2] = cc;
+            }
+            const double A00 = g[1][1] * g[2][2] - g[1][2] * g[2][1], A01 = g[0][2] * g[2][1] - g[0][1] * g[2][2];
+            const double A02 = g[0][1] * g[1][2] - g[0][2] * g[1][1], A10 = g[1][2] * g[2][0] - g[1][0] * g[2][2];
+            const double A11 = g[0][0] * g[2][2] - g[0][2] * g[2][0], A12 = g[0][2] * g[1][0] - g[0][0] * g[1][2];
+            const double A20 = g[1][0] * g[2][1] - g[1][1] * g[2][0], A21 = g[0][1] * g[2][0] - g[0][0] * g[2][1];
+            const double A22 = g[0][0] * g[1][1] - g[0][1] * g[1][0];
+            const double detJ = g[0][0] * A00 + g[0][1] * A10 + g[0][2] * A20;
+            const double id = 1.0 / detJ;
+            const double Ji[3][3] = {{A00 * id, A01 * id, A02 * id},
+                                     {A10 * id, A11 * id, A12 * id},
+                                     {A20 * id, A21 * id, A22 * id}};
+            const double w = wxy * tab[T::W + qz];
+            const double rho = mqv[qz] / (w * detJ);
+            const double pres = prm.gm1 * rho * eq[qz];
+            const double cs = sqrt(prm.gamma * prm.gm1 * fmax(eq[qz], 0.0));
+            double L[3][3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    L[c][k] = g[3 + c][0] * Ji[0][k] + g[3 + c][1] * Ji[1][k] + g[3 + c][2] * Ji[2][k];
+            double eps[3][3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) eps[a][b] = 0.5 * (L[a][b] + L[b][a]);
+            const double tr = eps[0][0] + eps[1][1] + eps[2][2];
+            const double ell = cbrt(detJ) * prm.inv_order;
+            const double mu = rho * ell * (prm.q1 * cs + prm.q2 * ell * fmax(-tr, 0.0));
+            const double speed = cs + mu / (rho * ell);
+            const double wd = w * detJ;
+            bool nf = !isfinite(detJ);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    double sv = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) sv += (mu * eps[c][k] - (c == k ? pres : 0.0)) * Ji[d][k];
+                    sv *= wd;
+                    nf = nf || !isfinite(sv);
+                    if (act) __builtin_nontemporal_store(cvt<RS>(sv), Se + (c * 3 + d) * SQ + qz * QQ);
+                }
+            if (act) {
+                const long long kd = ordered_key(speed > 0.0 ? ell / speed : INFINITY);
+                const long long km = ordered_key(detJ);
+                kDt = kd < kDt ? kd : kDt;
+                kMin = km < kMin ? km : kMin;
+                bad = bad || nf;
+            }
+        }
+        wave_sync();  // sSl is rewritten by the next pass
+    }
+    kMin = wave_min_key(kMin);
+    kDt = wave_min_key(kDt);
+    const bool anyBad = __any(bad);
+    if (lane == 0) {
+        sKey[0][wv] = kMin;
+        sKey[1][wv] = kDt;
+        if (anyBad) sBad = 1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        long long a = sKey[0][0], b = sKey[1][0];
+        for (int k = 1; k < NW; ++k) {
+            a = sKey[0][k] < a ? sKey[0][k] : a;
+            b = sKey[1][k] < b ? sKey[1][k] : b;
+        }
+        atomicMin(min_key, a);
+        atomicMin(min_key + 1, b);
+        if (sBad) atomicOr(nonfinite, 1);
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 // R: real type of S, m_q and the contractions (double, or float in the
 // FP32 precision form); the quadrature-data algebra always runs in FP64.
@@ -1672,6 +1887,14 @@ struct Launch {
                       QParams prm, long long *min_key, int *nonfinite, bool init, hipStream_t st)
     {
         const dim3 grid((E + NEp - 1) / NEp), block(NEp * Q * Q * Q);
+        if constexpr (Q == 4) {
+            if (!init) {  // column layout per patch (node_off is 0 on this path)
+                hipLaunchKernelGGL((k_qdata_q4<D, R, kQdataQ4Waves>), dim3(pd.n_patch),
+                                   dim3(kQdataQ4Waves * 64), 0, st, x, v, e, pd.perm, pd.slot, pd.pn,
+                                   pd.ptab, ncomp, mq, (R *)S, tab, prm, min_key, nonfinite);
+                return;
+            }
+        }
         if (init)
             hipLaunchKernelGGL((k_qdata<D, Q, true, R>), grid, block, 0, st, x, v, e, pd.map,
                                pd.perm, ncomp, node_off, mq, (R *)S, E, tab, prm, min_key,
@@ -1751,6 +1974,12 @@ struct LaunchBf16 {
         constexpr int NEp = pt_ne(Q);
         const dim3 grid((E + NEp - 1) / NEp), block(NEp * Q * Q * Q);
         (void)init;
+        if constexpr (Q == 4) {
+            hipLaunchKernelGGL((k_qdata_q4<D, __bf16, kQdataQ4Waves>), dim3(pd.n_patch),
+                               dim3(kQdataQ4Waves * 64), 0, st, x, v, e, pd.perm, pd.slot, pd.pn,
+                               pd.ptab, ncomp, mq, (__bf16 *)S, tab, prm, min_key, nonfinite);
+            return;
+        }
         hipLaunchKernelGGL((k_qdata<D, Q, false, __bf16>), grid, block, 0, st, x, v, e, pd.map,
                            pd.perm, ncomp, node_off, mq, (__bf16 *)S, E, tab, prm, min_key,
                            nonfinite);
