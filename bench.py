@@ -58,8 +58,8 @@ HBM_PEAK_GBS = 8000.0
 # reported only while those are unchanged (profiles/c2_fp64_step.md,
 # profiles/c4_step.md).
 TRAFFIC = {
-    ("c2", "fp64"): {"action": "pair", "kernel": "k_force_pair<3,4,ONE,double,2>", "bytes": 614.9e6,
-                     "src": {"kern_fp64.hip": "2817bcc2e6223854", "kern_common.hpp": "243f1c42df2ea2ef",
+    ("c2", "fp64"): {"action": "pair", "kernel": "k_force_pair<3,4,ONE,double,2>", "bytes": 615.0e6,
+                     "src": {"kern_fp64.hip": "81995b3436029ae1", "kern_common.hpp": "719ebdd81608eefe",
                              "tune_table.inc": "57afa8d182eb45ab"}},
     ("c4", "fp64"): {"action": "pair", "kernel": "k_force_pair<4,5,ONE,double,4>", "bytes": 3348.0e6,
                      "src": {"kern_fp64.hip": "2817bcc2e6223854", "kern_common.hpp": "243f1c42df2ea2ef",

@@ -646,7 +646,7 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         (rc = dev_alloc(ctx, &ctx->min_key, 2, &wb)) || (rc = dev_alloc(ctx, &ctx->nonfinite, 1, &wb)) ||
         (rc = dev_alloc(ctx, &ctx->r, 3 * ctx->N_tot, &wb)) || (rc = dev_alloc(ctx, &ctx->p, 3 * ctx->N_tot, &wb)) ||
         (rc = dev_alloc(ctx, &ctx->Ap, 3 * ctx->N_tot, &wb)) ||
-        (rc = dev_alloc(ctx, &ctx->part2, kVecBlocks, &wb)) || (rc = dev_alloc(ctx, &ctx->scal, 8, &wb)) ||
+        (rc = dev_alloc(ctx, &ctx->part2, std::max(kVecBlocks, kStepBlocks), &wb)) || (rc = dev_alloc(ctx, &ctx->scal, 8, &wb)) ||
         (rc = dev_alloc(ctx, &ctx->fr, 3 * ctx->N_tot, &wb)) || (rc = dev_alloc(ctx, &ctx->cg, 1, &wb)) ||
         (rc = dev_alloc(ctx, &ctx->bad, 1, &wb)))
         return bail(rc);

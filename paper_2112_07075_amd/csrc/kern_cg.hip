@@ -117,30 +117,32 @@ __global__ void k_cg_zero_rhs(double *__restrict__ x, long long n, const CgState
 
 // One step of a one-mesh solve, after Ap = M p' with p' = r + beta p (the
 // mass kernel forms p' during its gather, leaves partials of p'.Ap and leaves
-// the shared nodes of Ap as patch partials, no gather pass): p = p', alpha =
-// rr / (p.Ap), r -= alpha Ap on free DOFs, x += alpha p every second step,
-// partials of the new r.r. Every workgroup sums the p'.Ap partials in the same
-// order, so all agree on alpha without another launch (a last-workgroup
-// reduction would need a device-scope release fence per workgroup, which
-// writes back the XCD's L2 and costs more than a launch). Ap of a shared node
-// is the sum of its partials in ascending patch order (the order of the
-// gather it replaces), node by node with the three components in one thread.
-__global__ void k_cg_step_sh(double *__restrict__ x, double *__restrict__ r, double *__restrict__ p,
-                             const double *__restrict__ Ap, const unsigned char *__restrict__ fr,
-                             long long nn, const double *__restrict__ part_pap, int n_pap,
-                             CgState *__restrict__ st, double *__restrict__ part,
-                             const int32_t *__restrict__ node_sh, const int32_t *__restrict__ sh_ptr,
-                             const int32_t *__restrict__ sh_idx, const double *__restrict__ shpart)
+// the shared nodes of Ap as patch partials, no gather pass) and alpha = rr /
+// (p'.Ap) from k_cg_alpha: p = p', r -= alpha Ap on free DOFs, x += alpha p
+// every second step, partials of the new r.r (one per workgroup). One node
+// per thread (its three components), so that the dependent loads of many
+// nodes are in flight at once. Ap of a shared node is the sum of its partials
+// in ascending patch order (the order of the gather it replaces).
+// One workgroup: alpha = rr / (p'.Ap) from the mass kernel's partials.
+__global__ void k_cg_alpha(const double *__restrict__ part_pap, int n_pap, CgState *__restrict__ st)
 {
     __shared__ double sred[16];
-    __shared__ double s_alpha;
     if (st->done) return;
     double s = 0.0;
     for (int k = threadIdx.x; k < n_pap; k += blockDim.x) s += part_pap[k];
     s = block_sum(s, sred);
-    if (threadIdx.x == 0) s_alpha = st->rr / s;
-    __syncthreads();
-    const double alpha = s_alpha, beta = st->beta;
+    if (threadIdx.x == 0) st->alpha = st->rr / s;
+}
+
+__global__ void k_cg_step_sh(double *__restrict__ x, double *__restrict__ r, double *__restrict__ p,
+                             const double *__restrict__ Ap, const unsigned char *__restrict__ fr,
+                             long long nn, CgState *__restrict__ st, double *__restrict__ part,
+                             const int32_t *__restrict__ node_sh, const int32_t *__restrict__ sh_ptr,
+                             const int32_t *__restrict__ sh_idx, const double *__restrict__ shpart)
+{
+    __shared__ double sred[16];
+    if (st->done) return;
+    const double alpha = st->alpha, beta = st->beta;
     // x takes the directions of two iterations at once: after an even
     // iteration alpha is left pending, after an odd one both are added
     const bool flush = (st->iter & 1) != 0;
@@ -484,14 +486,22 @@ void cg_start(double *x, const double *b, const double *Ax, double *r, double *p
     hipLaunchKernelGGL(k_cg_zero_rhs, dim3(kVecBlocks), dim3(256), 0, st, x, n, state);
 }
 
+int cg_step_blocks(long long nn)
+{
+    const long long b = (nn + 255) / 256;
+    return (int)(b < 1 ? 1 : (b > kStepBlocks ? kStepBlocks : b));
+}
+
 void cg_step_shared(double *x, double *r, double *p, const double *Ap, const unsigned char *fr,
                     long long nn, const double *part_pap, int n_pap, CgState *state, double *part,
                     const int32_t *node_sh, const int32_t *sh_ptr, const int32_t *sh_idx,
                     const double *shpart, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cg_step_sh, dim3(kVecBlocks), dim3(256), 0, st, x, r, p, Ap, fr, nn,
-                       part_pap, n_pap, state, part, node_sh, sh_ptr, sh_idx, shpart);
-    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1024), 0, st, part, kVecBlocks, state);
+    const int nb = cg_step_blocks(nn);
+    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, st, part_pap, n_pap, state);
+    hipLaunchKernelGGL(k_cg_step_sh, dim3(nb), dim3(256), 0, st, x, r, p, Ap, fr, nn, state, part,
+                       node_sh, sh_ptr, sh_idx, shpart);
+    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1024), 0, st, part, nb, state);
 }
 
 void cg_finish(double *x, const double *p, long long n, const CgState *state, hipStream_t st)

@@ -15,6 +15,9 @@ struct CgState {
 };
 
 constexpr int kVecBlocks = 1024;  // workgroups of the vector kernels (partials per pass)
+constexpr int kStepBlocks = 16384;  // most workgroups (and r.r partials) of the one-mesh CG step
+// workgroups of the one-mesh CG step for nn nodes (one node per thread up to kStepBlocks)
+int cg_step_blocks(long long nn);
 
 // Several meshes solved at once, each with its own CG scalars (state[m]): the
 // DOF vector is cut into chunks that never straddle two meshes, and the
@@ -58,10 +61,11 @@ void cg_start(double *x, const double *b, const double *Ax, double *r, double *p
               CgState *state, double rel_tol, int max_iter, hipStream_t st);
 // One CG step of a one-mesh solve after Ap = M p' with p' = r + beta p (the
 // mass kernel forms p' during its gather, leaves partials of p'.Ap in part_pap
-// and skips the shared-node gather): p = p', alpha = rr / (p.Ap), r -= alpha
-// Ap on free DOFs, x += alpha p every second step (cg_finish adds a pending
-// last one); then one workgroup finishes r.r and sets beta, the iteration
-// count and done. Ap of a shared node is the sum of its patch partials
+// and skips the shared-node gather): one workgroup sets alpha = rr / (p.Ap);
+// p = p', r -= alpha Ap on free DOFs, x += alpha p every second step
+// (cg_finish adds a pending last one); then one workgroup finishes r.r (part
+// holds cg_step_blocks(nn) partials) and sets beta, the iteration count and
+// done. Ap of a shared node is the sum of its patch partials
 // (node_sh[g]: its row in the shared-node lists sh_ptr/sh_idx over shpart, or
 // -1); nn = nodes.
 void cg_step_shared(double *x, double *r, double *p, const double *Ap, const unsigned char *fr,

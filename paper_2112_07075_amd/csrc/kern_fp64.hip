@@ -1553,6 +1553,12 @@ k_qdata_q4(const double *__restrict__ x, const double *__restrict__ v,
         rGy[i] = tab[T::G + qy * D + i];
     }
     const double wxy = tab[T::W + qx] * tab[T::W + qy];
+    // 1/w per point as (1/(w_x w_y)) (1/w_z): rho = m_q / (w detJ) without a
+    // division per point
+    const double iwxy = 1.0 / wxy;
+    double iwz[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) iwz[k] = 1.0 / tab[T::W + k];
     const int qyc = qy < D ? qy : D - 1;
     long long kMin = 0x7fffffffffffffffLL, kDt = 0x7fffffffffffffffLL;
     bool bad = false;
@@ -1656,7 +1662,7 @@ k_qdata_q4(const double *__restrict__ x, const double *__restrict__ v,
                                      {A10 * id, A11 * id, A12 * id},
                                      {A20 * id, A21 * id, A22 * id}};
             const double w = wxy * tab[T::W + qz];
-            const double rho = mqv[qz] / (w * detJ);
+            const double rho = mqv[qz] * id * (iwxy * iwz[qz]);
             const double pres = prm.gm1 * rho * eq[qz];
             const double cs = sqrt(prm.gamma * prm.gm1 * fmax(eq[qz], 0.0));
             double L[3][3];
@@ -1672,10 +1678,12 @@ k_qdata_q4(const double *__restrict__ x, const double *__restrict__ v,
                 for (int b = 0; b < 3; ++b) eps[a][b] = 0.5 * (L[a][b] + L[b][a]);
             const double tr = eps[0][0] + eps[1][1] + eps[2][2];
             const double ell = cbrt(detJ) * prm.inv_order;
-            const double mu = rho * ell * (prm.q1 * cs + prm.q2 * ell * fmax(-tr, 0.0));
-            const double speed = cs + mu / (rho * ell);
+            // mu = rho l visc, and the viscous speed mu / (rho l) is visc itself
+            const double visc = prm.q1 * cs + prm.q2 * ell * fmax(-tr, 0.0);
+            const double mu = rho * ell * visc;
+            const double speed = cs + visc;
             const double wd = w * detJ;
-            bool nf = !isfinite(detJ);
+            double ssum = detJ;  // a non-finite S entry (or detJ) makes the sum non-finite
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -1684,9 +1692,10 @@ k_qdata_q4(const double *__restrict__ x, const double *__restrict__ v,
 #pragma unroll
                     for (int k = 0; k < 3; ++k) sv += (mu * eps[c][k] - (c == k ? pres : 0.0)) * Ji[d][k];
                     sv *= wd;
-                    nf = nf || !isfinite(sv);
+                    ssum += sv;
                     if (act) __builtin_nontemporal_store(cvt<RS>(sv), Se + (c * 3 + d) * SQ + qz * QQ);
                 }
+            const bool nf = !isfinite(ssum);
             if (act) {
                 const long long kd = ordered_key(speed > 0.0 ? ell / speed : INFINITY);
                 const long long km = ordered_key(detJ);
