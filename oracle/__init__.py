@@ -49,6 +49,9 @@ def lib():
         L.or_qdata.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _ip, _dp, _dp, _vp, _vp,
                                C.c_double, C.c_double, C.c_double, C.c_double, _vp, C.c_int,
                                _vp, _vp, _vp, _vp]
+        L.or_qdata_pt.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _ip, _dp, _dp, _vp, _vp,
+                                  C.c_double, _vp, C.c_double, C.c_double, C.c_double, _vp,
+                                  C.c_int, _vp, _vp, _vp, _vp]
         L.or_l2_mass.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp]
         L.or_force_elem_matrix.argtypes = [C.c_int, C.c_int, _dp, _dp]
         L.or_mass_elem_matrix.argtypes = [C.c_int, C.c_int, _dp, _dp]
@@ -109,17 +112,20 @@ class OracleError(RuntimeError):
 def qdata(mesh_map, p, Q, N, x0, x, v, e, rho0=1.0, gamma=5.0 / 3.0, q1=0.5, q2=2.0,
           elems=None, want=("S", "mq", "detJ"), allow_bad=False):
     """Quadrature data: dict with S [E][3][3][Q^3], mq, detJ and dt (the per-point
-    stable time step) [E][Q^3], as asked for in want."""
+    stable time step) [E][Q^3], as asked for in want. rho0 is the initial
+    density: a number, or an [E][Q^3] array of its value at every point."""
     mesh_map = _i32(mesh_map)
     E = mesh_map.shape[0]
     Q3 = Q ** 3
     out = {k: np.zeros((E, 9 * Q3) if k == "S" else (E, Q3)) for k in want}
     x0, x, v, e = _f64(x0), _f64(x), _f64(v), _f64(e)
     el = _i32(elems)
-    rc = lib().or_qdata(E, p, Q, N, mesh_map, x0, x, _ptr(v), _ptr(e), rho0, gamma, q1, q2,
-                        _ptr(el), 0 if el is None else len(el),
-                        _ptr(out.get("S")), _ptr(out.get("mq")), _ptr(out.get("detJ")),
-                        _ptr(out.get("dt")))
+    r0q = None if np.isscalar(rho0) else _f64(rho0).reshape(E, Q3)
+    rc = lib().or_qdata_pt(E, p, Q, N, mesh_map, x0, x, _ptr(v), _ptr(e),
+                           1.0 if r0q is not None else float(rho0), _ptr(r0q), gamma, q1, q2,
+                           _ptr(el), 0 if el is None else len(el),
+                           _ptr(out.get("S")), _ptr(out.get("mq")), _ptr(out.get("detJ")),
+                           _ptr(out.get("dt")))
     if rc == -2 and not allow_bad:
         raise OracleError("non-positive Jacobian determinant")
     if rc not in (0, -2):

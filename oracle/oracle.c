@@ -215,6 +215,8 @@ static void inv3(const double A[3][3], double det, double inv[3][3])
  * mass operators:
  *   S[e][c][d][q] = w_q detJ_q sum_k sigma_q[c][k] Jinv_q[d][k]  (w detJ sigma J^-T)
  *   mq[e][q]      = rho0 detJ0_q w_q                             (rho |J| = rho0 |J0|)
+ *                   (or_qdata_pt: rho0_q[e][q] detJ0_q w_q, an initial density
+ *                   given at every point, when rho0_q != NULL)
  *   detJ[e][q]    (optional)
  *   dt[e][q]      (optional) the stable explicit time step of the point: the
  *                 time a signal of speed c_s + mu/(rho l) needs to cross the
@@ -225,11 +227,11 @@ static void inv3(const double A[3][3], double det, double inv[3][3])
  * Returns 0, or -1 on bad arguments, or -2 when some detJ <= 0 (values still
  * written).
  */
-int or_qdata(int n_elem, int p, int Q, int N, const int32_t *map,
-             const double *x0, const double *x, const double *v, const double *e,
-             double rho0, double gamma, double q1, double q2,
-             const int32_t *elems, int n_sel,
-             double *S, double *mq, double *detJ_out, double *dt_out)
+int or_qdata_pt(int n_elem, int p, int Q, int N, const int32_t *map,
+                const double *x0, const double *x, const double *v, const double *e,
+                double rho0, const double *rho0_q, double gamma, double q1, double q2,
+                const int32_t *elems, int n_sel,
+                double *S, double *mq, double *detJ_out, double *dt_out)
 {
     or_basis bs;
     if (make_basis(p, Q, &bs)) return -1;
@@ -257,7 +259,8 @@ int or_qdata(int n_elem, int p, int Q, int N, const int32_t *map,
             }
             const double dJ = det3(J), dJ0 = det3(J0);
             if (!(dJ > 0.0)) bad = 1;
-            const double m = rho0 * dJ0 * w;
+            const double r0 = rho0_q ? rho0_q[(size_t)el * Q3 + q] : rho0;
+            const double m = r0 * dJ0 * w;
             if (mq) mq[(size_t)el * Q3 + q] = m;
             if (detJ_out) detJ_out[(size_t)el * Q3 + q] = dJ;
             if (!S && !dt_out) continue;
@@ -301,6 +304,16 @@ int or_qdata(int n_elem, int p, int Q, int N, const int32_t *map,
         }
     }
     return bad ? -2 : 0;
+}
+
+int or_qdata(int n_elem, int p, int Q, int N, const int32_t *map,
+             const double *x0, const double *x, const double *v, const double *e,
+             double rho0, double gamma, double q1, double q2,
+             const int32_t *elems, int n_sel,
+             double *S, double *mq, double *detJ_out, double *dt_out)
+{
+    return or_qdata_pt(n_elem, p, Q, N, map, x0, x, v, e, rho0, NULL, gamma, q1, q2, elems, n_sel,
+                       S, mq, detJ_out, dt_out);
 }
 
 /* ------------------------------------------------------- multi-material */
