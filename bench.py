@@ -559,6 +559,26 @@ def main():
                      "traffic": measured_traffic(args.config, args.precision, dom),
                      "traffic_unit": "MB per launch", "algorithmic_MB": round(ab[dom] / 1e6, 1)},
     }
+    if args.config == "c3":
+        # the pair's working set (272.8 MB) is about the 256 MB Infinity Cache:
+        # time the pair again over four contexts (four copies of S) in turn
+        ctxs = [run] + [Runner(torch, fe, W, meshes, qs, fields, fe.Opts(flags=flags)) for _ in range(3)]
+        for c in ctxs:
+            fe.fe_qdata_update(c.ctx, c.x0, c.v, c.e)
+        k = [0]
+
+        def rotated_pair():
+            c = ctxs[k[0] % 4]
+            k[0] += 1
+            fe.fe_force_mult_pair(c.ctx, None, c.y, c.v, c.z)
+
+        ms_rot = time_calls(torch, rotated_pair, reps=40, warm=4)
+        ach = ab[dom] / (ms_rot * 1e-3) / 1e9
+        out["roofline_rotated_S_x4"] = {"kernel": dom, "us": round(ms_rot * 1e3, 2),
+                                        "achieved": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+                                        "timed": "HIP events around 40 pair actions cycling over four "
+                                                 "contexts of the same mesh"}
+        del ctxs
     if args.precision != "fp64":
         # the same outputs from the FP64 path (which matches the oracle to 1e-12):
         # error of every output of the precision form, relative to max |FP64 output|

@@ -114,7 +114,8 @@ typedef struct fe_ctx fe_ctx_t;
 
 /* One mesh. elem_nodes is HOST memory, read during fe_pa_setup only.
  * x0 is DEVICE memory [3][n_nodes]: initial node positions, read during
- * fe_pa_setup only (to form m_q = rho0 detJ0 w). */
+ * fe_pa_setup only (to form m_q = rho0 detJ0 w, Sec. 3.3's rho |J| =
+ * rho0 |J0| at every quadrature point). */
 typedef struct fe_mesh_desc {
     int32_t n_elem;            /* E >= 1                                    */
     int32_t order;             /* p, 1..4                                   */
@@ -123,6 +124,11 @@ typedef struct fe_mesh_desc {
     const int32_t *elem_nodes; /* host [E][(p+1)^3], entries in [0, N)      */
     const double *x0;          /* device [3][N]                             */
     double rho0;               /* initial density (> 0), uniform            */
+    /* NULL, or the initial density at every quadrature point: device
+     * [E][Q^3] (caller element order, q = qx + Q*(qy + Q*qz), all > 0),
+     * read during fe_pa_setup only; then m_q = rho0_q detJ0 w and rho0 is
+     * not used. */
+    const double *rho0_q;
 } fe_mesh_desc_t;
 
 /* Several materials in one context (Sec. 2.1's multi-material equations,
@@ -146,10 +152,13 @@ typedef struct fe_materials {
 } fe_materials_t;
 
 /* Tile shapes of the patch kernels. 0 selects, in order of precedence, the
- * matching line of the tuning table named by the environment variable
- * FEPA_TUNE_TABLE (text lines "order q1d precision nw_force nw_force_t nw_mass
- * patch", as written by the package's autotuner), the library's built-in
- * table (measured by the same autotuner on MI355X), else the default rule. */
+ * matching line of the tuning table named by tune_table (or, when that is
+ * NULL, by the environment variable FEPA_TUNE_TABLE; text lines "order q1d
+ * precision nw_force nw_force_t nw_mass patch [nw_pair]", as written by the
+ * package's autotuner), the library's built-in table (measured by the same
+ * autotuner on MI355X), else the default rule. The element restriction's
+ * scatter is always the deterministic patch scatter (device-scope atomics
+ * were measured slower on MI355X and are not offered). */
 typedef struct fe_opts {
     int32_t precision;         /* FE_PREC_*                                 */
     int32_t flags;             /* FE_OPT_* bit set                          */
@@ -159,6 +168,10 @@ typedef struct fe_opts {
     int32_t tune_nw_force_t;   /* waves per workgroup of F^T v              */
     int32_t tune_nw_mass;      /* waves per workgroup of M x                */
     int32_t tune_patch;        /* elements per patch, 1..4096 (0: default)  */
+    /* NULL, or the path of a tuning table (format below), read during
+     * fe_pa_setup only, in place of FEPA_TUNE_TABLE; a file that cannot be
+     * opened fails the set-up with FE_EINVAL. */
+    const char *tune_table;
     /* NULL: one material (rho0 of the meshes, gamma above). Otherwise the
      * materials of a multi-material context (FE_PREC_FP64 only, not with
      * FE_OPT_STEP): the context's m_q (mass action and CG) becomes the

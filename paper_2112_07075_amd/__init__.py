@@ -42,7 +42,7 @@ class FepaError(RuntimeError):
 class _MeshDesc(C.Structure):
     _fields_ = [("n_elem", C.c_int32), ("order", C.c_int32), ("q1d", C.c_int32),
                 ("n_nodes", C.c_int32), ("elem_nodes", C.c_void_p), ("x0", C.c_void_p),
-                ("rho0", C.c_double)]
+                ("rho0", C.c_double), ("rho0_q", C.c_void_p)]
 
 
 class _Materials(C.Structure):
@@ -54,7 +54,8 @@ class _Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("flags", C.c_int32), ("gamma", C.c_double),
                 ("q1", C.c_double), ("q2", C.c_double), ("tune_nw_force", C.c_int32),
                 ("tune_nw_force_t", C.c_int32), ("tune_nw_mass", C.c_int32),
-                ("tune_patch", C.c_int32), ("materials", C.POINTER(_Materials))]
+                ("tune_patch", C.c_int32), ("tune_table", C.c_char_p),
+                ("materials", C.POINTER(_Materials))]
 
 
 class _Info(C.Structure):
@@ -153,6 +154,7 @@ class MeshDesc:
     order: int
     q1d: int
     rho0: float = 1.0
+    rho0_q: object = None   # device float64 [E][Q^3] initial density per point (torch), or None
 
 
 @dataclass
@@ -166,6 +168,7 @@ class Opts:
     tune_nw_force_t: int = 0
     tune_nw_mass: int = 0
     tune_patch: int = 0
+    tune_table: "str | None" = None   # tuning-table path (in place of FEPA_TUNE_TABLE)
     materials: "Materials | None" = None
 
 
@@ -207,10 +210,12 @@ def fe_pa_setup(meshes, opts: Opts | None = None, stream=None) -> Ctx:
         keep.append(en)
         E = en.shape[0]
         descs[k] = _MeshDesc(E, m.order, m.q1d, m.x0.shape[-1], en.ctypes.data,
-                             _ptr(m.x0).value, float(m.rho0))
+                             _ptr(m.x0).value, float(m.rho0),
+                             None if m.rho0_q is None else _ptr(m.rho0_q).value)
     o = opts or Opts()
     co = _Opts(o.precision, o.flags, o.gamma, o.q1, o.q2, o.tune_nw_force, o.tune_nw_force_t,
-               o.tune_nw_mass, o.tune_patch)
+               o.tune_nw_mass, o.tune_patch,
+               None if o.tune_table is None else os.fsencode(o.tune_table))
     if o.materials is not None:
         mt = o.materials
         g = np.ascontiguousarray(mt.gamma, dtype=np.float64)

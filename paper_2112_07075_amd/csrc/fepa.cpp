@@ -128,7 +128,7 @@ struct fe_ctx {
     long long n_parts = 0;
     // one mesh: the shared-node row of every node (-1: private or unreferenced),
     // so the CG step reads shared Ap from the patch partials (no gather pass)
-    int32_t *node_sh = nullptr;
+    long long *node_sh = nullptr;  // one-mesh CG: (first << 16) | count of a node's partials, or -1
     // several meshes: one CG per mesh (chunked vectors, per-mesh scalars)
     bool multi = false;
     CgMulti cm;
@@ -286,17 +286,22 @@ const TuneEntry kBuiltinTune[] = {
 #include "tune_table.inc"
     {0, 0, 0, 0, 0, 0, 0, 0}};
 
-// the built-in table followed by the one named by FEPA_TUNE_TABLE (missing or
-// unreadable: none); later rows take precedence
-std::vector<TuneEntry> read_tune_table()
+// the built-in table followed by the one named by opt_path, else by
+// FEPA_TUNE_TABLE (a missing file: none from the environment, *opened = false
+// from opt_path); later rows take precedence
+std::vector<TuneEntry> read_tune_table(const char *opt_path, bool *opened)
 {
     std::vector<TuneEntry> t;
     for (const TuneEntry &e : kBuiltinTune)
         if (e.p) t.push_back(e);
-    const char *path = std::getenv("FEPA_TUNE_TABLE");
+    *opened = true;
+    const char *path = opt_path ? opt_path : std::getenv("FEPA_TUNE_TABLE");
     if (!path || !*path) return t;
     FILE *f = std::fopen(path, "r");
-    if (!f) return t;
+    if (!f) {
+        *opened = opt_path == nullptr;  // a missing file named by the environment is ignored
+        return t;
+    }
     char line[256];
     while (std::fgets(line, sizeof(line), f)) {
         TuneEntry e{};
@@ -475,7 +480,9 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         if (o.precision == FE_PREC_BF16 && !bf16_force(d.order, d.q1d))
             return fail(nullptr, FE_EUNSUPPORTED, "(order, q1d) has no BF16 MFMA instance%s");
         if (!d.elem_nodes || !d.x0) return fail(nullptr, FE_EINVAL, "NULL mesh array%s");
-        if (!(d.rho0 > 0.0)) return fail(nullptr, FE_EINVAL, "rho0 must be > 0%s");
+        if (!d.rho0_q && !(d.rho0 > 0.0)) return fail(nullptr, FE_EINVAL, "rho0 must be > 0%s");
+        if (d.rho0_q && o.materials)
+            return fail(nullptr, FE_EUNSUPPORTED, "rho0_q with materials (each has its own rho0)%s");
         const long long D3 = (long long)(d.order + 1) * (d.order + 1) * (d.order + 1);
         const long long cnt = D3 * d.n_elem;
         for (long long k = 0; k < cnt; ++k)
@@ -504,7 +511,12 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
     (void)static_scratch_init(ctx->device);
 
     // layout of the concatenated vectors and context arrays
-    const std::vector<TuneEntry> tune = read_tune_table();
+    bool tune_opened = true;
+    const std::vector<TuneEntry> tune = read_tune_table(o.tune_table, &tune_opened);
+    if (!tune_opened) {
+        ctx->err = "cannot open the tuning table named by tune_table";
+        return bail(FE_EINVAL);
+    }
     std::map<std::pair<int, int>, int> slot_of;
     std::vector<double> tab_host;
     for (int m = 0; m < n_mesh; ++m) {
@@ -514,7 +526,8 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         r.p = d.order;
         r.Q = d.q1d;
         r.N = d.n_nodes;
-        r.rho0 = d.rho0;
+        // with rho0_q the set-up forms detJ0 w and scales it point by point
+        r.rho0 = d.rho0_q ? 1.0 : d.rho0;
         r.ks = fp64_kernels(r.p, r.Q);
         r.kl = ctx->lo ? *fp32_kernels(r.p, r.Q) : *r.ks;
         {
@@ -835,19 +848,30 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
     ctx->multi = n_mesh > 1;
     if (!ctx->multi) {
         const MeshRec &r = ctx->units()[0];
-        std::vector<int32_t> nsh((size_t)ctx->N_tot, -1), shn((size_t)r.pd.n_shared);
+        // a shared node's entry range in the gather lists, packed into one
+        // word so that the step kernel reads it in one load
+        std::vector<long long> nsh((size_t)ctx->N_tot, -1);
+        std::vector<int32_t> shn((size_t)r.pd.n_shared), shp((size_t)r.pd.n_shared + 1);
         if (r.pd.n_shared &&
-            hipMemcpy(shn.data(), r.pd.sh_node, shn.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+            (hipMemcpy(shn.data(), r.pd.sh_node, shn.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+             hipMemcpy(shp.data(), r.pd.sh_ptr, shp.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)) {
             ctx->err = "cannot read the shared-node list";
             return bail(FE_EDEVICE);
         }
-        for (size_t k = 0; k < shn.size(); ++k) nsh[(size_t)shn[k]] = (int32_t)k;
+        for (size_t k = 0; k < shn.size(); ++k) {
+            const long long cnt = shp[k + 1] - shp[k];
+            if (cnt >= 0x10000) {
+                ctx->err = "a node is shared by 65536 or more patches";
+                return bail(FE_EUNSUPPORTED);
+            }
+            nsh[(size_t)shn[k]] = ((long long)shp[k] << 16) | cnt;
+        }
         void *dp = nullptr;
-        if (upload(nsh.data(), nsh.size() * 4, &dp)) {
+        if (upload(nsh.data(), nsh.size() * sizeof(long long), &dp)) {
             ctx->err = "CG workspace allocation failed";
             return bail(FE_ENOMEM);
         }
-        ctx->node_sh = (int32_t *)dp;
+        ctx->node_sh = (long long *)dp;
     }
     if (ctx->multi) {
         std::vector<CgChunk> ch;
@@ -910,7 +934,17 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
                     ctx->mq + r.mq_off, nullptr, ctx->tabs + r.tab_slot, prm, ctx->min_key,
                     ctx->nonfinite, true, ctx->st);
     }
+    launch_reset_diag(nullptr, ctx->bad, ctx->st);
+    for (int m = 0; m < n_mesh; ++m) {
+        if (!meshes[m].rho0_q) continue;
+        const MeshRec &r = ctx->mesh[m];
+        const int perm_base = ctx->batched ? (int)(r.l2_off / ((long long)r.p * r.p * r.p)) : 0;
+        launch_point_density(ctx->mq + r.mq_off, meshes[m].rho0_q, r.pd.perm, perm_base,
+                             r.Q * r.Q * r.Q, r.E, ctx->bad, ctx->st);
+    }
+    int bad_rho = 0;
     if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(&bad_rho, ctx->bad, sizeof(int), hipMemcpyDeviceToHost, ctx->st) != hipSuccess ||
         hipMemcpyAsync(ctx->h_key, ctx->min_key, sizeof(long long), hipMemcpyDeviceToHost, ctx->st) != hipSuccess ||
         hipMemcpyAsync(ctx->h_flag, ctx->nonfinite, sizeof(int), hipMemcpyDeviceToHost, ctx->st) != hipSuccess ||
         hipStreamSynchronize(ctx->st) != hipSuccess) {
@@ -940,6 +974,10 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
             ctx->err = "set-up kernels failed";
             return bail(FE_EDEVICE);
         }
+    }
+    if (bad_rho) {
+        ctx->err = "rho0_q holds a value that is not a positive finite number";
+        return bail(FE_EINVAL);
     }
     const double min0 = key_to_double(*ctx->h_key);
     if (!(min0 > 0.0) || *ctx->h_flag) {
@@ -1299,8 +1337,8 @@ static int cg_run(fe_ctx *ctx, const double *b, double *x, double rel_tol, int m
         } else {
             const MeshRec &r = ctx->units()[0];
             cg_step_shared(x, ctx->r, ctx->p, ctx->Ap, ctx->fr, ctx->N_tot, ctx->part,
-                           (int)ctx->n_parts, ctx->cg, ctx->part2, ctx->node_sh, r.pd.sh_ptr,
-                           r.pd.sh_idx, r.pd.part, s);
+                           (int)ctx->n_parts, ctx->cg, ctx->part2, ctx->node_sh, r.pd.sh_idx,
+                           r.pd.part, s);
         }
     };
     const bool graph = (ctx->opts.flags & FE_OPT_GRAPH) != 0;

@@ -137,7 +137,7 @@ __global__ void k_cg_alpha(const double *__restrict__ part_pap, int n_pap, CgSta
 __global__ void k_cg_step_sh(double *__restrict__ x, double *__restrict__ r, double *__restrict__ p,
                              const double *__restrict__ Ap, const unsigned char *__restrict__ fr,
                              long long nn, CgState *__restrict__ st, double *__restrict__ part,
-                             const int32_t *__restrict__ node_sh, const int32_t *__restrict__ sh_ptr,
+                             const long long *__restrict__ node_sh,
                              const int32_t *__restrict__ sh_idx, const double *__restrict__ shpart)
 {
     __shared__ double sred[16];
@@ -150,14 +150,15 @@ __global__ void k_cg_step_sh(double *__restrict__ x, double *__restrict__ r, dou
     double rr = 0.0;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < nn; g += stride) {
-        const int sh = node_sh[g];
+        const long long code = node_sh[g];
         double ap[3];
-        if (sh < 0) {
+        if (code < 0) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) ap[c] = Ap[c * nn + g];
         } else {
             ap[0] = ap[1] = ap[2] = 0.0;
-            for (int j = sh_ptr[sh]; j < sh_ptr[sh + 1]; ++j) {
+            const long long j0 = code >> 16, j1 = j0 + (code & 0xffff);
+            for (long long j = j0; j < j1; ++j) {
                 const double *src = shpart + 3 * (long long)sh_idx[j];
                 ap[0] += src[0];
                 ap[1] += src[1];
@@ -494,13 +495,13 @@ int cg_step_blocks(long long nn)
 
 void cg_step_shared(double *x, double *r, double *p, const double *Ap, const unsigned char *fr,
                     long long nn, const double *part_pap, int n_pap, CgState *state, double *part,
-                    const int32_t *node_sh, const int32_t *sh_ptr, const int32_t *sh_idx,
-                    const double *shpart, hipStream_t st)
+                    const long long *node_sh, const int32_t *sh_idx, const double *shpart,
+                    hipStream_t st)
 {
     const int nb = cg_step_blocks(nn);
     hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, st, part_pap, n_pap, state);
     hipLaunchKernelGGL(k_cg_step_sh, dim3(nb), dim3(256), 0, st, x, r, p, Ap, fr, nn, state, part,
-                       node_sh, sh_ptr, sh_idx, shpart);
+                       node_sh, sh_idx, shpart);
     hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1024), 0, st, part, nb, state);
 }
 

@@ -65,13 +65,13 @@ void cg_start(double *x, const double *b, const double *Ax, double *r, double *p
 // p = p', r -= alpha Ap on free DOFs, x += alpha p every second step
 // (cg_finish adds a pending last one); then one workgroup finishes r.r (part
 // holds cg_step_blocks(nn) partials) and sets beta, the iteration count and
-// done. Ap of a shared node is the sum of its patch partials
-// (node_sh[g]: its row in the shared-node lists sh_ptr/sh_idx over shpart, or
-// -1); nn = nodes.
+// done. Ap of a shared node is the sum of its patch partials: node_sh[g] is
+// (first << 16) | count of its entries sh_idx[first .. first + count) into
+// shpart, or -1 for a node of one patch; nn = nodes.
 void cg_step_shared(double *x, double *r, double *p, const double *Ap, const unsigned char *fr,
                     long long nn, const double *part_pap, int n_pap, CgState *state, double *part,
-                    const int32_t *node_sh, const int32_t *sh_ptr, const int32_t *sh_idx,
-                    const double *shpart, hipStream_t st);
+                    const long long *node_sh, const int32_t *sh_idx, const double *shpart,
+                    hipStream_t st);
 // After the iterations of a one-mesh solve: x += alpha_p p if the last
 // iteration's direction is still pending.
 void cg_finish(double *x, const double *p, long long n, const CgState *state, hipStream_t st);

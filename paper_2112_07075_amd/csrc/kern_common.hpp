@@ -90,9 +90,12 @@ __device__ __forceinline__ long long wave_min_key(long long k)
 }
 
 // ---------------------------------------------------------------- patches
-// Distinct-node slots per patch (UMAX) and the elements a workgroup handles
-// per pass (NE) are chosen so that the static LDS of a workgroup stays below
-// 60 KiB: at most two workgroups' worth of LDS fit a 160 KiB CU at once.
+// Distinct-node slots per patch (UMAX): 768 at p = 1, 2 (a 4x4x4 block of Q2
+// elements has 729 nodes), 512 at p = 3 (a 2x2x2 block of Q3 elements: 343)
+// and 768 at p = 4 (a 2x2x2 block of Q4 elements: 729). Larger p = 3 tables
+// (640 nodes for 2x2x4 blocks, 1024 for about 27 elements) were measured
+// slower in FP64 at Q = 5: the fused pair's two node tables then leave room
+// for one workgroup per CU instead of two.
 __host__ __device__ constexpr int patch_umax(int D) { return D == 4 ? 512 : 768; }
 
 

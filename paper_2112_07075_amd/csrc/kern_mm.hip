@@ -47,6 +47,30 @@ __global__ void k_sum_blocks(const double *__restrict__ in, int K, long long str
     }
 }
 
+// Initial density given point by point (Sec. 3.3's rho |J| = rho0 |J0| with
+// rho0 varying over the mesh): m_q = rho0(q) detJ0 w from m_q = detJ0 w.
+__global__ void k_point_density(double *__restrict__ mq, const double *__restrict__ rho0q,
+                                const int32_t *__restrict__ perm, int perm_base, int Q3, long long n,
+                                int *__restrict__ bad)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const long long el = i / Q3;
+    const int q = (int)(i % Q3);
+    const double r = rho0q[(long long)(perm[el] - perm_base) * Q3 + q];
+    if (!(r > 0.0 && r < INFINITY)) *bad = 1;
+    mq[i] *= r;
+}
+
+void launch_point_density(double *mq, const double *rho0q, const int32_t *perm, int perm_base,
+                          int Q3, long long E, int *bad, hipStream_t st)
+{
+    const long long n = E * Q3;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_point_density, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, mq, rho0q,
+                       perm, perm_base, Q3, n, bad);
+}
+
 void launch_mat_mass(int p, int Q, const double *dw, const double *eta0, const int32_t *perm,
                      double rho0, double *mqk, long long E, const double *tab, hipStream_t st)
 {
