@@ -248,7 +248,8 @@ def extra_rows(torch, fe, W, mesh, Q, fields):
     """The operators beyond the force pair, timed on the same single-mesh
     workload: the stiffness (diffusion) action of the hyper-viscosity term, the
     fully matrix-free force pair (against stored-S qdata + pair), two materials
-    (their qdata and every material's F_k^T v) and the full Lagrange step."""
+    (their qdata and every material's F_k^T v), the full Lagrange step, and the
+    pair, F 1 and M x in both scatter modes."""
     dev = torch.device("cuda:0")
     p, E, N = mesh.p, mesh.n_elem, mesh.n_nodes
     Q3, D3, Dl3 = Q ** 3, (p + 1) ** 3, p ** 3
@@ -320,6 +321,19 @@ def extra_rows(torch, fe, W, mesh, Q, fields):
     rows["lagrange_step"] = {"ms": round(ms_step, 3), "dt": info["dt"], "cg_iters": list(info["cg_iters"]),
                              "gdof_s": round(3 * N / (ms_step * 1e-3) / 1e9, 3)}
     del ctx
+    # the two scatter modes of R^T: ordered patch partials (default) and
+    # device-scope atomics (FE_OPT_ATOMIC), same tile shapes
+    modes = {}
+    for name, fl in (("partials", 0), ("atomic", fe.FE_OPT_ATOMIC)):
+        ctx = fe.fe_pa_setup(desc, fe.Opts(flags=fl))
+        fe.fe_qdata_update(ctx, x, v, e)
+        ms_p = time_calls(torch, lambda: fe.fe_force_mult_pair(ctx, None, y, v, z))
+        ms_f = time_calls(torch, lambda: fe.fe_force_mult(ctx, None, y))
+        ms_m = time_calls(torch, lambda: fe.fe_mass_mult(ctx, v, y))
+        modes[name] = {"pair_us": round(ms_p * 1e3, 2), "force_1_us": round(ms_f * 1e3, 2),
+                       "mass_us": round(ms_m * 1e3, 2)}
+        del ctx
+    rows["scatter_modes"] = modes
     return rows
 
 

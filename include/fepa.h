@@ -100,6 +100,17 @@ extern "C" {
                                 (fe_stiffness_update / fe_stiffness_mult):
                                 its quadrature data, 6 Q^3 FP64 values per
                                 element, allocated at setup                */
+#define FE_OPT_ATOMIC   0x20 /* scatter mode of R^T (the sum over elements,
+                                Sec. 3.1's assembly of the element results):
+                                a node shared by several patches receives
+                                its patches' sums by device-scope FP64
+                                atomic adds (after the node is zeroed)
+                                instead of per-patch partials summed in a
+                                fixed order by a second kernel. The order of
+                                those adds is not fixed, so results may
+                                differ in the last bits from run to run;
+                                without this flag every output is
+                                reproducible bit for bit                   */
 
 /* kernels timed under FE_OPT_TIMERS */
 #define FE_TIMER_QDATA   0
@@ -156,9 +167,8 @@ typedef struct fe_materials {
  * NULL, by the environment variable FEPA_TUNE_TABLE; text lines "order q1d
  * precision nw_force nw_force_t nw_mass patch [nw_pair]", as written by the
  * package's autotuner), the library's built-in table (measured by the same
- * autotuner on MI355X), else the default rule. The element restriction's
- * scatter is always the deterministic patch scatter (device-scope atomics
- * were measured slower on MI355X and are not offered). */
+ * autotuner on MI355X), else the default rule. The scatter mode is a flag
+ * (FE_OPT_ATOMIC; the default is the deterministic patch scatter). */
 typedef struct fe_opts {
     int32_t precision;         /* FE_PREC_*                                 */
     int32_t flags;             /* FE_OPT_* bit set                          */

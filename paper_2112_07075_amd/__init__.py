@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(HERE, "libfepa.so")
 FE_OK, FE_EINVAL, FE_ENOMEM, FE_EDEVICE, FE_EUNSUPPORTED, FE_EBADMESH, FE_ENOTCONV = \
     0, -1, -2, -3, -4, -5, -6
 FE_PREC_FP64, FE_PREC_FP32, FE_PREC_BF16 = 0, 1, 2
-FE_OPT_TIMERS, FE_OPT_BATCHED, FE_OPT_GRAPH, FE_OPT_STEP, FE_OPT_STIFF = 0x1, 0x2, 0x4, 0x8, 0x10
+FE_OPT_TIMERS, FE_OPT_BATCHED, FE_OPT_GRAPH, FE_OPT_STEP, FE_OPT_STIFF, FE_OPT_ATOMIC = \
+    0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 FE_TIMER_QDATA, FE_TIMER_FORCE, FE_TIMER_FORCE_T, FE_TIMER_MASS, FE_TIMER_PAIR, FE_TIMER_MF = \
     0, 1, 2, 3, 4, 5
 

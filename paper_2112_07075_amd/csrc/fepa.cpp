@@ -101,6 +101,7 @@ struct fe_ctx {
     // batched form: one launch unit per (order, Q) class, covering all of the
     // class's meshes; otherwise every mesh is its own unit
     bool batched = false;
+    bool atomic = false;  // FE_OPT_ATOMIC: shared nodes summed by device atomics
     std::vector<MeshRec> unit;
     const std::vector<MeshRec> &units() const { return batched ? unit : mesh; }
     fe_opts_t opts{};
@@ -449,7 +450,7 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         return fail(nullptr, FE_EINVAL, "gamma must be > 1 and q1, q2 >= 0%s");
     if (o.precision != FE_PREC_FP64 && o.precision != FE_PREC_FP32 && o.precision != FE_PREC_BF16)
         return fail(nullptr, FE_EUNSUPPORTED, "precision not provided by this build%s");
-    if (o.flags & ~(FE_OPT_TIMERS | FE_OPT_BATCHED | FE_OPT_GRAPH | FE_OPT_STEP | FE_OPT_STIFF))
+    if (o.flags & ~(FE_OPT_TIMERS | FE_OPT_BATCHED | FE_OPT_GRAPH | FE_OPT_STEP | FE_OPT_STIFF | FE_OPT_ATOMIC))
         return fail(nullptr, FE_EINVAL, "unknown option flags%s");
     if (o.materials) {
         const fe_materials_t &mt = *o.materials;
@@ -592,6 +593,7 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
     // storage of S and m_q: grouped by (order, Q) class in the batched form, so
     // that every class is one contiguous range; in caller order otherwise
     ctx->batched = (o.flags & FE_OPT_BATCHED) != 0;
+    ctx->atomic = (o.flags & FE_OPT_ATOMIC) != 0;
     std::vector<int> order(n_mesh);
     for (int m = 0; m < n_mesh; ++m) order[m] = m;
     if (ctx->batched)
@@ -774,7 +776,10 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
         if (!urc && (urc = upload(pl.sh_node.data(), pl.sh_node.size() * 4, &dp)) == FE_OK) r.pd.sh_node = (const int32_t *)dp;
         if (!urc && (urc = upload(pl.sh_ptr.data(), pl.sh_ptr.size() * 4, &dp)) == FE_OK) r.pd.sh_ptr = (const int32_t *)dp;
         if (!urc && (urc = upload(pl.sh_idx.data(), pl.sh_idx.size() * 4, &dp)) == FE_OK) r.pd.sh_idx = (const int32_t *)dp;
-        if (!urc && (urc = upload(nullptr, (size_t)pl.n_entries * 3 * sizeof(double), &dp)) == FE_OK) r.pd.part = (double *)dp;
+        // shared-node partials (none in the atomic scatter mode: pd.part stays null)
+        if (!urc && !ctx->atomic &&
+            (urc = upload(nullptr, (size_t)pl.n_entries * 3 * sizeof(double), &dp)) == FE_OK)
+            r.pd.part = (double *)dp;
         r.pd.n_entries = pl.n_entries;
         if (!urc && (urc = upload(pl.orphans.data(), pl.orphans.size() * 4, &dp)) == FE_OK) r.orphans = (const int32_t *)dp;
         static_assert(sizeof(PatchRec) == 6 * sizeof(int32_t), "patch table rows are 6 int32");
@@ -858,7 +863,8 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
             ctx->err = "cannot read the shared-node list";
             return bail(FE_EDEVICE);
         }
-        for (size_t k = 0; k < shn.size(); ++k) {
+        // atomic scatter mode: the mass kernel leaves Ap complete at every node
+        for (size_t k = 0; k < (ctx->atomic ? 0 : shn.size()); ++k) {
             const long long cnt = shp[k + 1] - shp[k];
             if (cnt >= 0x10000) {
                 ctx->err = "a node is shared by 65536 or more patches";
@@ -1064,6 +1070,7 @@ int fe_force_mult(fe_ctx_t *ctx, const double *e, double *y)
     ScopedTimer tm(ctx, FE_TIMER_FORCE);
     return run_graph(ctx, GraphKey{kActForce, e, y}, [&](hipStream_t s, bool branch) {
         enqueue_units(ctx, s, branch, [&](const MeshRec &r, hipStream_t su) {
+            launch_scatter_prepare(r.pd, y, ctx->N_tot, nullptr, su);
             r.kl.force(S_of(ctx, r), e ? e + r.l2_off : nullptr, r.pd, y, ctx->N_tot,
                        tab_of(ctx, r), r.nw_force, su);
             launch_gather_shared(r.pd, y, ctx->N_tot, nullptr, su);
@@ -1098,6 +1105,7 @@ int fe_force_mult_pair(fe_ctx_t *ctx, const double *e, double *y, const double *
     ScopedTimer tm(ctx, FE_TIMER_PAIR);
     return run_graph(ctx, GraphKey{kActPair, e, y, v, 0, z}, [&](hipStream_t s, bool branch) {
         enqueue_units(ctx, s, branch, [&](const MeshRec &r, hipStream_t su) {
+            launch_scatter_prepare(r.pd, y, ctx->N_tot, nullptr, su);
             if (r.pair_split) {  // the tile table measured the two kernels faster here
                 r.kl.force(S_of(ctx, r), e ? e + r.l2_off : nullptr, r.pd, y, ctx->N_tot,
                            tab_of(ctx, r), r.nw_force, su);
@@ -1128,7 +1136,7 @@ int fe_force_mult_pair_noalloc(fe_ctx_t *ctx, const double *e, double *y, const 
     // the units run one after another on the context stream, so each reuses
     // the scratch from its start
     for (const MeshRec &r : ctx->units()) {
-        const long long need = r.pd.n_entries * 3 * (long long)sizeof(double);
+        const long long need = ctx->atomic ? 0 : r.pd.n_entries * 3 * (long long)sizeof(double);
         if (need > kStaticScratchBytes) {
             char buf[160];
             std::snprintf(buf, sizeof(buf),
@@ -1141,7 +1149,8 @@ int fe_force_mult_pair_noalloc(fe_ctx_t *ctx, const double *e, double *y, const 
     hipStream_t su = ctx->st;
     for (const MeshRec &r : ctx->units()) {
         PatchDev pd = r.pd;
-        pd.part = scr;
+        if (!ctx->atomic) pd.part = scr;
+        launch_scatter_prepare(pd, y, ctx->N_tot, nullptr, su);
         if (r.pair_split) {
             r.kl.force(S_of(ctx, r), e ? e + r.l2_off : nullptr, pd, y, ctx->N_tot, tab_of(ctx, r),
                        r.nw_force, su);
@@ -1182,6 +1191,7 @@ int fe_stiffness_mult(fe_ctx_t *ctx, const double *u, double *y)
     if ((const void *)u == (const void *)y) return fail(ctx, FE_EINVAL, "input aliases output%s");
     return run_graph(ctx, GraphKey{kActStiff, u, y}, [&](hipStream_t s, bool branch) {
         enqueue_units(ctx, s, branch, [&](const MeshRec &r, hipStream_t su) {
+            launch_scatter_prepare(r.pd, y, ctx->N_tot, nullptr, su);
             r.sk.mult(ctx->Dk + r.Dk_off, u, r.pd, y, ctx->N_tot, ctx->tabs + r.tab_slot,
                       r.nw_stiff, su);
             launch_gather_shared(r.pd, y, ctx->N_tot, nullptr, su);
@@ -1249,6 +1259,7 @@ int fe_force_mult_pair_mf(fe_ctx_t *ctx, const double *x, const double *v, const
         enqueue_units(ctx, s, branch, [&](const MeshRec &r, hipStream_t su) {
             QParams prm{r.rho0, ctx->opts.gamma, ctx->opts.gamma - 1.0, ctx->opts.q1, ctx->opts.q2,
                         1.0 / r.p};
+            launch_scatter_prepare(r.pd, y, ctx->N_tot, nullptr, su);
             r.mf(x, v, e + r.l2_off, ctx->mq + r.mq_off, r.pd, y, z + r.l2_off, ctx->N_tot,
                  ctx->tabs + r.tab_slot, prm, ctx->min_key, ctx->nonfinite, r.nw_mf, su);
             launch_gather_shared(r.pd, y, ctx->N_tot, nullptr, su);
@@ -1282,6 +1293,7 @@ static void mass_enqueue(fe_ctx *ctx, const double *x, double *y, bool lo, const
                 cg.beta = &ctx->cg->beta;
             }
         }
+        launch_scatter_prepare(r.pd, y, ctx->N_tot, skip, su);
         if (lo)
             r.kl.mass(ctx->mq32 + r.mq_off, x, r.pd, y, ctx->N_tot, ctx->tabs32 + r.tab_slot, cg,
                       r.nw_mass, su);

@@ -179,7 +179,9 @@ __device__ __forceinline__ PatchRow load_patch(const int32_t *__restrict__ ptab,
     return PatchRow{r[0], r[1], r[2], r[3], r[4], r[5]};
 }
 
-// R^T of one patch: private nodes are stored, shared nodes leave a partial.
+// R^T of one patch: private nodes are stored, shared nodes leave a partial
+// (part != nullptr) or, in the atomic scatter mode (part == nullptr), are
+// added to y with device-scope atomics (y zeroed there beforehand).
 // Threads first, first + stride, ... of the caller share the work.
 template <int UMAX, typename R>
 __device__ __forceinline__ void patch_write(const R *acc, const PatchRow &pr,
@@ -198,11 +200,16 @@ __device__ __forceinline__ void patch_write(const R *acc, const PatchRow &pr,
             y[g] = a0;
             y[ncomp + g] = a1;
             y[2 * ncomp + g] = a2;
-        } else {
+        } else if (part) {
             double *dst = part + 3 * (long long)(pr.sho + u - pr.P);
             dst[0] = a0;
             dst[1] = a1;
             dst[2] = a2;
+        } else {
+            const long long g = pn[pr.pno + u];
+            atomicAdd(&y[g], a0);
+            atomicAdd(&y[ncomp + g], a1);
+            atomicAdd(&y[2 * ncomp + g], a2);
         }
     }
 }

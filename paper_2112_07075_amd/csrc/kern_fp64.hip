@@ -2025,10 +2025,18 @@ void launch_f64_to_f32(const double *in, float *out, long long n, hipStream_t st
     hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)blocks), dim3(256), 0, st, in, out, n);
 }
 
+void launch_scatter_prepare(const PatchDev &pd, double *y, long long ncomp, const int *skip,
+                            hipStream_t st)
+{
+    if (pd.part || pd.n_shared <= 0) return;  // partial mode: nothing to prepare
+    hipLaunchKernelGGL(k_zero_nodes, dim3((pd.n_shared + 255) / 256), dim3(256), 0, st, pd.sh_node,
+                       pd.n_shared, y, ncomp, skip);
+}
+
 void launch_gather_shared(const PatchDev &pd, double *y, long long ncomp, const int *skip,
                           hipStream_t st)
 {
-    if (pd.n_shared <= 0) return;
+    if (!pd.part || pd.n_shared <= 0) return;  // atomic mode: the sums are in y
     hipLaunchKernelGGL(k_gather_shared, dim3((pd.n_shared + 255) / 256), dim3(256), 0, st, pd.part,
                        pd.sh_node, pd.sh_ptr, pd.sh_idx, pd.n_shared, y, ncomp, skip);
 }

@@ -86,9 +86,14 @@ void launch_unpermute_s_bf16(const void *in, const int32_t *perm, long long rows
                              double *out, hipStream_t st);
 void launch_f64_to_f32(const double *in, float *out, long long n, hipStream_t st);
 
-// y[c][g] for the shared nodes of a patch plan (after force or mass patches).
+// y[c][g] for the shared nodes of a patch plan (after force or mass patches);
+// nothing in the atomic scatter mode (pd.part == nullptr).
 void launch_gather_shared(const PatchDev &pd, double *y, long long ncomp, const int *skip,
                           hipStream_t st);
+// Before a patch kernel writes y in the atomic scatter mode: y = 0 at the
+// plan's shared nodes (nothing in the partial mode).
+void launch_scatter_prepare(const PatchDev &pd, double *y, long long ncomp, const int *skip,
+                            hipStream_t st);
 // y[c][g] = 0 for the listed nodes
 void launch_zero_nodes(const int32_t *nodes, int n, double *y, long long ncomp, const int *skip,
                        hipStream_t st);
