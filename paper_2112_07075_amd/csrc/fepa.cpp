@@ -557,7 +557,10 @@ int fe_pa_setup(const fe_mesh_desc_t *meshes, int32_t n_mesh, const fe_opts_t *o
             r.nw_force = std::min(r.nw_force, kc.max_nw(0));
             r.nw_force_t = std::min(r.nw_force_t, kc.max_nw(1));
             r.nw_mass = std::min(r.nw_mass, kc.max_nw(2));
-            if (o.tune_nw_force || !r.nw_pair) r.nw_pair = r.nw_force;  // explicit shapes: one for both
+            // explicit shapes: one wave count for both and the fused kernel (the
+            // autotuner times the two single kernels on their own)
+            if (o.tune_nw_force) r.pair_split = false;
+            if (o.tune_nw_force || !r.nw_pair) r.nw_pair = r.nw_force;
             r.nw_pair = std::min(r.nw_pair, kc.max_nw(3));
         }
         r.mf = mf_kernel(r.p, r.Q);

@@ -23,6 +23,24 @@ __device__ __forceinline__ double block_sum(double v, double *sred)
     return s;  // valid in thread 0
 }
 
+// This thread's share of part[0 .. n) (threads stride blockDim.x), four
+// independent running sums so that four loads are in flight at once; the
+// order is fixed, so the result is the same at every call.
+__device__ __forceinline__ double thread_parts(const double *__restrict__ part, int n)
+{
+    const int st = blockDim.x;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int k = threadIdx.x;
+    for (; k + 3 * st < n; k += 4 * st) {
+        a0 += part[k];
+        a1 += part[k + st];
+        a2 += part[k + 2 * st];
+        a3 += part[k + 3 * st];
+    }
+    for (; k < n; k += st) a0 += part[k];
+    return (a0 + a1) + (a2 + a3);
+}
+
 __global__ void k_mask_build(unsigned char *__restrict__ fr, long long n)
 {
     const long long stride = (long long)gridDim.x * blockDim.x;
@@ -128,9 +146,7 @@ __global__ void k_cg_alpha(const double *__restrict__ part_pap, int n_pap, CgSta
 {
     __shared__ double sred[16];
     if (st->done) return;
-    double s = 0.0;
-    for (int k = threadIdx.x; k < n_pap; k += blockDim.x) s += part_pap[k];
-    s = block_sum(s, sred);
+    const double s = block_sum(thread_parts(part_pap, n_pap), sred);
     if (threadIdx.x == 0) st->alpha = st->rr / s;
 }
 
@@ -202,9 +218,7 @@ __global__ void k_cg_beta(const double *__restrict__ part, int nparts, CgState *
 {
     __shared__ double sred[16];
     if (st->done) return;
-    double s = 0.0;
-    for (int k = threadIdx.x; k < nparts; k += blockDim.x) s += part[k];
-    s = block_sum(s, sred);
+    const double s = block_sum(thread_parts(part, nparts), sred);
     if (threadIdx.x == 0) {
         st->iter += 1;
         st->beta = s / st->rr;

@@ -441,26 +441,51 @@ k_force_t(const RS *__restrict__ S, const double *__restrict__ v,
 
     __syncthreads();
 
+    // At Q = 4 a pass loads its element's 9 Q values of S at once. For Q >= 5
+    // (registers) S streams by component: sv holds component c while sn
+    // loads the next component (or component 0 of the next pass).
+    constexpr bool STREAM = !LANES;
+    constexpr int SQ = s_stride<RS>(Q);
+    R sv[STREAM ? 3 : 9][Q], sn[STREAM ? 3 : 1][Q];
+    if constexpr (STREAM) {
+        const bool act0 = valid && le < pr.cnt;
+        const RS *__restrict__ S0 = S + (long long)(pr.eb + (act0 ? le : 0)) * 9 * SQ + t;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int qz = 0; qz < Q; ++qz) sv[d][qz] = (R)__builtin_nontemporal_load(S0 + d * SQ + qz * QQ);
+    }
 #pragma unroll 1
     for (int base = 0; base < pr.cnt; base += NE) {
         const int idx = base + le;
         const bool act = valid && idx < pr.cnt;
         const long long el = pr.eb + (act ? idx : 0);
-        constexpr int SQ = s_stride<RS>(Q);
         const RS *__restrict__ Se = S + el * 9 * SQ + t;
-        R sv[9][Q];
+        const bool actn = valid && idx + NE < pr.cnt;
+        const RS *__restrict__ Sn = S + (long long)(pr.eb + (actn ? idx + NE : 0)) * 9 * SQ + t;
+        if constexpr (!STREAM) {
 #pragma unroll
-        for (int cd = 0; cd < 9; ++cd)
+            for (int cd = 0; cd < 9; ++cd)
 #pragma unroll
-            for (int qz = 0; qz < Q; ++qz)
-                sv[cd][qz] = (R)__builtin_nontemporal_load(Se + cd * SQ + qz * QQ);
+                for (int qz = 0; qz < Q; ++qz)
+                    sv[cd][qz] = (R)__builtin_nontemporal_load(Se + cd * SQ + qz * QQ);
+        }
         for (int i = t; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
         wave_sync();
         R s[Q];
 #pragma unroll
         for (int k = 0; k < Q; ++k) s[k] = 0.0;
-#pragma unroll
+        constexpr int kCUnroll = STREAM ? 1 : 3;
+#pragma unroll kCUnroll
         for (int c = 0; c < 3; ++c) {
+            if constexpr (STREAM) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+#pragma unroll
+                    for (int qz = 0; qz < Q; ++qz)
+                        sn[d][qz] = (R)__builtin_nontemporal_load((c < 2 ? Se + (c + 1) * 3 * SQ : Sn) +
+                                                                  d * SQ + qz * QQ);
+            }
             R vx[D], vy[D], vz[D];
             if constexpr (LANES) {
                 // x-stage: thread (qx, iy = qy) from the node values; y-stage
@@ -535,7 +560,14 @@ k_force_t(const RS *__restrict__ S, const double *__restrict__ v,
                     dy += bb * vy[iz];
                     dz += gg * vz[iz];
                 }
-                s[qz] += sv[c * 3 + 0][qz] * dx + sv[c * 3 + 1][qz] * dy + sv[c * 3 + 2][qz] * dz;
+                const int r0 = STREAM ? 0 : c * 3;
+                s[qz] += sv[r0][qz] * dx + sv[r0 + 1][qz] * dy + sv[r0 + 2][qz] * dz;
+            }
+            if constexpr (STREAM) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+#pragma unroll
+                    for (int qz = 0; qz < Q; ++qz) sv[d][qz] = sn[d][qz];
             }
         }
         // L2 test functions: B_l^T in z (registers), y and x (LDS, or across
@@ -1042,6 +1074,21 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
         for (int k = 0; k < Q; ++k) m[k] = mq[el * Q3 + k * QQ + t];
         for (int i = t; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
         wave_sync();
+        // p <= 3: the LDS slots of the nodes this thread reads in the x stage
+        // (node row iy = qy) and adds to in the x^T stage (node (qx, qy, iz)),
+        // read once for the three components; at p = 4 (25 slots) they are
+        // read per component, which keeps more waves per SIMD
+        constexpr bool HOIST = D <= 4;
+        const int qyc = qy < D ? qy : D - 1, qxc = qx < D ? qx : D - 1;
+        int sl[HOIST ? D : 1][D], so[HOIST ? D : 1];
+        if constexpr (HOIST) {
+#pragma unroll
+            for (int iz = 0; iz < D; ++iz) {
+#pragma unroll
+                for (int ix = 0; ix < D; ++ix) sl[iz][ix] = 3 * sSl[le][(iz * D + qyc) * D + ix];
+                so[iz] = 3 * sSl[le][(iz * D + qyc) * D + qxc];
+            }
+        }
 #pragma unroll 1
         for (int c = 0; c < 3; ++c) {
             // x-stage: thread (qx, iy = qy)
@@ -1050,7 +1097,8 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
                 for (int iz = 0; iz < D; ++iz) {
                     R a = 0;
 #pragma unroll
-                    for (int ix = 0; ix < D; ++ix) a += rBx[ix] * xs[3 * sSl[le][(iz * D + qy) * D + ix] + c];
+                    for (int ix = 0; ix < D; ++ix)
+                        a += rBx[ix] * xs[(HOIST ? sl[HOIST ? iz : 0][ix] : 3 * sSl[le][(iz * D + qy) * D + ix]) + c];
                     sX[le][iz][qy * Q + qx] = a;
                 }
             }
@@ -1094,7 +1142,7 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
             if (act && qx < D && qy < D) {
 #pragma unroll
                 for (int iz = 0; iz < D; ++iz) {
-                    const int s = 3 * sSl[le][(iz * D + qy) * D + qx] + c;
+                    const int s = (HOIST ? so[HOIST ? iz : 0] : 3 * sSl[le][(iz * D + qy) * D + qx]) + c;
                     R r = 0;
 #pragma unroll
                     for (int k = 0; k < Q; ++k) r += cBx[k] * sX[le][iz][qy * Q + k];
