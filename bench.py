@@ -58,12 +58,12 @@ HBM_PEAK_GBS = 8000.0
 # reported only while those are unchanged (profiles/c2_fp64_step.md,
 # profiles/c4_step.md).
 TRAFFIC = {
-    ("c2", "fp64"): {"action": "pair", "kernel": "k_force_pair<3,4,ONE,double,2>", "bytes": 615.0e6,
-                     "src": {"kern_fp64.hip": "81995b3436029ae1", "kern_common.hpp": "719ebdd81608eefe",
-                             "tune_table.inc": "57afa8d182eb45ab"}},
-    ("c4", "fp64"): {"action": "pair", "kernel": "k_force_pair<4,5,ONE,double,4>", "bytes": 3348.0e6,
-                     "src": {"kern_fp64.hip": "2817bcc2e6223854", "kern_common.hpp": "243f1c42df2ea2ef",
-                             "tune_table.inc": "57afa8d182eb45ab"}},
+    ("c2", "fp64"): {"action": "pair", "kernel": "k_force_pair<3,4,ONE,double,2>", "bytes": 614.9e6,
+                     "src": {"kern_fp64.hip": "eb37dd5291fe23a0", "kern_common.hpp": "0d61728c91a0271d",
+                             "tune_table.inc": "971665e72d09a781"}},
+    ("c4", "fp64"): {"action": "pair", "kernel": "k_force_pair<4,5,ONE,double,4>", "bytes": 3347.7e6,
+                     "src": {"kern_fp64.hip": "eb37dd5291fe23a0", "kern_common.hpp": "0d61728c91a0271d",
+                             "tune_table.inc": "971665e72d09a781"}},
 }
 
 
