@@ -138,7 +138,9 @@ typedef struct fe_mesh_desc {
     /* NULL, or the initial density at every quadrature point: device
      * [E][Q^3] (caller element order, q = qx + Q*(qy + Q*qz), all > 0),
      * read during fe_pa_setup only; then m_q = rho0_q detJ0 w and rho0 is
-     * not used. */
+     * not used. A value that is not a positive finite number fails the
+     * set-up with FE_EINVAL; with fe_opts_t.materials it is FE_EUNSUPPORTED
+     * (each material has its own rho0). */
     const double *rho0_q;
 } fe_mesh_desc_t;
 
@@ -178,7 +180,7 @@ typedef struct fe_opts {
     int32_t tune_nw_force_t;   /* waves per workgroup of F^T v              */
     int32_t tune_nw_mass;      /* waves per workgroup of M x                */
     int32_t tune_patch;        /* elements per patch, 1..4096 (0: default)  */
-    /* NULL, or the path of a tuning table (format below), read during
+    /* NULL, or the path of a tuning table (format above), read during
      * fe_pa_setup only, in place of FEPA_TUNE_TABLE; a file that cannot be
      * opened fails the set-up with FE_EINVAL. */
     const char *tune_table;
