@@ -61,6 +61,9 @@ def _setup(descs, n, opts=None):
     ("bad_precision", fe.FE_EUNSUPPORTED),
     ("bad_waves", fe.FE_EINVAL),
     ("bad_patch", fe.FE_EINVAL),
+    ("unknown_flag", fe.FE_EINVAL),
+    ("zero_rho0", fe.FE_EINVAL),
+    ("rho0_q_with_materials", fe.FE_EUNSUPPORTED),
 ])
 def test_setup_rejects_invalid_arguments_without_device(case, expect):
     d, keep = _desc()
@@ -84,6 +87,18 @@ def test_setup_rejects_invalid_arguments_without_device(case, expect):
         opts = fe._Opts(0, 0, 5.0 / 3.0, 0.5, 2.0, 3, 0, 0, 0)
     elif case == "bad_patch":
         opts = fe._Opts(0, 0, 5.0 / 3.0, 0.5, 2.0, 0, 0, 0, 5000)
+    elif case == "unknown_flag":
+        opts = fe._Opts(0, 0x40, 5.0 / 3.0, 0.5, 2.0, 0, 0, 0, 0)
+    elif case == "zero_rho0":
+        d.rho0 = 0.0  # and no per-point density
+    elif case == "rho0_q_with_materials":
+        # both checked on the host, before any device work: the pointers are
+        # never read
+        d.rho0_q = 0x1000
+        g, r = (C.c_double * 1)(1.4), (C.c_double * 1)(1.0)
+        keep = (keep, g, r)
+        mat = fe._Materials(1, C.cast(g, C.c_void_p), C.cast(r, C.c_void_p), 0x2000)
+        opts = fe._Opts(0, 0, 5.0 / 3.0, 0.5, 2.0, 0, 0, 0, 0, None, C.pointer(mat))
     rc, h = _setup([d], n, opts)
     assert rc == expect
     assert not h.value
