@@ -105,12 +105,13 @@ extern "C" {
                                 a node shared by several patches receives
                                 its patches' sums by device-scope FP64
                                 atomic adds (after the node is zeroed)
-                                instead of per-patch partials summed in a
-                                fixed order by a second kernel. The order of
-                                those adds is not fixed, so results may
-                                differ in the last bits from run to run;
-                                without this flag every output is
-                                reproducible bit for bit                   */
+                                instead of per-patch partials that a second
+                                kernel sums in a fixed order. Either way the
+                                elements of one patch are summed by LDS
+                                atomics whose order is not fixed, so results
+                                may differ in the last bits of the working
+                                precision from run to run; the atomic mode
+                                adds that freedom for the shared nodes     */
 
 /* kernels timed under FE_OPT_TIMERS */
 #define FE_TIMER_QDATA   0
@@ -170,7 +171,7 @@ typedef struct fe_materials {
  * precision nw_force nw_force_t nw_mass patch [nw_pair]", as written by the
  * package's autotuner), the library's built-in table (measured by the same
  * autotuner on MI355X), else the default rule. The scatter mode is a flag
- * (FE_OPT_ATOMIC; the default is the deterministic patch scatter). */
+ * (FE_OPT_ATOMIC; the default is the patch scatter with ordered partials). */
 typedef struct fe_opts {
     int32_t precision;         /* FE_PREC_*                                 */
     int32_t flags;             /* FE_OPT_* bit set                          */

@@ -130,3 +130,26 @@ def test_atomic_scatter_several_meshes(torch_cuda):
             assert rel_cw(bh[:, sl], O.mass_mult(M, c.p, c.Q, c.N, qd["mq"], xr[:, sl]),
                           O.mass_mult(M, c.p, c.Q, c.N, qd["mq"], xr[:, sl], absmode=True)) < TOL
             assert np.abs(xh[:, sl] - xr[:, sl]).max() < 1e-9 * np.abs(xr[:, sl]).max()
+
+
+@pytest.mark.parametrize("precision", [fe.FE_PREC_FP32, fe.FE_PREC_BF16])
+def test_atomic_scatter_precision_forms(torch_cuda, precision):
+    # the same form with the two scatter modes: they differ only in the order
+    # of additions (the in-patch LDS sums, in the form's FP32, have no fixed
+    # order in either mode), so by a few FP32 roundings of the summed terms
+    t = torch_cuda
+    c = make_case(4, 2, 4, seed=230, compress=0.2)
+    outs = []
+    for flags in (0, fe.FE_OPT_ATOMIC):
+        ctx = fe.fe_pa_setup(fe.MeshDesc(c.mesh.elem_nodes, dev(t, c.mesh.x0), 2, 4),
+                             fe.Opts(precision=precision, flags=flags, tune_patch=8))
+        x, v, e = (dev(t, a) for a in (c.x, c.v, c.e))
+        fe.fe_qdata_update(ctx, x, v, e)
+        y1, y2, ym = t.empty_like(x), t.empty_like(x), t.empty_like(x)
+        z = t.empty_like(e)
+        fe.fe_force_mult(ctx, None, y1)
+        fe.fe_force_mult_pair(ctx, None, y2, v, z)
+        fe.fe_mass_mult(ctx, v, ym)
+        outs.append([a.cpu().numpy() for a in (y1, y2, z, ym)])
+    for a, b in zip(*outs):
+        assert np.abs(a - b).max() <= 1e-5 * np.abs(a).max()
