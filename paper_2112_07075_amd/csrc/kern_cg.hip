@@ -7,6 +7,7 @@
 // lives on the device; every kernel leaves at once when the solve is done, so
 // the host can enqueue batches of iterations and poll rarely.
 #include "kern_cg.hpp"
+#include "kern_common.hpp"
 
 namespace fepa {
 
@@ -172,14 +173,8 @@ __global__ void k_cg_step_sh(double *__restrict__ x, double *__restrict__ r, dou
 #pragma unroll
             for (int c = 0; c < 3; ++c) ap[c] = Ap[c * nn + g];
         } else {
-            ap[0] = ap[1] = ap[2] = 0.0;
-            const long long j0 = code >> 16, j1 = j0 + (code & 0xffff);
-            for (long long j = j0; j < j1; ++j) {
-                const double *src = shpart + 3 * (long long)sh_idx[j];
-                ap[0] += src[0];
-                ap[1] += src[1];
-                ap[2] += src[2];
-            }
+            const long long j0 = code >> 16;
+            sum_partials(shpart, sh_idx, j0, j0 + (code & 0xffff), ap);
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {

@@ -179,6 +179,37 @@ __device__ __forceinline__ PatchRow load_patch(const int32_t *__restrict__ ptab,
     return PatchRow{r[0], r[1], r[2], r[3], r[4], r[5]};
 }
 
+// a[c] = sum of the partials part[3 * sh_idx[j] + c], j = j0 .. j1-1, added in
+// ascending j. Four entries at a time: their index loads, then their partial
+// loads, are all in flight together (a slot past j1 reads entry j0 again and
+// its terms are not added), instead of one dependent pair of loads per entry.
+__device__ __forceinline__ void sum_partials(const double *__restrict__ part,
+                                             const int32_t *__restrict__ sh_idx, long long j0,
+                                             long long j1, double a[3])
+{
+    a[0] = a[1] = a[2] = 0.0;
+    for (long long j = j0; j < j1; j += 4) {
+        int id[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) id[k] = sh_idx[j + k < j1 ? j + k : j0];
+        double v[4][3];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double *src = part + 3 * (long long)id[k];
+            v[k][0] = src[0];
+            v[k][1] = src[1];
+            v[k][2] = src[2];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (j + k < j1) {
+                a[0] += v[k][0];
+                a[1] += v[k][1];
+                a[2] += v[k][2];
+            }
+    }
+}
+
 // R^T of one patch: private nodes are stored, shared nodes leave a partial
 // (part != nullptr) or, in the atomic scatter mode (part == nullptr), are
 // added to y with device-scope atomics (y zeroed there beforehand).

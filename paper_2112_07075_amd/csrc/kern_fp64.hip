@@ -1322,17 +1322,12 @@ __global__ void k_gather_shared(const double *__restrict__ part, const int32_t *
     if (skip && *skip) return;
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n_shared) return;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int j = sh_ptr[s]; j < sh_ptr[s + 1]; ++j) {
-        const double *src = part + 3 * (long long)sh_idx[j];
-        a0 += src[0];
-        a1 += src[1];
-        a2 += src[2];
-    }
     const long long g = sh_node[s];
-    y[g] = a0;
-    y[ncomp + g] = a1;
-    y[2 * ncomp + g] = a2;
+    double a[3];
+    sum_partials(part, sh_idx, sh_ptr[s], sh_ptr[s + 1], a);
+    y[g] = a[0];
+    y[ncomp + g] = a[1];
+    y[2 * ncomp + g] = a[2];
 }
 
 // y[c][g] = 0 for nodes that no element references
