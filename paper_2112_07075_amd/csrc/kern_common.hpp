@@ -210,6 +210,52 @@ __device__ __forceinline__ void sum_partials(const double *__restrict__ part,
     }
 }
 
+// The patch's distinct-node values of the three components into LDS:
+// dst[3u + c] = x[c][pn[u]], or x + bt * x2 there when x2 is given. Each
+// thread takes up to K nodes a round: their node-number loads, then all their
+// value loads, are in flight together.
+template <int K, typename R>
+__device__ __forceinline__ void patch_gather(R *dst, const PatchRow &pr,
+                                             const int32_t *__restrict__ pn,
+                                             const double *__restrict__ x,
+                                             const double *__restrict__ x2, double bt,
+                                             long long ncomp)
+{
+    const int st = blockDim.x;
+    for (int u0 = threadIdx.x; u0 < pr.U; u0 += K * st) {
+        long long g[K];
+        bool h[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            h[k] = u0 + k * st < pr.U;
+            g[k] = h[k] ? pn[pr.pno + u0 + k * st] : 0;
+        }
+        double a[K][3];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a[k][c] = h[k] ? x[c * ncomp + g[k]] : 0.0;
+        if (x2) {
+            double b[K][3];
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) b[k][c] = h[k] ? x2[c * ncomp + g[k]] : 0.0;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) a[k][c] += bt * b[k][c];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (h[k]) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) dst[3 * (u0 + k * st) + c] = (R)a[k][c];
+            }
+        }
+    }
+}
+
 // R^T of one patch: private nodes are stored, shared nodes leave a partial
 // (part != nullptr) or, in the atomic scatter mode (part == nullptr), are
 // added to y with device-scope atomics (y zeroed there beforehand).

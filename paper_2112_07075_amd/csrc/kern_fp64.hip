@@ -215,6 +215,7 @@ __device__ __forceinline__ float dpp_r(float v)
 }
 constexpr int kQuadBcast0 = 0x00, kQuadBcast1 = 0x55, kQuadBcast2 = 0xAA, kQuadBcast3 = 0xFF;
 constexpr int kRowRor4 = 0x124, kRowRor8 = 0x128, kRowRor12 = 0x12C;
+constexpr int kGatherK = 2;  // patch nodes per thread and round of the node gathers
 
 template <int D, bool ONE, typename R, int NW, typename RS = R>
 __global__ void __launch_bounds__(NW * 64)
@@ -411,12 +412,7 @@ k_force_t(const RS *__restrict__ S, const double *__restrict__ v,
         valid = L.valid;
     }
     const PatchRow pr = load_patch(ptab, xcd_block(blockIdx.x, gridDim.x));
-    for (int u = tid; u < pr.U; u += blockDim.x) {
-        const long long g = pn[pr.pno + u];
-        vs[3 * u] = (R)v[g];
-        vs[3 * u + 1] = (R)v[ncomp + g];
-        vs[3 * u + 2] = (R)v[2 * ncomp + g];
-    }
+    patch_gather<kGatherK>(vs, pr, pn, v, nullptr, 0.0, ncomp);
     R rBx[D], rGx[D], rBy[D], rGy[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -674,12 +670,7 @@ k_force_pair(const RS *__restrict__ S, const double *__restrict__ e, const doubl
     }
     const PatchRow pr = load_patch(ptab, xcd_block(blockIdx.x, gridDim.x));
     for (int k = tid; k < 3 * pr.U; k += blockDim.x) acc[k] = 0.0;
-    for (int u = tid; u < pr.U; u += blockDim.x) {
-        const long long g = pn[pr.pno + u];
-        vs[3 * u] = (R)v[g];
-        vs[3 * u + 1] = (R)v[ncomp + g];
-        vs[3 * u + 2] = (R)v[2 * ncomp + g];
-    }
+    patch_gather<kGatherK>(vs, pr, pn, v, nullptr, 0.0, ncomp);
     // F e: y weights (column qy), x weights (column qx, or the rotated source column)
     R cBy[Q], cGy[Q], cBx[Q], cGx[Q];
 #pragma unroll
@@ -1036,6 +1027,11 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
     const Lane L = lane_map<Q, NE>();
     const int tid = threadIdx.x, le = L.le, t = L.t, qx = t % Q, qy = t / Q;
     const PatchRow pr = load_patch(ptab, pi);
+    const double bt = x2 ? *(const double *)((const char *)beta + soff) : 0.0;
+    // the three components together: one gather, one pass over the elements
+    // (m_q and the slots read once), one write-out
+    for (int k = tid; k < 3 * pr.U; k += blockDim.x) acc[k] = (R)0;
+    patch_gather<kGatherK>(xs, pr, pn, x, x2, bt, ncomp);
     R rBx[D], rBy[D], cBy[Q], cBx[Q];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -1048,19 +1044,6 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
         cBx[k] = qx < D ? tab[T::B + k * D + qx] : (R)0;
     }
     double dot = 0.0;
-    const double bt = x2 ? *(const double *)((const char *)beta + soff) : 0.0;
-
-    // the three components together: one gather, one pass over the elements
-    // (m_q and the slots read once), one write-out
-    for (int u = tid; u < pr.U; u += blockDim.x) {
-        const long long g = pn[pr.pno + u];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const long long gc = c * ncomp + g;
-            xs[3 * u + c] = (R)(x2 ? x[gc] + bt * x2[gc] : x[gc]);
-            acc[3 * u + c] = (R)0;
-        }
-    }
     // idle lanes (spare element row NE) read slots from the spare row: keep it valid
     for (int i = tid; i < D3; i += blockDim.x) sSl[NE][i] = 0;
     __syncthreads();
@@ -1199,6 +1182,11 @@ k_mass_q4(const R *__restrict__ mq, const double *__restrict__ x,
     const int le = (tid >> 6) * 4 + (lane >> 4);
     const int r = lane & 15, qy = r & 3, qx = r >> 2, t = qx + Q * qy;
     const PatchRow pr = load_patch(ptab, pi);
+    const double bt = x2 ? *(const double *)((const char *)beta + soff) : 0.0;
+    // the three components together: one gather of the patch's node values, one
+    // pass over the elements (m_q and the slots read once), one write-out
+    for (int k = tid; k < 3 * pr.U; k += blockDim.x) acc[k] = (R)0;
+    patch_gather<kGatherK>(xs, pr, pn, x, x2, bt, ncomp);
     // x: interpolation weights of column qx; y: weights of row qy (broadcast lane k
     // brings node row k); y^T: weights of node row qy over the quad's points;
     // x^T: weights over the rotated source columns
@@ -1216,19 +1204,6 @@ k_mass_q4(const R *__restrict__ mq, const double *__restrict__ x,
     }
     const int qyc = qy < D ? qy : D - 1;
     double dot = 0.0;
-    const double bt = x2 ? *(const double *)((const char *)beta + soff) : 0.0;
-
-    // the three components together: one gather of the patch's node values, one
-    // pass over the elements (m_q and the slots read once), one write-out
-    for (int u = tid; u < pr.U; u += blockDim.x) {
-        const long long g = pn[pr.pno + u];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const long long gc = c * ncomp + g;
-            xs[3 * u + c] = (R)(x2 ? x[gc] + bt * x2[gc] : x[gc]);
-            acc[3 * u + c] = (R)0;
-        }
-    }
     __syncthreads();
 #pragma unroll 1
     for (int base = 0; base < pr.cnt; base += NE) {
