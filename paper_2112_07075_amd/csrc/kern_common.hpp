@@ -210,6 +210,27 @@ __device__ __forceinline__ void sum_partials(const double *__restrict__ part,
     }
 }
 
+// The LDS node slots of one element into its row, lanes t = 0 .. NT-1 of the
+// element sharing the D3 entries; a lane's loads are all in flight together
+// (one wait, not one per entry).
+template <int D3, int NT>
+__device__ __forceinline__ void load_slots(int *row, const uint16_t *__restrict__ slot,
+                                           long long el, int t)
+{
+    constexpr int NS = (D3 + NT - 1) / NT;
+    int v[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const int i = t + k * NT;
+        v[k] = i < D3 ? (int)slot[el * D3 + i] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const int i = t + k * NT;
+        if (i < D3) row[i] = v[k];
+    }
+}
+
 // The patch's distinct-node values of the three components into LDS:
 // dst[3u + c] = x[c][pn[u]], or x + bt * x2 there when x2 is given. Each
 // thread takes up to K nodes a round: their node-number loads, then all their

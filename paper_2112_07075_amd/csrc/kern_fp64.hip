@@ -1055,7 +1055,12 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
         R m[Q];
 #pragma unroll
         for (int k = 0; k < Q; ++k) m[k] = mq[el * Q3 + k * QQ + t];
-        for (int i = t; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
+        // the slots' loads in flight together; the FP32 instances keep their
+        // waves per SIMD with one load at a time
+        if constexpr (sizeof(R) == 8)
+            load_slots<D3, QQ>(sSl[le], slot, el, t);
+        else
+            for (int i = t; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
         wave_sync();
         // p <= 3: the LDS slots of the nodes this thread reads in the x stage
         // (node row iy = qy) and adds to in the x^T stage (node (qx, qy, iz)),
@@ -1213,7 +1218,7 @@ k_mass_q4(const R *__restrict__ mq, const double *__restrict__ x,
         R m[Q];
 #pragma unroll
         for (int k = 0; k < Q; ++k) m[k] = mq[el * Q3 + k * QQ + t];
-        for (int i = r; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
+        load_slots<D3, QQ>(sSl[le], slot, el, r);
         wave_sync();
 #pragma unroll 1
         for (int c = 0; c < 3; ++c) {
