@@ -466,7 +466,10 @@ k_force_t(const RS *__restrict__ S, const double *__restrict__ v,
                 for (int qz = 0; qz < Q; ++qz)
                     sv[cd][qz] = (R)__builtin_nontemporal_load(Se + cd * SQ + qz * QQ);
         }
-        for (int i = t; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
+        if constexpr (sizeof(R) == 8)  // the loads in flight together (FP64 instances)
+            load_slots<D3, QQ>(sSl[le], slot, el, t);
+        else
+            for (int i = t; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
         wave_sync();
         R s[Q];
 #pragma unroll
@@ -730,7 +733,10 @@ k_force_pair(const RS *__restrict__ S, const double *__restrict__ e, const doubl
         const bool actn = valid && idx + NE < pr.cnt;
         const RS *__restrict__ Sc = S + el * 9 * SQ + t;
         const RS *__restrict__ Sn = S + (long long)(pr.eb + (actn ? idx + NE : 0)) * 9 * SQ + t;
-        for (int i = t; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
+        if constexpr (sizeof(R) == 8)  // the loads in flight together (FP64 instances)
+            load_slots<D3, QQ>(sSl[le], slot, el, t);
+        else
+            for (int i = t; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
         R eq[Q];
         if (ONE) {
 #pragma unroll
