@@ -58,11 +58,11 @@ HBM_PEAK_GBS = 8000.0
 # reported only while those are unchanged (profiles/c2_fp64_step.md,
 # profiles/c4_step.md).
 TRAFFIC = {
-    ("c2", "fp64"): {"action": "pair", "kernel": "k_force_pair<3,4,ONE,double,2>", "bytes": 614.9e6,
-                     "src": {"kern_fp64.hip": "eb37dd5291fe23a0", "kern_common.hpp": "0d61728c91a0271d",
+    ("c2", "fp64"): {"action": "pair", "kernel": "k_force_pair<3,4,ONE,double,2>", "bytes": 614.8e6,
+                     "src": {"kern_fp64.hip": "921d63d24b2a14fd", "kern_common.hpp": "a91bc88126a1a2ab",
                              "tune_table.inc": "971665e72d09a781"}},
-    ("c4", "fp64"): {"action": "pair", "kernel": "k_force_pair<4,5,ONE,double,4>", "bytes": 3347.7e6,
-                     "src": {"kern_fp64.hip": "eb37dd5291fe23a0", "kern_common.hpp": "0d61728c91a0271d",
+    ("c4", "fp64"): {"action": "pair", "kernel": "k_force_pair<4,5,ONE,double,4>", "bytes": 3337.9e6,
+                     "src": {"kern_fp64.hip": "921d63d24b2a14fd", "kern_common.hpp": "a91bc88126a1a2ab",
                              "tune_table.inc": "971665e72d09a781"}},
 }
 
