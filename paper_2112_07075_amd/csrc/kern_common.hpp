@@ -210,26 +210,31 @@ __device__ __forceinline__ void sum_partials(const double *__restrict__ part,
     }
 }
 
-// The LDS node slots of one element into its row, lanes t = 0 .. NT-1 of the
-// element sharing the D3 entries; a lane's loads are all in flight together
-// (one wait, not one per entry).
+// The LDS node slots of one element, fetched one element pass ahead: lanes
+// t = 0 .. NT-1 of the element share its D3 entries; fetch() issues the next
+// pass's loads into registers, store() writes this pass's into the LDS row,
+// so the loads' latency is covered by a pass of work.
 template <int D3, int NT>
-__device__ __forceinline__ void load_slots(int *row, const uint16_t *__restrict__ slot,
-                                           long long el, int t)
-{
-    constexpr int NS = (D3 + NT - 1) / NT;
+struct SlotPipe {
+    static constexpr int NS = (D3 + NT - 1) / NT;
     int v[NS];
+    __device__ __forceinline__ void fetch(const uint16_t *__restrict__ slot, long long el, int t)
+    {
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
-        const int i = t + k * NT;
-        v[k] = i < D3 ? (int)slot[el * D3 + i] : 0;
+        for (int k = 0; k < NS; ++k) {
+            const int i = t + k * NT;
+            v[k] = i < D3 ? (int)slot[el * D3 + i] : 0;
+        }
     }
+    __device__ __forceinline__ void store(int *row, int t) const
+    {
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
-        const int i = t + k * NT;
-        if (i < D3) row[i] = v[k];
+        for (int k = 0; k < NS; ++k) {
+            const int i = t + k * NT;
+            if (i < D3) row[i] = v[k];
+        }
     }
-}
+};
 
 // The patch's distinct-node values of the three components into LDS:
 // dst[3u + c] = x[c][pn[u]], or x + bt * x2 there when x2 is given. Each

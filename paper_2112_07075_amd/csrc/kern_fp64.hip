@@ -466,10 +466,13 @@ k_force_t(const RS *__restrict__ S, const double *__restrict__ v,
                 for (int qz = 0; qz < Q; ++qz)
                     sv[cd][qz] = (R)__builtin_nontemporal_load(Se + cd * SQ + qz * QQ);
         }
-        if constexpr (sizeof(R) == 8)  // the loads in flight together (FP64 instances)
-            load_slots<D3, QQ>(sSl[le], slot, el, t);
-        else
+        if constexpr (sizeof(R) == 8) {  // FP64 instances: the slot loads in flight together
+            SlotPipe<D3, QQ> sp;
+            sp.fetch(slot, el, t);
+            sp.store(sSl[le], t);
+        } else {
             for (int i = t; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
+        }
         wave_sync();
         R s[Q];
 #pragma unroll
@@ -725,6 +728,8 @@ k_force_pair(const RS *__restrict__ S, const double *__restrict__ e, const doubl
             for (int qz = 0; qz < Q; ++qz)
                 sv[d][qz] = (R)__builtin_nontemporal_load(S0 + d * SQ + qz * QQ);
     }
+    SlotPipe<D3, QQ> sp;
+    if constexpr (sizeof(R) == 8) sp.fetch(slot, pr.eb + (valid && le < pr.cnt ? le : 0), t);
 #pragma unroll 1
     for (int base = 0; base < pr.cnt; base += NE) {
         const int idx = base + le;
@@ -733,10 +738,12 @@ k_force_pair(const RS *__restrict__ S, const double *__restrict__ e, const doubl
         const bool actn = valid && idx + NE < pr.cnt;
         const RS *__restrict__ Sc = S + el * 9 * SQ + t;
         const RS *__restrict__ Sn = S + (long long)(pr.eb + (actn ? idx + NE : 0)) * 9 * SQ + t;
-        if constexpr (sizeof(R) == 8)  // the loads in flight together (FP64 instances)
-            load_slots<D3, QQ>(sSl[le], slot, el, t);
-        else
+        if constexpr (sizeof(R) == 8) {  // FP64 instances: slots fetched a pass ahead
+            sp.store(sSl[le], t);
+            sp.fetch(slot, pr.eb + (actn ? idx + NE : 0), t);
+        } else {
             for (int i = t; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
+        }
         R eq[Q];
         if (ONE) {
 #pragma unroll
@@ -1053,6 +1060,8 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
     // idle lanes (spare element row NE) read slots from the spare row: keep it valid
     for (int i = tid; i < D3; i += blockDim.x) sSl[NE][i] = 0;
     __syncthreads();
+    SlotPipe<D3, QQ> sp;
+    if constexpr (sizeof(R) == 8) sp.fetch(slot, pr.eb + (L.valid && le < pr.cnt ? le : 0), t);
 #pragma unroll 1
     for (int base = 0; base < pr.cnt; base += NE) {
         const int idx = base + le;
@@ -1061,12 +1070,14 @@ k_mass(const R *__restrict__ mq, const double *__restrict__ x,
         R m[Q];
 #pragma unroll
         for (int k = 0; k < Q; ++k) m[k] = mq[el * Q3 + k * QQ + t];
-        // the slots' loads in flight together; the FP32 instances keep their
-        // waves per SIMD with one load at a time
-        if constexpr (sizeof(R) == 8)
-            load_slots<D3, QQ>(sSl[le], slot, el, t);
-        else
+        // the slots fetched a pass ahead; the FP32 instances keep their waves
+        // per SIMD with one load at a time
+        if constexpr (sizeof(R) == 8) {
+            sp.store(sSl[le], t);
+            sp.fetch(slot, pr.eb + (L.valid && idx + NE < pr.cnt ? idx + NE : 0), t);
+        } else {
             for (int i = t; i < D3; i += QQ) sSl[le][i] = slot[el * D3 + i];
+        }
         wave_sync();
         // p <= 3: the LDS slots of the nodes this thread reads in the x stage
         // (node row iy = qy) and adds to in the x^T stage (node (qx, qy, iz)),
@@ -1216,6 +1227,8 @@ k_mass_q4(const R *__restrict__ mq, const double *__restrict__ x,
     const int qyc = qy < D ? qy : D - 1;
     double dot = 0.0;
     __syncthreads();
+    SlotPipe<D3, QQ> sp;  // FP64: the slots fetched a pass ahead
+    if constexpr (sizeof(R) == 8) sp.fetch(slot, pr.eb + (le < pr.cnt ? le : 0), r);
 #pragma unroll 1
     for (int base = 0; base < pr.cnt; base += NE) {
         const int idx = base + le;
@@ -1224,7 +1237,13 @@ k_mass_q4(const R *__restrict__ mq, const double *__restrict__ x,
         R m[Q];
 #pragma unroll
         for (int k = 0; k < Q; ++k) m[k] = mq[el * Q3 + k * QQ + t];
-        load_slots<D3, QQ>(sSl[le], slot, el, r);
+        if constexpr (sizeof(R) == 8) {
+            sp.store(sSl[le], r);
+            sp.fetch(slot, pr.eb + (idx + NE < pr.cnt ? idx + NE : 0), r);
+        } else {  // FP32: fetched here (a pass ahead costs a wave per SIMD at p = 3)
+            sp.fetch(slot, el, r);
+            sp.store(sSl[le], r);
+        }
         wave_sync();
 #pragma unroll 1
         for (int c = 0; c < 3; ++c) {
