@@ -59,10 +59,10 @@ HBM_PEAK_GBS = 8000.0
 # profiles/c4_step.md).
 TRAFFIC = {
     ("c2", "fp64"): {"action": "pair", "kernel": "k_force_pair<3,4,ONE,double,2>", "bytes": 614.8e6,
-                     "src": {"kern_fp64.hip": "921d63d24b2a14fd", "kern_common.hpp": "a91bc88126a1a2ab",
+                     "src": {"kern_fp64.hip": "0eef1e45315ca80c", "kern_common.hpp": "81135cc579cad6ef",
                              "tune_table.inc": "971665e72d09a781"}},
-    ("c4", "fp64"): {"action": "pair", "kernel": "k_force_pair<4,5,ONE,double,4>", "bytes": 3337.9e6,
-                     "src": {"kern_fp64.hip": "921d63d24b2a14fd", "kern_common.hpp": "a91bc88126a1a2ab",
+    ("c4", "fp64"): {"action": "pair", "kernel": "k_force_pair<4,5,ONE,double,4>", "bytes": 3337.6e6,
+                     "src": {"kern_fp64.hip": "0eef1e45315ca80c", "kern_common.hpp": "81135cc579cad6ef",
                              "tune_table.inc": "971665e72d09a781"}},
 }
 
