@@ -165,6 +165,9 @@ struct fe_ctx {
     long long qdata_bytes = 0, work_bytes = 0;
     int last_iters = 0;
     double last_res = 0.0;
+    // iterations of the last CG solve with the FP64 [0] and the FP32 [1]
+    // operator: where the next solve's first poll of the device state goes
+    int cg_hint[2] = {0, 0};
     std::string err;
     TimerPool timers[FE_TIMER_COUNT];
     // FE_OPT_GRAPH: captured action graphs, the private capture stream and the
@@ -1357,7 +1360,16 @@ static int cg_run(fe_ctx *ctx, const double *b, double *x, double rel_tol, int m
         }
     };
     const bool graph = (ctx->opts.flags & FE_OPT_GRAPH) != 0;
-    int batch = graph ? kGraphCgIters : 4;
+    const int gi = graph ? kGraphCgIters : 4;  // iterations per graph replay / per poll at first
+    int batch = gi;
+    // A context solves with one mass matrix per mesh, so consecutive solves
+    // take about as many iterations: the first poll of the device state goes
+    // out at the last multiple of gi not past the previous solve's count, the
+    // later ones after gi, 2 gi, 4 gi, ... (at most 32) more. Iterations past
+    // convergence are launched but return at once.
+    int &hint = ctx->cg_hint[lo ? 1 : 0];
+    bool hinted = std::min(hint, max_iter) / gi * gi > batch;
+    if (hinted) batch = std::min(hint, max_iter) / gi * gi;
     for (;;) {
         if (graph) {
             // kGraphCgIters iterations per replay; finished iterations are no-ops
@@ -1390,7 +1402,12 @@ static int cg_run(fe_ctx *ctx, const double *b, double *x, double rel_tol, int m
         HIP_OK(hipStreamSynchronize(ctx->st));
         if (*ctx->h_flag) return fail(ctx, FE_EINVAL, "essential DOF index out of range%s");
         if (ctx->multi ? ctx->h_glob->done : ctx->h_cg->done) break;
-        if (batch < 32) batch *= 2;
+        if (hinted) {
+            batch = gi;
+            hinted = false;
+        } else if (batch < 32) {
+            batch *= 2;
+        }
     }
     // the last direction, where the step left it pending
     if (ctx->multi)
@@ -1406,6 +1423,8 @@ static int cg_run(fe_ctx *ctx, const double *b, double *x, double rel_tol, int m
     } else {
         out.assign(1, *ctx->h_cg);
     }
+    hint = 0;
+    for (const CgState &c : out) hint = std::max(hint, c.iter);
     return FE_OK;
 }
 
